@@ -1,0 +1,305 @@
+// The Schroedinger-Poisson split step of the oracle, taken step by step from
+// the paper: the kick-drift-kick sequence of Eq. (SPE_solver_KDK) and
+// Algorithm 1 (Sec. 3.1), the periodic FFT Poisson solver (Sec. 3.2.1), the
+// second-order central-difference gradient (Sec. 3.1), the dynamic two-way
+// particle coupling (Sec. 3.2.2, here through the mesh with cloud-in-cell
+// weights) and the CFL time step (Sec. 3.5).  Plain FP64, no fusion.
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace orc {
+
+struct Grid {
+    int64_t nx, ny, nz;
+    double lx, ly, lz, dx, dy, dz, dv;
+    explicit Grid(const orc_config* c)
+        : nx(c->nx), ny(c->ny), nz(c->nz), lx(c->lx), ly(c->ly), lz(c->lz) {
+        dx = lx / nx;
+        dy = ly / ny;
+        dz = lz / nz;
+        dv = dx * dy * dz;
+    }
+    int64_t n() const { return nx * ny * nz; }
+    int64_t at(int64_t i, int64_t j, int64_t k) const {
+        return (wrap_index(i, nx) * ny + wrap_index(j, ny)) * nz + wrap_index(k, nz);
+    }
+    // |k|^2 of the mode stored at (i, j, k)
+    double k2(int64_t i, int64_t j, int64_t k) const {
+        const double kx = kTwoPi * double(signed_mode(i, nx)) / lx;
+        const double ky = kTwoPi * double(signed_mode(j, ny)) / ly;
+        const double kz = kTwoPi * double(signed_mode(k, nz)) / lz;
+        return kx * kx + ky * ky + kz * kz;
+    }
+};
+
+// (c) Phi = F^-1{ -(4 pi G) / k^2 F{rho} }, mean removed by zeroing k = 0.
+static void poisson(const orc_config* c, const double* rho, double* phi) {
+    Grid g(c);
+    std::vector<cplx> f(g.n());
+    for (int64_t i = 0; i < g.n(); ++i) f[i] = cplx(rho[i], 0.0);
+    fft3d(f.data(), int(g.nx), int(g.ny), int(g.nz), -1);
+    parallel_for(g.nx, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i)
+            for (int64_t j = 0; j < g.ny; ++j)
+                for (int64_t k = 0; k < g.nz; ++k) {
+                    const int64_t o = (i * g.ny + j) * g.nz + k;
+                    const double k2 = g.k2(i, j, k);
+                    f[o] = (i == 0 && j == 0 && k == 0) ? cplx(0.0, 0.0)
+                                                        : f[o] * (-c->four_pi_G / k2);
+                }
+    });
+    fft3d(f.data(), int(g.nx), int(g.ny), int(g.nz), +1);
+    for (int64_t i = 0; i < g.n(); ++i) phi[i] = f[i].real();
+}
+
+// Cloud-in-cell: s = x/dx, cell i = floor(s), f = s - i, weights (1-f, f) per
+// axis on nodes i and i+1 (periodic).
+struct Cic {
+    int64_t i[3];
+    double w[3][2];
+};
+
+static Cic cic_of(const Grid& g, const double* p) {
+    Cic r;
+    const double h[3] = {g.dx, g.dy, g.dz};
+    for (int a = 0; a < 3; ++a) {
+        const double s = p[a] / h[a];
+        const double fl = std::floor(s);
+        const double f = s - fl;
+        r.i[a] = int64_t(fl);
+        r.w[a][0] = 1.0 - f;
+        r.w[a][1] = f;
+    }
+    return r;
+}
+
+static void cic_deposit(const orc_config* c, const double* pos, double* rho_b) {
+    Grid g(c);
+    std::fill(rho_b, rho_b + g.n(), 0.0);
+    const double q = c->particle_mass / g.dv;
+    for (int64_t p = 0; p < c->n_particles; ++p) {  // sequential, fixed order
+        Cic w = cic_of(g, pos + 3 * p);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d)
+                    rho_b[g.at(w.i[0] + a, w.i[1] + b, w.i[2] + d)] +=
+                        q * (w.w[0][a] * w.w[1][b] * w.w[2][d]);
+    }
+}
+
+// g = -grad(Phi) at node (i,j,k) by central differences.
+static void node_accel(const Grid& g, const double* phi, int64_t i, int64_t j, int64_t k,
+                       double* out) {
+    out[0] = -(phi[g.at(i + 1, j, k)] - phi[g.at(i - 1, j, k)]) / (2.0 * g.dx);
+    out[1] = -(phi[g.at(i, j + 1, k)] - phi[g.at(i, j - 1, k)]) / (2.0 * g.dy);
+    out[2] = -(phi[g.at(i, j, k + 1)] - phi[g.at(i, j, k - 1)]) / (2.0 * g.dz);
+}
+
+static void cic_force(const orc_config* c, const double* phi, const double* pos, double* acc) {
+    Grid g(c);
+    parallel_for(c->n_particles, [&](int64_t b0, int64_t e0) {
+        for (int64_t p = b0; p < e0; ++p) {
+            Cic w = cic_of(g, pos + 3 * p);
+            double s[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int d = 0; d < 2; ++d) {
+                        double na[3];
+                        node_accel(g, phi, w.i[0] + a, w.i[1] + b, w.i[2] + d, na);
+                        const double wt = w.w[0][a] * w.w[1][b] * w.w[2][d];
+                        for (int t = 0; t < 3; ++t) s[t] += wt * na[t];
+                    }
+            for (int t = 0; t < 3; ++t) acc[3 * p + t] = s[t];
+        }
+    });
+}
+
+static void total_potential(const orc_config* c, const cplx* psi, const double* pos,
+                            double* phi) {
+    Grid g(c);
+    std::vector<double> rho(g.n(), 0.0);
+    if (c->n_particles > 0) cic_deposit(c, pos, rho.data());
+    for (int64_t i = 0; i < g.n(); ++i) rho[i] += std::norm(psi[i]);
+    poisson(c, rho.data(), phi);
+}
+
+// (a)/(d): psi <- exp(-i Phi tau / eta) psi.
+static void kick(const orc_config* c, cplx* psi, const double* phi, double tau) {
+    const int64_t n = cells(c);
+    const double s = tau / c->hbar_over_m;
+    parallel_for(n, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) psi[i] *= std::polar(1.0, -phi[i] * s);
+    });
+}
+
+// (b): psi <- F^-1{ exp(-i eta k^2 dt / 2) F{psi} }.
+static void drift(const orc_config* c, cplx* psi, double dt) {
+    Grid g(c);
+    fft3d(psi, int(g.nx), int(g.ny), int(g.nz), -1);
+    parallel_for(g.nx, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i)
+            for (int64_t j = 0; j < g.ny; ++j)
+                for (int64_t k = 0; k < g.nz; ++k)
+                    psi[(i * g.ny + j) * g.nz + k] *=
+                        std::polar(1.0, -0.5 * c->hbar_over_m * g.k2(i, j, k) * dt);
+    });
+    fft3d(psi, int(g.nx), int(g.ny), int(g.nz), +1);
+}
+
+static void particle_kick(const orc_config* c, const double* phi, const double* pos,
+                          double* vel, double tau, std::vector<double>& acc) {
+    acc.resize(size_t(3 * c->n_particles));
+    cic_force(c, phi, pos, acc.data());
+    for (int64_t i = 0; i < 3 * c->n_particles; ++i) vel[i] += acc[i] * tau;
+}
+
+static void particle_drift(const orc_config* c, double* pos, const double* vel, double dt) {
+    const double L[3] = {c->lx, c->ly, c->lz};
+    for (int64_t p = 0; p < c->n_particles; ++p)
+        for (int a = 0; a < 3; ++a) {
+            double x = pos[3 * p + a] + vel[3 * p + a] * dt;
+            x -= L[a] * std::floor(x / L[a]);
+            if (x >= L[a]) x = 0.0;
+            pos[3 * p + a] = x;
+        }
+}
+
+static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_t nsteps,
+                double dt) {
+    const int64_t n = cells(c);
+    const bool parts = c->n_particles > 0;
+    std::vector<double> phi(n), acc;
+    total_potential(c, psi, pos, phi.data());
+    for (int64_t s = 0; s < nsteps; ++s) {
+        // (a) first half kick with the current potential
+        kick(c, psi, phi.data(), 0.5 * dt);
+        if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt, acc);
+        // (b) full drift: kinetic phase in Fourier space; particles move
+        drift(c, psi, dt);
+        if (parts) particle_drift(c, pos, vel, dt);
+        // (c) potential of the wave density plus the deposited baryons
+        total_potential(c, psi, pos, phi.data());
+        // (d) second half kick with the new potential
+        kick(c, psi, phi.data(), 0.5 * dt);
+        if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt, acc);
+    }
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+extern "C" {
+
+void orc_poisson(const orc_config* c, const double* rho, double* phi) { poisson(c, rho, phi); }
+
+void orc_cic_deposit(const orc_config* c, const double* pos, double* rho_b) {
+    cic_deposit(c, pos, rho_b);
+}
+
+void orc_cic_force(const orc_config* c, const double* phi, const double* pos, double* acc) {
+    cic_force(c, phi, pos, acc);
+}
+
+void orc_potential(const orc_config* c, const double* psi, const double* pos, double* phi) {
+    total_potential(c, reinterpret_cast<const cplx*>(psi), pos, phi);
+}
+
+void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
+             double dt) {
+    kdk(c, reinterpret_cast<cplx*>(psi), pos, vel, nsteps, dt);
+}
+
+void orc_energy(const orc_config* c, const double* psi_in, const double* pos, const double* vel,
+                double* out) {
+    Grid g(c);
+    const cplx* psi = reinterpret_cast<const cplx*>(psi_in);
+    const int64_t n = g.n();
+    std::vector<double> phi(n), rho(n, 0.0);
+    if (c->n_particles > 0) cic_deposit(c, pos, rho.data());
+    double mass = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = std::norm(psi[i]);
+        mass += d;
+        rho[i] += d;
+    }
+    poisson(c, rho.data(), phi.data());
+    std::vector<cplx> f(psi, psi + n);
+    fft3d(f.data(), int(g.nx), int(g.ny), int(g.nz), -1);
+    double ek = 0.0;
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k)
+                ek += g.k2(i, j, k) * std::norm(f[(i * g.ny + j) * g.nz + k]);
+    const double eta = c->hbar_over_m;
+    ek *= 0.5 * eta * eta * g.dv / double(n);
+    double ep = 0.0, maxphi = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        ep += rho[i] * phi[i];
+        maxphi = std::max(maxphi, std::fabs(phi[i]));
+    }
+    ep *= 0.5 * g.dv;
+    double kp = 0.0, mom[3] = {0.0, 0.0, 0.0};
+    for (int64_t p = 0; p < c->n_particles; ++p)
+        for (int a = 0; a < 3; ++a) {
+            const double v = vel[3 * p + a];
+            kp += v * v;
+            mom[a] += v;
+        }
+    kp *= 0.5 * c->particle_mass;
+    out[0] = mass * g.dv;
+    out[1] = ek;
+    out[2] = ep;
+    out[3] = kp;
+    out[4] = ek + ep + kp;
+    for (int a = 0; a < 3; ++a) out[5 + a] = mom[a] * c->particle_mass;
+    out[8] = maxphi;
+    out[9] = 0.0;
+}
+
+void orc_paper_energies(const orc_config* c, const double* psi_in, const double* phi, double* out) {
+    Grid g(c);
+    const cplx* psi = reinterpret_cast<const cplx*>(psi_in);
+    const double h[3] = {g.dx, g.dy, g.dz};
+    double K = 0.0, Q = 0.0, V = 0.0;
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k) {
+                const int64_t o = g.at(i, j, k);
+                const double rho = std::norm(psi[o]);
+                int64_t nb[3][2] = {{g.at(i + 1, j, k), g.at(i - 1, j, k)},
+                                    {g.at(i, j + 1, k), g.at(i, j - 1, k)},
+                                    {g.at(i, j, k + 1), g.at(i, j, k - 1)}};
+                double j2 = 0.0, q2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const cplx dpsi = (psi[nb[a][0]] - psi[nb[a][1]]) / (2.0 * h[a]);
+                    const double ja = (std::conj(psi[o]) * dpsi).imag();
+                    j2 += ja * ja;
+                    const double ds = (std::sqrt(std::norm(psi[nb[a][0]])) -
+                                       std::sqrt(std::norm(psi[nb[a][1]]))) / (2.0 * h[a]);
+                    q2 += ds * ds;
+                }
+                if (rho > 1e-30) K += 0.5 * j2 / rho;
+                Q += q2;
+                V += rho * phi[o];
+            }
+    out[0] = K * g.dv;
+    out[1] = Q * g.dv;
+    out[2] = V * g.dv;
+    out[3] = 2.0 * out[0] + 2.0 * out[1] + out[2];
+}
+
+double orc_dt_auto(const orc_config* c, const double* phi, double zeta, double c_kin) {
+    Grid g(c);
+    double m = 0.0;
+    for (int64_t i = 0; i < g.n(); ++i) m = std::max(m, std::fabs(phi[i]));
+    const double h = std::min(g.dx, std::min(g.dy, g.dz));
+    const double eta = c->hbar_over_m;
+    double t = c_kin * h * h / eta;
+    if (m > 0.0) t = std::min(t, kTwoPi * eta / m);
+    return zeta * 0.5 * t;
+}
+
+}  // extern "C"

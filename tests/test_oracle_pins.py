@@ -1,0 +1,479 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks one piece of the oracle against the DFT definition, a library
+routine, a closed-form solution, an exact invariant of the method or a
+textbook special case, chosen so that a dropped term, a wrong sign, a wrong
+factor or a transposed axis anywhere in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage, stats
+
+from paper_2606_25026_amd import inputs
+
+TWO_PI = 2 * math.pi
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def grid_coords(shape, L):
+    if isinstance(L, (int, float)):
+        L = (L,) * 3
+    return [np.arange(n) * (l / n) for n, l in zip(shape, L)]
+
+
+# --------------------------------------------------------------------- FFT
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 6, 6), (12, 12, 12), (8, 6, 12), (4, 9, 2)])
+def test_fft_matches_brute_force_dft(orc, shape):
+    rng = np.random.default_rng(sum(shape))
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ref = orc.dft3d_brute(x, -1)
+    # the brute DFT is itself pinned to numpy's transform
+    assert rel_l2(ref, np.fft.fftn(x)) < 1e-13
+    assert rel_l2(orc.fft3d(x, -1), ref) < 1e-13
+    assert rel_l2(orc.fft3d(x, +1), np.fft.ifftn(x)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 3, 16, 27, 96, 256, 384, 512])
+def test_fft1d_lengths_roundtrip_parseval(orc, n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    X = orc.fft1d(x, -1)
+    assert rel_l2(X, np.fft.fft(x)) < 1e-13
+    assert rel_l2(orc.fft1d(X, +1), x) < 1e-13
+    assert abs(np.sum(np.abs(X) ** 2) / n - np.sum(np.abs(x) ** 2)) < 1e-12 * np.sum(np.abs(x) ** 2)
+
+
+def test_fft_rejects_unsupported_length(orc):
+    with pytest.raises(ValueError):
+        orc.fft1d(np.ones(10))
+
+
+# ----------------------------------------------------------------- Poisson
+@pytest.mark.parametrize("m,shape,L,G4", [((1, 0, 0), (16, 8, 12), 1.0, 1.0),
+                                          ((2, -3, 1), (16, 8, 12), (1.0, 2.0, 0.5), 2.5),
+                                          ((0, 4, 6), (8, 16, 12), 1.0, 1.0)])
+def test_poisson_single_mode_closed_form(orc, m, shape, L, G4):
+    Ls = (L,) * 3 if isinstance(L, float) else L
+    x, y, z = np.meshgrid(*grid_coords(shape, Ls), indexing="ij")
+    k = [TWO_PI * mi / li for mi, li in zip(m, Ls)]
+    arg = k[0] * x + k[1] * y + k[2] * z + 0.3
+    rho = 1.7 + 0.4 * np.cos(arg)
+    cfg = orc.make_config(shape, L=Ls, four_pi_G=G4)
+    phi = orc.poisson(cfg, rho)
+    k2 = sum(ki * ki for ki in k)
+    exact = -G4 * 0.4 * np.cos(arg) / k2
+    assert np.max(np.abs(phi - exact)) < 1e-13 * max(1.0, np.max(np.abs(exact))) * 10
+
+
+# -------------------------------------------------------------------- CIC
+def test_cic_mass_node_and_centre(orc):
+    shape, L = (8, 6, 4), (1.0, 0.75, 0.5)
+    dx = [l / n for l, n in zip(L, shape)]
+    dv = dx[0] * dx[1] * dx[2]
+    # particle exactly on node (3, 2, 1) and one at the centre of cell (5, 4, 3)
+    pos = np.array([[3 * dx[0], 2 * dx[1], 1 * dx[2]],
+                    [5.5 * dx[0], 4.5 * dx[1], 3.5 * dx[2]]])
+    cfg = orc.make_config(shape, L=L, n_particles=2, particle_mass=0.25)
+    rho = orc.cic_deposit(cfg, pos)
+    assert abs(rho.sum() * dv - 0.5) < 1e-15
+    assert abs(rho[3, 2, 1] - 0.25 / dv) < 1e-12
+    cube = rho[5:7, 4:6, 3:4]
+    assert rho[5, 4, 3] == pytest.approx(0.25 / 8 / dv, rel=1e-14)
+    # the centre particle wraps in z: nodes 3 and 0
+    assert rho[5, 4, 0] == pytest.approx(0.25 / 8 / dv, rel=1e-14)
+    assert cube.shape == (2, 2, 1)
+    assert np.count_nonzero(rho) == 9
+
+
+def test_cic_random_mass_and_linear_interpolation(orc):
+    rng = np.random.default_rng(5)
+    shape = (16, 8, 12)
+    pos = rng.uniform(0, 1, (500, 3)) * np.array([1.0, 1.0, 1.0])
+    cfg = orc.make_config(shape, L=1.0, n_particles=500, particle_mass=1e-3)
+    rho = orc.cic_deposit(cfg, pos)
+    assert abs(rho.sum() / np.prod(shape) - 0.5) < 1e-14
+    # interpolation of a field whose central-difference gradient is linear:
+    # Phi = a x^3 on interior nodes makes -dPhi/dx = -a (3 x^2 + dx^2)... use a
+    # quadratic Phi instead: the central difference of b x^2 is exactly 2 b x,
+    # and CIC reproduces linear functions exactly inside the box interior.
+    x, y, z = np.meshgrid(*grid_coords(shape, 1.0), indexing="ij")
+    phi = 0.7 * x ** 2 - 0.3 * y ** 2 + 0.2 * z ** 2
+    inner = rng.uniform(0.2, 0.75, (200, 3))
+    acc = orc.cic_force(orc.make_config(shape, L=1.0, n_particles=200), phi, inner)
+    expect = np.stack([-1.4 * inner[:, 0], 0.6 * inner[:, 1], -0.4 * inner[:, 2]], axis=1)
+    assert np.max(np.abs(acc - expect)) < 1e-12
+
+
+# --------------------------------------------------------------- PM force
+def test_pm_momentum_conservation_and_no_self_force(orc):
+    rng = np.random.default_rng(11)
+    shape = (16, 16, 16)
+    npart = 64
+    pos = rng.uniform(0, 1, (npart, 3))
+    cfg = orc.make_config(shape, n_particles=npart, particle_mass=1.0 / npart)
+    psi = np.ones(shape, complex)  # uniform wave: no wave force
+    phi = orc.potential(cfg, psi, pos)
+    acc = orc.cic_force(cfg, phi, pos)
+    total = acc.sum(axis=0) / npart
+    scale = np.abs(acc).sum() / npart
+    assert np.max(np.abs(total)) < 1e-13 * scale
+    one = orc.make_config(shape, n_particles=1, particle_mass=0.3)
+    p1 = np.array([[0.3141, 0.2718, 0.5772]])
+    a1 = orc.cic_force(one, orc.potential(one, psi, p1), p1)
+    assert np.max(np.abs(a1)) < 1e-12
+
+
+@pytest.mark.slow
+def test_pm_two_body_force_is_newtonian(orc):
+    # Two particles a distance r apart along x, dx << r << L.  In a periodic
+    # cube with the mean removed the pair force is G m / r^2 - (4 pi/3) G m r / L^3
+    # up to O(r^4) lattice terms (Ewald); the PM smoothing error (CIC deposit and
+    # interpolation, central difference) falls off as (dx/r)^2.
+    G4, m, r = 1.0, 1e-3, 0.09
+    G = G4 / (4 * math.pi)
+    expect = G * m / r ** 2 - (4 * math.pi / 3) * G * m * r
+    pos = np.array([[0.5 - r / 2, 0.5, 0.5], [0.5 + r / 2, 0.5, 0.5]])
+    dev = {}
+    for n in (128, 256):
+        cfg = orc.make_config((n, n, n), four_pi_G=G4, n_particles=2, particle_mass=m)
+        acc = orc.cic_force(cfg, orc.potential(cfg, np.zeros((n, n, n), complex), pos), pos)
+        assert acc[0, 0] > 0 and acc[1, 0] < 0          # attractive
+        assert acc[0, 0] == pytest.approx(-acc[1, 0], rel=1e-12)
+        assert abs(acc[0, 1]) < 1e-3 * expect and abs(acc[0, 2]) < 1e-3 * expect
+        dev[n] = acc[0, 0] / expect - 1
+    assert abs(dev[128]) < 0.03 and abs(dev[256]) < 0.01
+    assert 3.0 < dev[128] / dev[256] < 5.0
+
+
+def test_wave_density_mode_pulls_particle(orc):
+    # rho = 1 + A cos(k x): spectral Phi = -4piG A cos(kx)/k^2, node gradient by
+    # central differences gives -4piG A sin(k x) sin(k dx)/(k^2 dx); CIC then
+    # interpolates linearly between the two nodes.
+    shape = (32, 4, 4)
+    A, G4 = 0.2, 3.0
+    k = TWO_PI
+    x = np.arange(32) / 32
+    psi = np.sqrt(1 + A * np.cos(k * x))[:, None, None] * np.ones(shape)
+    pos = np.array([[0.1 + 1e-3, 0.25, 0.5], [0.6, 0.1, 0.3]])
+    cfg = orc.make_config(shape, four_pi_G=G4, n_particles=2, particle_mass=0.0)
+    acc = orc.cic_force(cfg, orc.potential(cfg, psi, pos), pos)
+    dx = 1 / 32
+    g = -G4 * A * np.sin(k * x) * np.sin(k * dx) / (k * k * dx)
+    for p in range(2):
+        s = pos[p, 0] / dx
+        i = int(np.floor(s))
+        f = s - i
+        ex = (1 - f) * g[i % 32] + f * g[(i + 1) % 32]
+        assert acc[p, 0] == pytest.approx(ex, rel=1e-12, abs=1e-14)
+        assert abs(acc[p, 1]) < 1e-12 and abs(acc[p, 2]) < 1e-12
+    assert acc[0, 0] < 0   # just right of the overdensity at x = 0: pulled back
+
+
+# ---------------------------------------------------------- time stepping
+def test_free_evolution_is_exact(orc):
+    wl = inputs.plane_wave_box(32, seed=0)
+    pw = wl.extra["waves"]
+    cfg = orc.make_config((32,) * 3, four_pi_G=0.0)
+    psi, _, _ = orc.kdk(cfg, wl.psi, nsteps=100, dt=wl.dt)
+    exact = pw.evaluate(100 * wl.dt)
+    assert rel_l2(psi, exact) < 1e-12
+
+
+def test_free_evolution_anisotropic_box_and_eta(orc):
+    # non-cubic grid, unequal lengths and hbar/m != 1 catch transposed axes
+    # and a misplaced eta
+    rng = np.random.default_rng(3)
+    shape, L, eta = (16, 8, 12), (1.0, 0.5, 2.0), 0.37
+    modes = np.array([[1, 2, -3], [-4, 0, 5], [2, -1, 0]])
+    x, y, z = np.meshgrid(*grid_coords(shape, L), indexing="ij")
+    amps = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+
+    def field(t):
+        out = np.zeros(shape, complex)
+        for a, m in zip(amps, modes):
+            k = [TWO_PI * mi / li for mi, li in zip(m, L)]
+            w = 0.5 * eta * sum(ki * ki for ki in k)
+            out += a * np.exp(1j * (k[0] * x + k[1] * y + k[2] * z - w * t))
+        return out
+
+    cfg = orc.make_config(shape, L=L, hbar_over_m=eta, four_pi_G=0.0)
+    psi, _, _ = orc.kdk(cfg, field(0.0), nsteps=37, dt=3.1e-3)
+    assert rel_l2(psi, field(37 * 3.1e-3)) < 1e-12
+
+
+def test_single_plane_wave_with_gravity_is_exact(orc):
+    shape = (16, 16, 16)
+    x, y, z = np.meshgrid(*grid_coords(shape, 1.0), indexing="ij")
+    k = TWO_PI * np.array([2, -1, 3])
+    psi0 = 1.3 * np.exp(1j * (k[0] * x + k[1] * y + k[2] * z))
+    cfg = orc.make_config(shape, four_pi_G=5.0)
+    dt = 1e-3
+    psi, _, _ = orc.kdk(cfg, psi0, nsteps=50, dt=dt)
+    exact = psi0 * np.exp(-0.5j * (k @ k) * 50 * dt)
+    assert rel_l2(psi, exact) < 1e-12
+
+
+def _mode_amplitude(psi, k):
+    rho = np.abs(psi) ** 2
+    prof = rho.mean(axis=(1, 2))
+    x = np.arange(prof.size) / prof.size
+    return 2 * np.mean(prof * np.cos(k * x))
+
+
+def test_linear_jeans_oscillation_frequency(orc):
+    # omega^2 = eta^2 k^4 / 4 - 4 pi G rho_bar for a small cos(kx) perturbation
+    # (linearised Madelung equations of Sec. 2.2); choose 4piG rho = 0.75 k^4/4.
+    shape, k, eps = (32, 4, 4), TWO_PI, 1e-3
+    x = np.arange(32) / 32
+    psi0 = (1 + 0.5 * eps * np.cos(k * x))[:, None, None] * np.ones(shape)
+    rho_bar = float(np.mean(np.abs(psi0) ** 2))
+    G4 = 0.75 * k ** 4 / 4 / rho_bar
+    omega = math.sqrt(k ** 4 / 4 - G4 * rho_bar)
+    cfg = orc.make_config(shape, four_pi_G=G4)
+    dt = 2e-4
+    psi = psi0.copy()
+    amps = [_mode_amplitude(psi, k)]
+    for _ in range(900):
+        psi, _, _ = orc.kdk(cfg, psi, nsteps=1, dt=dt)
+        amps.append(_mode_amplitude(psi, k))
+    amps = np.array(amps)
+    i = int(np.argmax(amps < 0))
+    t0 = dt * (i - 1 + amps[i - 1] / (amps[i - 1] - amps[i]))
+    w_meas = math.pi / (2 * t0)
+    assert abs(w_meas / omega - 1) < 2e-3
+    # wrong gravity sign or factor would move omega far away
+    assert abs(math.sqrt(k ** 4 / 4) / omega - 1) > 0.5
+
+
+def test_linear_jeans_growth_rate(orc):
+    shape, k, eps = (32, 4, 4), TWO_PI, 1e-3
+    x = np.arange(32) / 32
+    psi0 = (1 + 0.5 * eps * np.cos(k * x))[:, None, None] * np.ones(shape)
+    rho_bar = float(np.mean(np.abs(psi0) ** 2))
+    G4 = 1.25 * k ** 4 / 4 / rho_bar
+    gamma = math.sqrt(G4 * rho_bar - k ** 4 / 4)
+    cfg = orc.make_config(shape, four_pi_G=G4)
+    T, n = 0.3, 1500
+    psi, _, _ = orc.kdk(cfg, psi0, nsteps=n, dt=T / n)
+    a0 = _mode_amplitude(psi0, k)
+    g_meas = math.acosh(_mode_amplitude(psi, k) / a0) / T
+    assert abs(g_meas / gamma - 1) < 2e-3
+
+
+def test_unitarity_and_reversibility_with_particles(orc):
+    wl = inputs.plane_wave_box(32, seed=1)
+    pos, vel = inputs.plummer(300, a=0.1, total_mass=0.1, seed=4)
+    cfg = orc.make_config((32,) * 3, n_particles=300, particle_mass=0.1 / 300)
+    m0 = np.sum(np.abs(wl.psi) ** 2)
+    psi, p, v = orc.kdk(cfg, wl.psi, pos, vel, nsteps=100, dt=wl.dt)
+    assert abs(np.sum(np.abs(psi) ** 2) / m0 - 1) < 1e-12
+    assert rel_l2(psi, wl.psi) > 1e-3          # it did evolve
+    psi2, p2, v2 = orc.kdk(cfg, psi, p, v, nsteps=100, dt=-wl.dt)
+    assert rel_l2(psi2, wl.psi) < 1e-10
+    assert np.max(np.abs(p2 - pos)) < 1e-10
+    assert np.max(np.abs(v2 - vel)) < 1e-10 * np.max(np.abs(vel))
+
+
+def test_second_order_convergence(orc):
+    wl = inputs.plane_wave_box(16, seed=2)
+    cfg = orc.make_config((16,) * 3, four_pi_G=40.0)
+    T = 0.02
+    ref, _, _ = orc.kdk(cfg, wl.psi, nsteps=1280, dt=T / 1280)
+    errs = []
+    for n in (20, 40, 80):
+        psi, _, _ = orc.kdk(cfg, wl.psi, nsteps=n, dt=T / n)
+        errs.append(rel_l2(psi, ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert errs[0] > 1e-8
+    assert abs(r1 - 4) < 0.2 and abs(r2 - 4) < 0.2
+
+
+def test_energy_conserved_to_second_order(orc):
+    # wave only: spectral kinetic + spectral Poisson make the semi-discrete
+    # system Hamiltonian, so the KDK energy error is O(dt^2)
+    wl = inputs.plane_wave_box(16, seed=3)
+    cfg = orc.make_config((16,) * 3, four_pi_G=10.0)
+    e0 = orc.energy(cfg, wl.psi)["e_total"]
+    drifts = []
+    for n in (20, 40, 80):
+        psi, _, _ = orc.kdk(cfg, wl.psi, nsteps=n, dt=0.02 / n)
+        drifts.append(abs(orc.energy(cfg, psi)["e_total"] - e0))
+    assert abs(drifts[0] / drifts[1] - 4) < 0.3 and abs(drifts[1] / drifts[2] - 4) < 0.3
+    # with particles, CIC + central differences conserve momentum, not energy:
+    # the leftover drift is a small spatial-discretisation effect
+    pos, vel = inputs.plummer(200, a=0.1, total_mass=0.2, seed=9)
+    cfg = orc.make_config((16,) * 3, four_pi_G=10.0, n_particles=200, particle_mass=0.2 / 200)
+    e0 = orc.energy(cfg, wl.psi, pos, vel)["e_total"]
+    psi, p, v = orc.kdk(cfg, wl.psi, pos, vel, nsteps=40, dt=0.02 / 40)
+    assert abs(orc.energy(cfg, psi, p, v)["e_total"] / e0 - 1) < 1e-6
+
+
+def test_energy_terms_closed_form(orc):
+    # plane wave: e_kin = eta^2/2 |k|^2 |A|^2 V; uniform density: e_pot = 0
+    shape = (8, 8, 8)
+    x, y, z = np.meshgrid(*grid_coords(shape, 1.0), indexing="ij")
+    k = TWO_PI * np.array([1, 2, 0])
+    psi = 0.5 * np.exp(1j * (k[0] * x + k[1] * y + k[2] * z))
+    cfg = orc.make_config(shape, hbar_over_m=0.8)
+    e = orc.energy(cfg, psi)
+    assert e["mass"] == pytest.approx(0.25, rel=1e-14)
+    assert e["e_kin"] == pytest.approx(0.5 * 0.64 * (k @ k) * 0.25, rel=1e-13)
+    assert abs(e["e_pot"]) < 1e-14
+
+
+def test_paper_energy_terms_plane_wave(orc):
+    # plane wave of amplitude A: rho v = A^2 sin(k dx)/dx per axis (central
+    # difference), grad sqrt(rho) = 0, V = 0 for Phi = 0
+    n = 16
+    x, y, z = np.meshgrid(*grid_coords((n,) * 3, 1.0), indexing="ij")
+    k = TWO_PI * np.array([1, 0, 2])
+    A = 0.7
+    psi = A * np.exp(1j * (k[0] * x + k[1] * y + k[2] * z))
+    cfg = orc.make_config((n,) * 3)
+    d = orc.paper_energies(cfg, psi, np.zeros((n,) * 3))
+    dx = 1 / n
+    j = A * A * np.sin(k * dx) / dx
+    assert d["K"] == pytest.approx(0.5 * (j @ j) / (A * A), rel=1e-12)
+    assert abs(d["Q"]) < 1e-20 and abs(d["V"]) < 1e-20
+
+
+def test_dt_auto_formula(orc):
+    # parity unpinned beyond the printed CFL formula (Sec. 3.5)
+    shape = (16, 16, 16)
+    phi = np.zeros(shape)
+    phi[3, 4, 5] = -2.0
+    cfg = orc.make_config(shape, hbar_over_m=1.0)
+    kin = 4 / (3 * math.pi) / 256
+    pot = TWO_PI / 2.0
+    assert orc.dt_auto(cfg, phi) == pytest.approx(0.9 * 0.5 * min(kin, pot), rel=1e-15)
+    phi[0, 0, 0] = 1e4
+    assert orc.dt_auto(cfg, phi) == pytest.approx(0.45 * TWO_PI / 1e4, rel=1e-15)
+
+
+# ------------------------------------------------------ analysis / corrector
+def test_power_spectrum_single_mode_and_white_noise(orc):
+    n = 16
+    x, y, z = np.meshgrid(*grid_coords((n,) * 3, 1.0), indexing="ij")
+    rho = 1 + 0.1 * np.cos(TWO_PI * (3 * x + 4 * z))
+    pk, cnt = orc.power_spectrum(rho)
+    nz = np.nonzero(pk > 1e-20)[0]
+    assert list(nz) == [5]
+    # two modes (+/-m) of |delta_k|/N^3 = 0.05 each, averaged over the shell
+    assert pk[5] * cnt[5] == pytest.approx(2 * 0.05 ** 2, rel=1e-12)
+    noise = 1 + 0.01 * np.random.default_rng(0).standard_normal((32,) * 3)
+    pk, cnt = orc.power_spectrum(noise)
+    flat = pk[2:16]
+    assert np.std(flat) / np.mean(flat) < 0.15
+
+
+def test_restriction_of_band_limited_field(orc):
+    nf, nc = 16, 8
+    xs_f = grid_coords((nf,) * 3, 1.0)
+    xs_c = grid_coords((nc,) * 3, 1.0)
+    modes = [(1, -2, 3), (-3, 0, 1), (0, 2, -1)]
+
+    def f(xs):
+        x, y, z = np.meshgrid(*xs, indexing="ij")
+        return sum((j + 1) * np.exp(TWO_PI * 1j * (m[0] * x + m[1] * y + m[2] * z))
+                   for j, m in enumerate(modes))
+
+    out = orc.restrict(f(xs_f), nc)
+    assert rel_l2(out, f(xs_c)) < 1e-13
+    # a mode at the coarse Nyquist (|m| = nc/2) is dropped
+    x, y, z = np.meshgrid(*xs_f, indexing="ij")
+    assert np.max(np.abs(orc.restrict(np.exp(TWO_PI * 1j * 4 * x), nc))) < 1e-14
+
+
+def test_conv3d_forward_matches_library_correlation(orc):
+    rng = np.random.default_rng(7)
+    n, cin, cout = 6, 3, 4
+    x = rng.standard_normal((cin, n, n, n))
+    w = rng.standard_normal((cout, cin, 27))
+    b = rng.standard_normal(cout)
+    y = orc.conv3d_fwd(x, w, b)
+    for co in range(cout):
+        ref = b[co] + sum(ndimage.correlate(x[ci], w[co, ci].reshape(3, 3, 3), mode="wrap")
+                          for ci in range(cin))
+        assert np.max(np.abs(y[co] - ref)) < 1e-12
+
+
+def test_conv3d_backward_finite_differences(orc):
+    rng = np.random.default_rng(8)
+    n, cin, cout = 5, 2, 3
+    x = rng.standard_normal((cin, n, n, n))
+    w = rng.standard_normal((cout, cin, 27))
+    b = rng.standard_normal(cout)
+    R = rng.standard_normal((cout, n, n, n))
+    dx, dw, db = orc.conv3d_bwd(x, w, R)
+
+    def loss(x_, w_, b_):
+        return float(np.sum(orc.conv3d_fwd(x_, w_, b_) * R))
+
+    h = 1e-6
+    for _ in range(6):
+        idx = tuple(rng.integers(0, s) for s in w.shape)
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += h
+        wm[idx] -= h
+        assert (loss(x, wp, b) - loss(x, wm, b)) / (2 * h) == pytest.approx(dw[idx], rel=1e-7, abs=1e-7)
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        assert (loss(xp, w, b) - loss(xm, w, b)) / (2 * h) == pytest.approx(dx[idx], rel=1e-7, abs=1e-7)
+    bp = b.copy()
+    bp[1] += h
+    assert (loss(x, w, bp) - loss(x, w, b)) / h == pytest.approx(db[1], rel=1e-6)
+
+
+def test_bf16_rounding_is_nearest_even(orc):
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -9, -3.0e-3, 65504.0])
+    out = orc.round_bf16(vals)
+    assert out[0] == 1.0
+    assert out[1] == 1.0 + 2 ** -7 or out[1] == 1.0    # tie -> even mantissa
+    assert out[1] == 1.0
+    assert out[2] == 1.0 + 2 ** -7
+    assert out[3] == 1.0
+    assert abs(out[4] / -3.0e-3 - 1) < 2 ** -8
+    assert out[5] == 65536.0
+
+
+# ------------------------------------------------------------- generators
+def test_grf_shell_spectrum_is_gaussian(orc):
+    n = 64
+    psi = inputs.grf_soliton(n, rho_c=0.0, seed=3)
+    assert np.mean(np.abs(psi) ** 2) == pytest.approx(1.0, rel=1e-12)
+    F = np.fft.fftn(psi)
+    m = np.fft.fftfreq(n, 1 / n)
+    mm = np.sqrt(m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2)
+    shell = np.rint(mm).astype(int)
+    k0 = 16 * TWO_PI
+    for b in (4, 8, 12, 16):
+        sel = shell == b
+        meas = np.mean(np.abs(F[sel]) ** 2)
+        model = np.mean(np.exp(-(TWO_PI * mm[sel]) ** 2 / k0 ** 2))
+        ratio0 = meas / model
+        if b == 4:
+            c0 = ratio0
+        else:
+            assert ratio0 / c0 == pytest.approx(1.0, rel=4 / math.sqrt(sel.sum()) * 3)
+
+
+def test_plummer_mass_profile_and_virial():
+    a, M, G = 0.03, 0.1, 1 / (4 * math.pi)
+    pos, vel = inputs.plummer(200_000, a=a, total_mass=M, seed=5)
+    d = pos.astype(np.float64) - 0.5
+    r = np.sqrt((d ** 2).sum(1))
+    rmax = 0.4
+    fmax = rmax ** 3 / (rmax ** 2 + a ** 2) ** 1.5
+    cdf = lambda rr: (rr ** 3 / (rr ** 2 + a ** 2) ** 1.5) / fmax
+    assert stats.kstest(r, cdf).pvalue > 1e-3
+    K = 0.5 * (M / len(r)) * float((vel.astype(np.float64) ** 2).sum())
+    W = 3 * math.pi * G * M * M / (32 * a)
+    assert 2 * K / W == pytest.approx(1.0, abs=0.03)
+    assert pos.min() >= 0 and pos.max() < 1
