@@ -1,0 +1,218 @@
+"""Benchmark: grid cell-updates/s of the KDK split step on one MI355X.
+
+Workload: the coupled halo -- 256^3 complex64 wave field (GRF with power
+exp(-k^2/k0^2), k0 = 16 * 2 pi / L, plus a soliton core) and 1e6 CIC-coupled
+Plummer baryon particles, dt = 0.2 dx^2 -- resident in HBM before timing.
+A step is one full kick-drift-kick step (all eight grid passes plus the
+particle kick/drift/deposit; periodic particle re-sorts included).
+
+Prints one JSON line with the metric, a per-kernel roofline entry for the
+dominant pass (algorithmic bytes / HIP-event duration on the plan's stream),
+the whole-step roofline fraction, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--particles 1000000]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell (grid passes) and per particle
+BYTES_PER_CELL = {
+    "z_potential_kick": 24, "y_fft_psi_fwd": 16, "x_kinetic": 16, "y_fft_psi_inv": 16,
+    "z_density_r2c": 28, "y_fft_spec_fwd": 8, "x_green": 8, "y_fft_spec_inv": 8,
+    "z_potential_close_kick": 24,
+}
+BYTES_PER_PARTICLE = {"particles_kick_drift_deposit": 48, "particles_close_kick": 36}
+STEP_BYTES_PER_CELL = 124
+STEP_BYTES_PER_PARTICLE = 48
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted((ROOT / "paper_2606_25026_amd" / "csrc").glob("*")):
+        h.update(f.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, launches_cells: int):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None."""
+    f = ROOT / "profiles" / "traffic_counters.json"
+    if not f.exists():
+        return None
+    try:
+        d = json.loads(f.read_text())
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None  # the kernels changed since the counters were taken
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s: float = 20.0):
+    import oracle
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    oracle.set_threads(cores)
+    cfg = oracle.make_config((wl.n,) * 3, n_particles=wl.n_particles,
+                             particle_mass=wl.particle_mass)
+    pos = wl.pos.astype(np.float64)
+    vel = wl.vel.astype(np.float64)
+    t = time.perf_counter()
+    oracle.kdk(cfg, wl.psi, pos, vel, nsteps=0, dt=wl.dt)   # initial potential only
+    setup = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.kdk(cfg, wl.psi, pos, vel, nsteps=1, dt=wl.dt)
+    one = time.perf_counter() - t - setup
+    steps = max(1, min(10, int(budget_s / max(one, 1e-3))))
+    t = time.perf_counter()
+    oracle.kdk(cfg, wl.psi, pos, vel, nsteps=steps, dt=wl.dt)
+    per = (time.perf_counter() - t - setup) / steps
+    return {"value": wl.n ** 3 / per, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} unmerged FP64 KDK steps of the same {wl.n}^3 + "
+                      f"{wl.n_particles}-particle halo (initial Poisson solve subtracted)",
+            "s_per_step": per}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--sort-interval", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without per-kernel HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not a built path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_25026_amd import inputs, wdm
+
+    wdm.load()
+    dev = torch.device("cuda:0")
+    wl = inputs.coupled_halo(n=args.n, n_particles=args.particles, seed=0)
+    n3 = args.n ** 3
+    cfg = wdm.make_config(args.n, n_particles=wl.n_particles, particle_mass=wl.particle_mass)
+    plan = wdm.Plan(cfg, device=dev)
+    h = plan.handle
+    psi = torch.from_numpy(wl.psi.astype(np.complex64)).to(dev)
+    pos = torch.from_numpy(wl.pos).to(dev) if wl.n_particles else None
+    vel = torch.from_numpy(wl.vel).to(dev) if wl.n_particles else None
+    wdm.wdm_set_state(h, 0, psi, pos, vel)
+    wdm.wdm_set_sort_interval(h, args.sort_interval)
+    e0 = wdm.wdm_energy(h, 0)
+    print(f"# workload ready: {args.n}^3 + {wl.n_particles} particles, dt={wl.dt:.4e}, "
+          f"dt_auto={e0['dt_auto']:.4e}", file=sys.stderr, flush=True)
+
+    # achievable-bandwidth reference (plain copy of one psi-sized buffer)
+    src = torch.empty(n3 * 8, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms = wdm.wdm_copy_bandwidth(dst, src, n3 * 8, reps=20)
+    copy_gbs = 2 * n3 * 8 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+
+    wdm.wdm_step(h, args.warmup, wl.dt)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        wdm.wdm_profile_read(h)          # clear
+        wdm.wdm_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wdm.wdm_step(h, args.steps, wl.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = []
+    if not args.no_profile:
+        wdm.wdm_profile(h, False)
+        stats = wdm.wdm_profile_read(h)
+    e1 = wdm.wdm_energy(h, 0)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n3 * args.steps / elapsed
+
+    roofline = None
+    per_kernel = {}
+    for s in stats:
+        nm = s["name"]
+        avg_ms = s["total_ms"] / max(1, s["launches"])
+        if nm in BYTES_PER_CELL:
+            alg = BYTES_PER_CELL[nm] * n3
+        elif nm in BYTES_PER_PARTICLE:
+            alg = BYTES_PER_PARTICLE[nm] * wl.n_particles
+        else:
+            alg = None
+        per_kernel[nm] = {"launches": s["launches"], "avg_us": avg_ms * 1e3,
+                          "share": s["total_ms"] / (elapsed * 1e3),
+                          "gbs": (alg / (avg_ms * 1e-3) / 1e9) if alg else None}
+    grid_kernels = [s for s in stats if s["name"] in BYTES_PER_CELL]
+    if grid_kernels:
+        dom = max(grid_kernels, key=lambda s: s["total_ms"])
+        avg_s = dom["total_ms"] / dom["launches"] * 1e-3
+        alg = BYTES_PER_CELL[dom["name"]] * n3
+        ach = alg / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "traffic": traffic_from_profiles(dom["name"], n3),
+                    "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6}
+    step_bytes = STEP_BYTES_PER_CELL * n3 + STEP_BYTES_PER_PARTICLE * wl.n_particles
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# timing the FP64 CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl)
+
+    out = {
+        "metric": "grid cell-updates/s (KDK) at 256^3 c64 + % HBM roofline",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"coupled halo {args.n}^3 complex64 + {wl.n_particles} CIC "
+                               "Plummer particles (GRF k0=16*2pi + soliton rc=0.05)",
+                   "grid": args.n, "particles": wl.n_particles, "dt": wl.dt,
+                   "phase_args": "fp64", "sort_interval": args.sort_interval,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "step_roofline": {"bytes_per_cell_update": step_bytes / n3, "achieved": step_gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
+                          "copy_kernel_gbs": copy_gbs},
+        "per_kernel": per_kernel,
+        "profiled": not args.no_profile,
+        "mass_drift": e1["mass"] / e0["mass"] - 1.0,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

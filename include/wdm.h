@@ -1,0 +1,170 @@
+/*
+ * wdm.h -- C ABI of the MI355X split-step Schroedinger-Poisson library.
+ *
+ * The library advances a wave-dark-matter field psi coupled to N-body baryon
+ * particles with the kick-drift-kick split-step Fourier method of Meng & Dong,
+ * "WaveDM.jl" (Sec. 3.1, Eq. SPE_solver_KDK and Algorithm 1), in code units
+ * (Sec. 2.2, Eq. SPE_dimensionless) on a periodic box:
+ *
+ *     i d(psi)/dt = -(eta/2) lap(psi) + (1/eta) Phi psi,     eta = hbar/m
+ *     lap(Phi)    = 4 pi G (|psi|^2 + rho_b - mean),
+ *
+ * with the periodic FFT Poisson solver of Sec. 3.2.1 and the dynamic baryon
+ * mode of Sec. 3.2.2 (particles feed rho_b through a cloud-in-cell deposit and
+ * feel -grad Phi, central differences of Sec. 3.1, CIC-interpolated).
+ *
+ * Conventions shared by every entry point:
+ *  - Grids are C-ordered [nx][ny][nz] with z contiguous; node i sits at
+ *    x_i = i * lx / nx (periodic reading of the grid of Sec. 3.1).
+ *  - psi buffers are interleaved complex: complex64 (float re, im) when the
+ *    plan precision is WDM_C64, complex128 for WDM_C128.  Real grids (density,
+ *    potential) are float for WDM_C64 and double for WDM_C128.
+ *  - Particle buffers are float32 [n_particles][3], positions in [0, L).
+ *  - All pointers named "dev" are device pointers owned by the caller; the
+ *    library reads them during the call (stream-ordered on the plan's stream)
+ *    and keeps no reference to them afterwards.  Host pointers are noted.
+ *  - All device memory the plan needs lives in one caller-provided workspace
+ *    (wdm_workspace_bytes); the library never allocates device memory.
+ *  - Every call is ordered on the plan's HIP stream.  Only wdm_energy,
+ *    wdm_profile_read and wdm_copy_bandwidth synchronise with the host.
+ *  - On an error nothing is launched, the plan keeps its state and
+ *    wdm_last_error() describes the failure (thread-local string).
+ *  - A plan is not thread safe; distinct plans are independent.
+ */
+#ifndef WDM_H
+#define WDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wdm_plan wdm_plan;
+
+typedef enum {
+    WDM_OK = 0,
+    WDM_EINVAL = 1,       /* bad argument (shape, size, index, null pointer) */
+    WDM_ENOMEM = 2,       /* workspace too small */
+    WDM_EDEVICE = 3,      /* a HIP call failed */
+    WDM_ESTATE = 4,       /* call not valid in the plan's state (e.g. step before set_state) */
+    WDM_EUNSTABLE = 5,    /* non-finite state or CFL violation detected */
+    WDM_EUNSUPPORTED = 6  /* axis length or option not built */
+} wdm_status;
+
+typedef enum { WDM_C64 = 0, WDM_C128 = 1 } wdm_precision;
+
+/* One periodic box (an ensemble has several). */
+typedef struct {
+    int32_t nx, ny, nz;        /* each in {16,32,64,96,128,192,256,384,512} */
+    double lx, ly, lz;         /* box lengths; dx = lx / nx */
+    double hbar_over_m;        /* eta (1 in code units, Sec. 2.2) */
+    double four_pi_G;          /* Poisson prefactor (Sec. 3.2.1); 0 = free equation */
+    int64_t n_particles;       /* baryon particles (0 = none) */
+    double particle_mass;      /* equal-mass particles */
+    int32_t precision;         /* wdm_precision; all members of a plan share it */
+    uint32_t flags;            /* reserved, must be 0 */
+} wdm_config;
+
+/* Diagnostics of a synchronised state (Sec. 3.6 energy bookkeeping). */
+typedef struct {
+    double mass;               /* sum |psi|^2 dV */
+    double e_kin;              /* eta^2/2 int |grad psi|^2, spectral */
+    double e_pot;              /* 1/2 int (|psi|^2 + rho_b) Phi dV */
+    double e_kin_particles;    /* 1/2 sum m v^2 */
+    double e_total;            /* e_kin + e_pot + e_kin_particles */
+    double momentum[3];        /* particle momentum sum m v */
+    double max_abs_phi;        /* max |Phi| over the grid */
+    double t;                  /* simulated time */
+    double dt;                 /* time step last used (or selected) */
+    double dt_auto;            /* CFL step of Sec. 3.5 from the last wdm_set_state */
+} wdm_energy_t;
+
+typedef struct {
+    char name[40];             /* pass name, e.g. "x_kinetic" */
+    int64_t launches;          /* launches recorded */
+    double total_ms;           /* summed HIP-event durations */
+} wdm_kernel_stat;
+
+/* Bytes of device workspace a plan over `members` needs (256-byte aligned
+ * sections).  Returns 0 for an invalid or unsupported configuration. */
+size_t wdm_workspace_bytes(const wdm_config* members, int32_t n_members);
+
+/* Create a plan for n_members boxes (n_members > 1: an ensemble advanced
+ * together, one launch per pass per size class).  `workspace` is a device
+ * buffer of at least wdm_workspace_bytes (caller owned, must outlive the
+ * plan); `hip_stream` is the hipStream_t all work is ordered on (NULL = null
+ * stream).  Twiddle tables are computed in FP64 on the host and uploaded
+ * (this call synchronises).  *out receives the plan. */
+wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* workspace,
+                           size_t workspace_bytes, void* hip_stream, wdm_plan** out);
+wdm_status wdm_plan_destroy(wdm_plan* plan);
+
+/* Load the state of one member: psi (dev, [nx][ny][nz] complex of the plan
+ * precision), pos and vel (dev, float [n_particles][3], may be NULL only when
+ * n_particles == 0) at time t0.  Builds the initial potential Phi_0 from psi
+ * and the deposited particles (Algorithm 1 needs Phi before its first kick),
+ * its FP64 max |Phi| and the CFL step dt_auto of Sec. 3.5 (zeta = 0.9). */
+wdm_status wdm_set_state(wdm_plan* plan, int32_t member, const void* psi, const float* pos,
+                         const float* vel, double t0);
+
+/* Per-member time step for ensembles, used by wdm_step(plan, n, 0). */
+wdm_status wdm_set_member_dt(wdm_plan* plan, int32_t member, double dt);
+
+/* Advance every member by n KDK steps (Eq. SPE_solver_KDK (a)-(d)).  dt != 0:
+ * that step (negative = backwards in time) for all members; dt == 0: each
+ * member's own dt (wdm_set_member_dt, else its dt_auto).  Half kicks of
+ * consecutive steps share one potential and are merged.  The particle KDK
+ * leapfrog is synchronous with the wave kicks (one particle step per wave
+ * step).  Between calls the state is synchronised (positions, velocities and
+ * psi at the same time). */
+wdm_status wdm_step(wdm_plan* plan, int64_t n, double dt);
+
+/* Copy psi (dev out, plan precision) of a member. */
+wdm_status wdm_get_psi(wdm_plan* plan, int32_t member, void* psi_out);
+
+/* Density |psi|^2, plus the CIC baryon density when include_baryons != 0
+ * (dev out, real grid of the plan precision). */
+wdm_status wdm_density(wdm_plan* plan, int32_t member, void* rho_out, int32_t include_baryons);
+
+/* Total potential Phi of the synchronised state (dev out, real grid). */
+wdm_status wdm_potential(wdm_plan* plan, int32_t member, void* phi_out);
+
+/* FP64 diagnostics (host out).  Synchronises the plan's stream. */
+wdm_status wdm_energy(wdm_plan* plan, int32_t member, wdm_energy_t* out);
+
+/* Particle positions and velocities in their original order (dev out,
+ * float [n_particles][3]; either pointer may be NULL). */
+wdm_status wdm_particles(wdm_plan* plan, int32_t member, float* pos_out, float* vel_out);
+
+/* Forward (inverse = 0, unnormalised exp(-i k.x)) or inverse (inverse = 1,
+ * scaled by 1/N) 3D FFT of a member's psi in place -- the transform used by
+ * the drift step (b) -- exposed for verification.  Leaves the member's
+ * state unsynchronised: call wdm_set_state before stepping again. */
+wdm_status wdm_fft3d(wdm_plan* plan, int32_t member, int32_t inverse);
+
+/* Re-sort particles by cell every `interval` steps (0 = only in
+ * wdm_set_state).  Ordering only affects speed and atomic summation order. */
+wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);
+
+/* Per-pass timing: while enabled, every kernel launch of wdm_step is
+ * bracketed by HIP events on the plan's stream.  wdm_profile_read
+ * synchronises, reports one entry per pass (up to `cap`, host array) and
+ * clears the record. */
+wdm_status wdm_profile(wdm_plan* plan, int32_t enable);
+wdm_status wdm_profile_read(wdm_plan* plan, wdm_kernel_stat* out, int32_t cap, int32_t* count);
+
+/* Achievable-bandwidth reference: a plain float4 copy of `bytes` from src to
+ * dst (dev), `reps` times on `hip_stream`; returns the mean ms per copy
+ * (host out).  Synchronises. */
+wdm_status wdm_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps,
+                              void* hip_stream, double* ms_per_copy);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* wdm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WDM_H */

@@ -1,0 +1,653 @@
+// Host side of libwdm: plan creation (workspace carving, FP64 twiddles),
+// the merged kick-drift-kick schedule of Algorithm 1, diagnostics, profiling
+// and the C ABI declared in include/wdm.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/wdm.h"
+#include "wdm_internal.hpp"
+
+namespace wdm {
+int64_t axis_tiles(int n, int64_t pencils, int prec);
+hipError_t launch_scale_complex(hipStream_t s, void* p, int64_t n, double scale, int prec);
+int sort_blocks(int64_t np);
+}  // namespace wdm
+
+using namespace wdm;
+
+namespace {
+
+thread_local std::string g_err;
+
+wdm_status fail(wdm_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        const size_t o = off;
+        off += bytes;
+        return o;
+    }
+};
+
+struct MemberLayout {
+    size_t psi, phi, rho_b, spec, nyq, dt, results;
+    size_t p[7], a[7], key_a, key_b, idx_a, idx_b, hist;
+};
+
+struct Layout {
+    std::vector<MemberLayout> m;
+    std::map<int, size_t> tw;     // axis length -> twiddle table offset
+    size_t scratch = 0, partials = 0, table = 0, total = 0;
+    int64_t partial_rows = 0;
+};
+
+enum Kind : int {
+    kKZPot = 0, kKParticles, kKYPsiF, kKXKin, kKYPsiI, kKZDens, kKYSpecF, kKXGreen, kKYSpecI,
+    kKClose, kKCloseParticles, kKSort, kKinds
+};
+const char* kKindNames[kKinds] = {"z_potential_kick", "particles_kick_drift_deposit",
+                                  "y_fft_psi_fwd",    "x_kinetic",
+                                  "y_fft_psi_inv",    "z_density_r2c",
+                                  "y_fft_spec_fwd",   "x_green",
+                                  "y_fft_spec_inv",   "z_potential_close_kick",
+                                  "particles_close_kick", "particle_sort"};
+
+bool valid_config(const wdm_config& c, std::string& why) {
+    if (!axis_supported(c.nx) || !axis_supported(c.ny) || !axis_supported(c.nz)) {
+        why = "axis lengths must be in {16,32,64,96,128,192,256,384,512}";
+        return false;
+    }
+    if (!(c.lx > 0 && c.ly > 0 && c.lz > 0)) {
+        why = "box lengths must be positive";
+        return false;
+    }
+    if (!(c.hbar_over_m > 0) || !std::isfinite(c.four_pi_G)) {
+        why = "hbar_over_m must be positive and four_pi_G finite";
+        return false;
+    }
+    if (c.n_particles < 0 || c.n_particles > (int64_t(1) << 31) - 1) {
+        why = "n_particles out of range";
+        return false;
+    }
+    if (c.n_particles > 0 && !(c.particle_mass >= 0 && std::isfinite(c.particle_mass))) {
+        why = "particle_mass must be finite and non-negative";
+        return false;
+    }
+    if (c.precision != WDM_C64 && c.precision != WDM_C128) {
+        why = "precision must be WDM_C64 or WDM_C128";
+        return false;
+    }
+    if (c.flags != 0) {
+        why = "flags must be 0";
+        return false;
+    }
+    return true;
+}
+
+bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
+    if (!mem || n <= 0) {
+        why = "need at least one member";
+        return false;
+    }
+    const int prec = mem[0].precision;
+    for (int i = 0; i < n; ++i) {
+        if (!valid_config(mem[i], why)) {
+            why = "member " + std::to_string(i) + ": " + why;
+            return false;
+        }
+        if (mem[i].precision != prec) {
+            why = "all members must share one precision";
+            return false;
+        }
+    }
+    const size_t cs = prec ? 16 : 8, rs = prec ? 8 : 4;
+    Carver c;
+    int64_t maxn = 0, maxplane = 0;
+    L.m.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const wdm_config& g = mem[i];
+        const int64_t cells = int64_t(g.nx) * g.ny * g.nz;
+        maxn = std::max(maxn, cells);
+        maxplane = std::max(maxplane, int64_t(g.ny) * g.nz);
+        MemberLayout& m = L.m[i];
+        m.psi = c.take(cells * cs);
+        m.phi = c.take(cells * rs);
+        m.rho_b = c.take(cells * rs);
+        m.spec = c.take(int64_t(g.nx) * g.ny * (g.nz / 2) * cs);
+        m.nyq = c.take(int64_t(g.nx) * g.ny * cs);
+        m.dt = c.take(4 * sizeof(double));
+        m.results = c.take(kRedFields * sizeof(double));
+        const int64_t np = std::max<int64_t>(g.n_particles, 0);
+        for (int a = 0; a < 7; ++a) m.p[a] = c.take(np * 4);
+        for (int a = 0; a < 7; ++a) m.a[a] = c.take(np * 4);
+        m.key_a = c.take(np * 4);
+        m.key_b = c.take(np * 4);
+        m.idx_a = c.take(np * 4);
+        m.idx_b = c.take(np * 4);
+        m.hist = c.take(int64_t(256) * std::max(1, sort_blocks(np)) * 4);
+        for (int len : {g.nx, g.ny, g.nz})
+            if (!L.tw.count(len)) L.tw[len] = 0;
+    }
+    for (auto& kv : L.tw) kv.second = c.take(size_t(kv.first) * cs);
+    L.scratch = c.take(maxn * cs);
+    L.partial_rows = std::max<int64_t>(kRedBlocks, (maxplane + 7) / 8);
+    L.partials = c.take(L.partial_rows * kRedFields * sizeof(double));
+    L.table = c.take(n * sizeof(MemberDev));
+    L.total = (c.off + kAlign - 1) / kAlign * kAlign;
+    return true;
+}
+
+struct SizeClass {
+    int first, count;       // device-table range
+    int nx, ny, nz;
+    int64_t max_np;
+};
+
+struct Rec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct wdm_plan {
+    hipStream_t stream = nullptr;
+    int prec = 0;
+    std::vector<wdm_config> cfg;        // user order
+    std::vector<int> dev_index;         // user member -> device table slot
+    std::vector<MemberDev> host;        // device-table order
+    std::vector<SizeClass> classes;
+    std::vector<bool> has_state;        // user order
+    MemberDev* table = nullptr;
+    Layout layout;
+    uint8_t* ws = nullptr;
+    int sort_interval = 32;
+    int64_t steps_done = 0;
+    bool profiling = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_next = 0;
+};
+
+namespace {
+
+hipEvent_t take_event(wdm_plan* p) {
+    if (p->pool_next == p->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->pool.push_back(e);
+    }
+    return p->pool[p->pool_next++];
+}
+
+template <class F>
+hipError_t timed(wdm_plan* p, int kind, F&& f) {
+    if (!p->profiling) return f();
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return f();
+    hipEventRecord(a, p->stream);
+    const hipError_t e = f();
+    hipEventRecord(b, p->stream);
+    p->recs.push_back({kind, a, b});
+    return e;
+}
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        const hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess)                                                         \
+            return fail(WDM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t cells_of(const wdm_config& c) { return int64_t(c.nx) * c.ny * c.nz; }
+
+wdm_status check_member(wdm_plan* p, int32_t member) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    if (member < 0 || member >= int32_t(p->cfg.size()))
+        return fail(WDM_EINVAL, "member index out of range");
+    return WDM_OK;
+}
+
+Launch one(wdm_plan* p, int32_t member) {
+    return Launch{p->stream, p->table, p->dev_index[member], 1};
+}
+
+// Poisson solve of the density already deposited in rho_b plus |psi|^2
+// (psi in real space), ending with Phi written and psi untouched.
+hipError_t potential_from_state(wdm_plan* p, const Launch& L, const wdm_config& c) {
+    hipError_t e;
+    if ((e = launch_z_density(L, p->prec, c.nx, c.ny, c.nz, kDensDirect)) != hipSuccess) return e;
+    if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, false)) != hipSuccess) return e;
+    if ((e = launch_x_green(L, p->prec, c.nx, c.ny, c.nz)) != hipSuccess) return e;
+    if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, true)) != hipSuccess) return e;
+    return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZPhiOnly, kHalfKick);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* wdm_last_error(void) { return g_err.c_str(); }
+
+size_t wdm_workspace_bytes(const wdm_config* members, int32_t n_members) {
+    Layout L;
+    std::string why;
+    if (!make_layout(members, n_members, L, why)) {
+        g_err = why;
+        return 0;
+    }
+    return L.total;
+}
+
+wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* workspace,
+                           size_t workspace_bytes, void* hip_stream, wdm_plan** out) {
+    if (!out) return fail(WDM_EINVAL, "out is null");
+    *out = nullptr;
+    Layout L;
+    std::string why;
+    if (!make_layout(members, n_members, L, why)) return fail(WDM_EINVAL, why);
+    if (!workspace) return fail(WDM_EINVAL, "workspace is null");
+    if (workspace_bytes < L.total)
+        return fail(WDM_ENOMEM, "workspace of " + std::to_string(workspace_bytes) +
+                                    " bytes < required " + std::to_string(L.total));
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(WDM_EINVAL, "workspace must be 256-byte aligned");
+    auto* p = new wdm_plan();
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->prec = members[0].precision;
+    p->cfg.assign(members, members + n_members);
+    p->layout = L;
+    p->ws = static_cast<uint8_t*>(workspace);
+    p->has_state.assign(n_members, false);
+    uint8_t* ws = p->ws;
+    const size_t cs = p->prec ? 16 : 8;
+
+    // group members into size classes (identical grids), contiguous in the table
+    std::vector<int> order(n_members);
+    for (int i = 0; i < n_members; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const auto& A = members[a];
+        const auto& B = members[b];
+        return std::make_tuple(A.nx, A.ny, A.nz) < std::make_tuple(B.nx, B.ny, B.nz);
+    });
+    p->dev_index.assign(n_members, 0);
+    p->host.resize(n_members);
+    for (int d = 0; d < n_members; ++d) {
+        const int u = order[d];
+        p->dev_index[u] = d;
+        const wdm_config& c = members[u];
+        const MemberLayout& ml = L.m[u];
+        MemberDev& m = p->host[d];
+        std::memset(&m, 0, sizeof(m));
+        m.psi = ws + ml.psi;
+        m.phi = ws + ml.phi;
+        m.rho_b = ws + ml.rho_b;
+        m.spec = ws + ml.spec;
+        m.spec_nyq = ws + ml.nyq;
+        m.scratch = ws + L.scratch;
+        m.tw_x = ws + L.tw.at(c.nx);
+        m.tw_y = ws + L.tw.at(c.ny);
+        m.tw_z = ws + L.tw.at(c.nz);
+        m.nx = c.nx;
+        m.ny = c.ny;
+        m.nz = c.nz;
+        m.lx = c.lx;
+        m.ly = c.ly;
+        m.lz = c.lz;
+        m.eta = c.hbar_over_m;
+        m.four_pi_G = c.four_pi_G;
+        m.dt = reinterpret_cast<double*>(ws + ml.dt);
+        m.np = c.n_particles;
+        float** pp[6] = {&m.px, &m.py, &m.pz, &m.vx, &m.vy, &m.vz};
+        float** aa[6] = {&m.apx, &m.apy, &m.apz, &m.avx, &m.avy, &m.avz};
+        for (int a = 0; a < 6; ++a) {
+            *pp[a] = reinterpret_cast<float*>(ws + ml.p[a]);
+            *aa[a] = reinterpret_cast<float*>(ws + ml.a[a]);
+        }
+        m.id = reinterpret_cast<int32_t*>(ws + ml.p[6]);
+        m.aid = reinterpret_cast<int32_t*>(ws + ml.a[6]);
+        m.key_a = reinterpret_cast<uint32_t*>(ws + ml.key_a);
+        m.key_b = reinterpret_cast<uint32_t*>(ws + ml.key_b);
+        m.idx_a = reinterpret_cast<uint32_t*>(ws + ml.idx_a);
+        m.idx_b = reinterpret_cast<uint32_t*>(ws + ml.idx_b);
+        m.hist = reinterpret_cast<uint32_t*>(ws + ml.hist);
+        m.particle_mass = c.particle_mass;
+        m.partials = reinterpret_cast<double*>(ws + L.partials);
+        m.results = reinterpret_cast<double*>(ws + ml.results);
+        if (p->classes.empty() || p->classes.back().nx != c.nx || p->classes.back().ny != c.ny ||
+            p->classes.back().nz != c.nz)
+            p->classes.push_back({d, 0, c.nx, c.ny, c.nz, 0});
+        p->classes.back().count++;
+        p->classes.back().max_np = std::max<int64_t>(p->classes.back().max_np, c.n_particles);
+    }
+    p->table = reinterpret_cast<MemberDev*>(ws + L.table);
+
+    auto cleanup = [&](wdm_status st, const std::string& msg) {
+        delete p;
+        return fail(st, msg);
+    };
+    // twiddles W_n^m = exp(-2 pi i m / n) in FP64, rounded once
+    for (const auto& kv : L.tw) {
+        const int n = kv.first;
+        std::vector<double> d(2 * size_t(n));
+        std::vector<float> f(2 * size_t(n));
+        for (int m = 0; m < n; ++m) {
+            const double a = -kTwoPi * double(m) / double(n);
+            d[2 * m] = std::cos(a);
+            d[2 * m + 1] = std::sin(a);
+            f[2 * m] = float(d[2 * m]);
+            f[2 * m + 1] = float(d[2 * m + 1]);
+        }
+        const void* src = p->prec ? static_cast<const void*>(d.data()) : f.data();
+        if (hipMemcpy(ws + kv.second, src, size_t(n) * cs, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(WDM_EDEVICE, "twiddle upload failed");
+    }
+    if (hipMemcpy(p->table, p->host.data(), sizeof(MemberDev) * n_members,
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(WDM_EDEVICE, "member table upload failed");
+    // clear accumulators and slots that must start at zero
+    for (int d = 0; d < n_members; ++d) {
+        const MemberDev& m = p->host[d];
+        const int64_t cells = int64_t(m.nx) * m.ny * m.nz;
+        launch_zero(p->stream, m.rho_b, size_t(cells) * (p->prec ? 8 : 4));
+        launch_zero(p->stream, m.dt, 4 * sizeof(double));
+        launch_zero(p->stream, m.results, kRedFields * sizeof(double));
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return cleanup(WDM_EDEVICE, "plan initialisation failed");
+    *out = p;
+    g_err.clear();
+    return WDM_OK;
+}
+
+wdm_status wdm_plan_destroy(wdm_plan* plan) {
+    if (!plan) return fail(WDM_EINVAL, "null plan");
+    hipStreamSynchronize(plan->stream);
+    for (hipEvent_t e : plan->pool) hipEventDestroy(e);
+    delete plan;
+    return WDM_OK;
+}
+
+wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const float* pos,
+                         const float* vel, double t0) {
+    if (wdm_status s = check_member(p, member)) return s;
+    const wdm_config& c = p->cfg[member];
+    if (!psi) return fail(WDM_EINVAL, "psi is null");
+    if (c.n_particles > 0 && (!pos || !vel)) return fail(WDM_EINVAL, "pos/vel are null");
+    if (!std::isfinite(t0)) return fail(WDM_EINVAL, "t0 must be finite");
+    const Launch L = one(p, member);
+    const MemberDev& m = p->host[p->dev_index[member]];
+    const int64_t n = cells_of(c);
+    HIPCHK(hipMemcpyAsync(m.psi, psi, size_t(n) * (p->prec ? 16 : 8), hipMemcpyDeviceToDevice,
+                          p->stream));
+    HIPCHK(launch_zero(p->stream, m.rho_b, size_t(n) * (p->prec ? 8 : 4)));
+    if (c.n_particles > 0) {
+        HIPCHK(launch_particle_upload(p->stream, m, pos, vel));
+        HIPCHK(launch_particle_sort(p->stream, m, p->table, p->prec));
+        HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick));
+    }
+    HIPCHK(potential_from_state(p, L, c));
+    HIPCHK(launch_reduce_grid(L, p->prec, n, 0));
+    HIPCHK(launch_reduce_finish(L, 7, kRedBlocks, true));
+    HIPCHK(launch_dt_auto(L, 0.9, 4.0 / (3.0 * kPi)));
+    HIPCHK(launch_set_dt(L, t0, 3));
+    p->has_state[member] = true;
+    return WDM_OK;
+}
+
+wdm_status wdm_set_member_dt(wdm_plan* p, int32_t member, double dt) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!std::isfinite(dt)) return fail(WDM_EINVAL, "dt must be finite");
+    HIPCHK(launch_set_dt(one(p, member), dt, 2));
+    return WDM_OK;
+}
+
+wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    if (n < 0) return fail(WDM_EINVAL, "n must be >= 0");
+    if (!std::isfinite(dt)) return fail(WDM_EINVAL, "dt must be finite");
+    for (size_t i = 0; i < p->has_state.size(); ++i)
+        if (!p->has_state[i]) return fail(WDM_ESTATE, "wdm_set_state not called for every member");
+    if (n == 0) return WDM_OK;
+    const int prec = p->prec;
+    for (const auto& c : p->classes) {
+        const Launch L{p->stream, p->table, c.first, c.count};
+        HIPCHK(dt != 0.0 ? launch_set_dt(L, dt, 0) : launch_set_dt(L, 0.0, 1));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const KickMode km = i == 0 ? kHalfKick : kFullKick;
+        const bool resort = p->sort_interval > 0 && p->steps_done > 0 &&
+                            p->steps_done % p->sort_interval == 0;
+        for (const auto& c : p->classes) {
+            const Launch L{p->stream, p->table, c.first, c.count};
+            if (resort && c.max_np > 1) {
+                HIPCHK(timed(p, kKSort, [&] {
+                    hipError_t e = hipSuccess;
+                    for (int d = c.first; d < c.first + c.count && e == hipSuccess; ++d)
+                        e = launch_particle_sort(p->stream, p->host[d], p->table, prec);
+                    return e;
+                }));
+            }
+            HIPCHK(timed(p, kKZPot, [&] {
+                return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km);
+            }));
+            if (c.max_np > 0)
+                HIPCHK(timed(p, kKParticles, [&] { return launch_particles(L, prec, c.max_np, 0, km); }));
+            HIPCHK(timed(p, kKYPsiF, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, false); }));
+            HIPCHK(timed(p, kKXKin, [&] { return launch_x_kinetic(L, prec, c.nx, c.ny, c.nz); }));
+            HIPCHK(timed(p, kKYPsiI, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, true); }));
+            HIPCHK(timed(p, kKZDens, [&] {
+                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft);
+            }));
+            HIPCHK(timed(p, kKYSpecF, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, false); }));
+            HIPCHK(timed(p, kKXGreen, [&] { return launch_x_green(L, prec, c.nx, c.ny, c.nz); }));
+            HIPCHK(timed(p, kKYSpecI, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, true); }));
+        }
+        p->steps_done++;
+    }
+    for (const auto& c : p->classes) {
+        const Launch L{p->stream, p->table, c.first, c.count};
+        HIPCHK(timed(p, kKClose, [&] {
+            return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickOnly, kHalfKick);
+        }));
+        if (c.max_np > 0)
+            HIPCHK(timed(p, kKCloseParticles, [&] {
+                return launch_particles(L, prec, c.max_np, 1, kHalfKick);
+            }));
+        HIPCHK(launch_advance_time(L, n));
+    }
+    return WDM_OK;
+}
+
+wdm_status wdm_get_psi(wdm_plan* p, int32_t member, void* out) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!out) return fail(WDM_EINVAL, "psi_out is null");
+    const MemberDev& m = p->host[p->dev_index[member]];
+    HIPCHK(hipMemcpyAsync(out, m.psi, size_t(cells_of(p->cfg[member])) * (p->prec ? 16 : 8),
+                          hipMemcpyDeviceToDevice, p->stream));
+    return WDM_OK;
+}
+
+wdm_status wdm_potential(wdm_plan* p, int32_t member, void* out) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!out) return fail(WDM_EINVAL, "phi_out is null");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const MemberDev& m = p->host[p->dev_index[member]];
+    HIPCHK(hipMemcpyAsync(out, m.phi, size_t(cells_of(p->cfg[member])) * (p->prec ? 8 : 4),
+                          hipMemcpyDeviceToDevice, p->stream));
+    return WDM_OK;
+}
+
+wdm_status wdm_density(wdm_plan* p, int32_t member, void* out, int32_t include_baryons) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!out) return fail(WDM_EINVAL, "rho_out is null");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const wdm_config& c = p->cfg[member];
+    const Launch L = one(p, member);
+    const MemberDev& m = p->host[p->dev_index[member]];
+    const int64_t n = cells_of(c);
+    const bool inc = include_baryons && c.n_particles > 0;
+    if (inc) {
+        HIPCHK(launch_zero(p->stream, m.scratch, size_t(n) * (p->prec ? 8 : 4)));
+        HIPCHK(launch_particles(L, p->prec, c.n_particles, 3, kHalfKick));
+    }
+    HIPCHK(launch_density_out(L, p->prec, n, out, inc ? 1 : 0));
+    return WDM_OK;
+}
+
+wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!out) return fail(WDM_EINVAL, "out is null");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const wdm_config& c = p->cfg[member];
+    const Launch L = one(p, member);
+    const MemberDev& m = p->host[p->dev_index[member]];
+    const int64_t n = cells_of(c);
+    const int prec = p->prec;
+    // mass and max |Phi|
+    HIPCHK(launch_reduce_grid(L, prec, n, 0));
+    HIPCHK(launch_reduce_finish(L, 0, kRedBlocks, false));
+    HIPCHK(launch_reduce_finish(L, 7, kRedBlocks, true));
+    // potential energy with the deposited baryons
+    HIPCHK(launch_zero(p->stream, m.scratch, size_t(n) * (prec ? 8 : 4)));
+    if (c.n_particles > 0) HIPCHK(launch_particles(L, prec, c.n_particles, 3, kHalfKick));
+    HIPCHK(launch_reduce_grid(L, prec, n, 1));
+    HIPCHK(launch_reduce_finish(L, 2, kRedBlocks, false));
+    // spectral kinetic energy: F_z, F_y into scratch, F_x fused with the sum
+    HIPCHK(hipMemcpyAsync(m.scratch, m.psi, size_t(n) * (prec ? 16 : 8), hipMemcpyDeviceToDevice,
+                          p->stream));
+    HIPCHK(launch_axis_fft(L, prec, c.nx, c.ny, c.nz, 2, false, 1));
+    HIPCHK(launch_axis_fft(L, prec, c.nx, c.ny, c.nz, 1, false, 1));
+    HIPCHK(launch_x_kinetic_energy(L, prec, c.nx, c.ny, c.nz));
+    HIPCHK(launch_reduce_finish(L, 1, int(axis_tiles(c.nx, int64_t(c.ny) * c.nz, prec)), false));
+    if (c.n_particles > 0) {
+        HIPCHK(launch_reduce_particles(L, c.n_particles));
+        for (int f = 3; f < 7; ++f) HIPCHK(launch_reduce_finish(L, f, kRedBlocks, false));
+    }
+    double res[kRedFields], dts[4];
+    HIPCHK(hipMemcpyAsync(res, m.results, sizeof(res), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipMemcpyAsync(dts, m.dt, sizeof(dts), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    const double dv = (c.lx / c.nx) * (c.ly / c.ny) * (c.lz / c.nz);
+    const double eta = c.hbar_over_m;
+    std::memset(out, 0, sizeof(*out));
+    out->mass = res[0] * dv;
+    out->e_kin = 0.5 * eta * eta * res[1] * dv / double(n);
+    out->e_pot = 0.5 * res[2] * dv;
+    if (c.n_particles > 0) {
+        out->e_kin_particles = 0.5 * c.particle_mass * res[3];
+        for (int a = 0; a < 3; ++a) out->momentum[a] = c.particle_mass * res[4 + a];
+    }
+    out->e_total = out->e_kin + out->e_pot + out->e_kin_particles;
+    out->max_abs_phi = res[7];
+    out->t = dts[3];
+    out->dt = dts[0] != 0.0 ? dts[0] : dts[1];
+    out->dt_auto = dts[1];
+    const bool finite = std::isfinite(out->mass) && std::isfinite(out->e_total) &&
+                        std::isfinite(out->max_abs_phi);
+    if (!finite) return fail(WDM_EUNSTABLE, "non-finite state");
+    return WDM_OK;
+}
+
+wdm_status wdm_particles(wdm_plan* p, int32_t member, float* pos_out, float* vel_out) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    if (p->cfg[member].n_particles == 0) return WDM_OK;
+    HIPCHK(launch_particle_unsort(p->stream, p->host[p->dev_index[member]], pos_out, vel_out));
+    return WDM_OK;
+}
+
+wdm_status wdm_fft3d(wdm_plan* p, int32_t member, int32_t inverse) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const wdm_config& c = p->cfg[member];
+    const Launch L = one(p, member);
+    const bool inv = inverse != 0;
+    // forward: z, y, x; inverse: x, y, z
+    for (int k = 0; k < 3; ++k)
+        HIPCHK(launch_axis_fft(L, p->prec, c.nx, c.ny, c.nz, inv ? k : 2 - k, inv, 0));
+    if (inv)
+        HIPCHK(launch_scale_complex(p->stream, p->host[p->dev_index[member]].psi, cells_of(c),
+                                    1.0 / double(cells_of(c)), p->prec));
+    return WDM_OK;
+}
+
+wdm_status wdm_set_sort_interval(wdm_plan* p, int32_t interval) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    if (interval < 0) return fail(WDM_EINVAL, "interval must be >= 0");
+    p->sort_interval = interval;
+    return WDM_OK;
+}
+
+wdm_status wdm_profile(wdm_plan* p, int32_t enable) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    p->profiling = enable != 0;
+    return WDM_OK;
+}
+
+wdm_status wdm_profile_read(wdm_plan* p, wdm_kernel_stat* out, int32_t cap, int32_t* count) {
+    if (!p || !count) return fail(WDM_EINVAL, "null argument");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    std::vector<wdm_kernel_stat> agg(kKinds);
+    for (int k = 0; k < kKinds; ++k) {
+        std::memset(&agg[k], 0, sizeof(wdm_kernel_stat));
+        std::snprintf(agg[k].name, sizeof(agg[k].name), "%s", kKindNames[k]);
+    }
+    for (const Rec& r : p->recs) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        agg[r.kind].launches++;
+        agg[r.kind].total_ms += ms;
+    }
+    p->recs.clear();
+    p->pool_next = 0;
+    int32_t n = 0;
+    for (int k = 0; k < kKinds; ++k)
+        if (agg[k].launches > 0) {
+            if (out && n < cap) out[n] = agg[k];
+            ++n;
+        }
+    *count = n;
+    return WDM_OK;
+}
+
+wdm_status wdm_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps,
+                              void* hip_stream, double* ms_per_copy) {
+    if (!dst || !src || !ms_per_copy || reps <= 0 || bytes < 16)
+        return fail(WDM_EINVAL, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = int64_t(bytes / 16);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(launch_stream_copy(s, static_cast<float4*>(dst), static_cast<const float4*>(src), n));
+    HIPCHK(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r)
+        HIPCHK(launch_stream_copy(s, static_cast<float4*>(dst), static_cast<const float4*>(src), n));
+    HIPCHK(hipEventRecord(b, s));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    *ms_per_copy = double(ms) / reps;
+    return WDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,382 @@
+// Baryon particles coupled to the wave through the mesh (Sec. 3.2.2, dynamic
+// mode): the wave + baryon potential on the grid is differentiated by second
+// order central differences (Sec. 3.1) and interpolated to the particles with
+// cloud-in-cell weights; particles are kicked, drifted and deposited back onto
+// the grid with the same weights.
+//
+// The deposit sorts nothing per step: particles are kept ordered by cell (a
+// stable LSD radix sort, re-run periodically), so lanes of a wavefront mostly
+// share cells; each wavefront sums its contributions per run of equal cells and
+// one lane per run issues the eight atomic adds.
+#include "wdm_internal.hpp"
+
+namespace wdm {
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+template <typename T>
+struct CellW {
+    int i, j, k;          // base cell (index in [0, n))
+    T w[3][2];            // (1 - f, f) per axis
+};
+
+// s = x / dx, i = floor(s), f = s - i, formed in FP64 from the float position;
+// the weights are kept in the grid precision T.
+template <typename T>
+__device__ __forceinline__ CellW<T> cic(float x, float y, float z, const MemberDev& m) {
+    CellW<T> c;
+    const double s[3] = {double(x) * (double(m.nx) / m.lx), double(y) * (double(m.ny) / m.ly),
+                         double(z) * (double(m.nz) / m.lz)};
+    const int n[3] = {m.nx, m.ny, m.nz};
+    int ii[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double fl = floor(s[a]);
+        const T f = T(s[a] - fl);
+        ii[a] = wrapi(int(fl), n[a]);
+        c.w[a][0] = T(1) - f;
+        c.w[a][1] = f;
+    }
+    c.i = ii[0];
+    c.j = ii[1];
+    c.k = ii[2];
+    return c;
+}
+
+// g = -grad Phi (central differences at the 8 CIC nodes), interpolated.
+template <typename T>
+__device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const MemberDev& m,
+                                          const CellW<T>& c, float g[3]) {
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    int ix[4], iy[4], iz[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        ix[d] = wrapi(c.i + d - 1, nx);
+        iy[d] = wrapi(c.j + d - 1, ny);
+        iz[d] = wrapi(c.k + d - 1, nz);
+    }
+    auto P = [&](int a, int b, int d) -> T {
+        return phi[(int64_t(ix[a]) * ny + iy[b]) * nz + iz[d]];
+    };
+    const T hx = T(0.5) * T(m.nx / m.lx), hy = T(0.5) * T(m.ny / m.ly),
+            hz = T(0.5) * T(m.nz / m.lz);
+    T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const T w = T(c.w[0][a]) * T(c.w[1][b]) * T(c.w[2][d]);
+                // node (a+1, b+1, d+1) in the 4x4x4 neighbourhood
+                gx += w * (P(a, b + 1, d + 1) - P(a + 2, b + 1, d + 1)) * hx;
+                gy += w * (P(a + 1, b, d + 1) - P(a + 1, b + 2, d + 1)) * hy;
+                gz += w * (P(a + 1, b + 1, d) - P(a + 1, b + 1, d + 2)) * hz;
+            }
+    g[0] = float(gx);
+    g[1] = float(gy);
+    g[2] = float(gz);
+}
+
+__device__ __forceinline__ float wrap_pos(double x, double L) {
+    x -= L * floor(x / L);
+    float f = float(x);
+    if (f >= float(L) || f < 0.0f) f = 0.0f;
+    return f;
+}
+
+// Deposit q * w into `grid` at the 8 nodes of cell c.  All 64 lanes of the
+// wavefront must call this together; inactive lanes pass act = false.
+template <typename T>
+__device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberDev& m,
+                                             const CellW<T>& c, T q, bool act) {
+    const int lane = int(__lane_id());
+    const int64_t key = act ? (int64_t(c.i) * m.ny + c.j) * m.nz + c.k : -1 - lane;
+    T val[8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                val[a * 4 + b * 2 + d] = act ? q * c.w[0][a] * c.w[1][b] * c.w[2][d] : T(0);
+    // run heads: lanes whose key differs from the previous lane's
+    const int64_t prev = __shfl_up(key, 1);
+    const bool head = lane == 0 || prev != key;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const int seg = __popcll(heads & upto);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int oseg = __shfl_down(seg, off);
+        const bool take = (lane + off < 64) && (oseg == seg);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const T o = __shfl_down(val[v], off);
+            if (take) val[v] += o;
+        }
+    }
+    if (!(head && act)) return;
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    const int i1 = c.i + 1 == nx ? 0 : c.i + 1;
+    const int j1 = c.j + 1 == ny ? 0 : c.j + 1;
+    const int k1 = c.k + 1 == nz ? 0 : c.k + 1;
+    const int I[2] = {c.i, i1}, J[2] = {c.j, j1}, K[2] = {c.k, k1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                atomicAdd(&grid[(int64_t(I[a]) * ny + J[b]) * nz + K[d]],
+                          T(val[a * 4 + b * 2 + d]));
+}
+
+// mode 0: kick + drift + deposit into rho_b; 1: kick only; 2: deposit into
+// rho_b; 3: deposit into scratch (as a real grid).
+template <typename T>
+__global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__ mems, int first,
+                                                   int mode, int kick) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    if (int64_t(blockIdx.x) * 256 >= m.np) return;  // uniform per block
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool act = i < m.np;
+    const int64_t ii = act ? i : 0;
+    float x = m.px[ii], y = m.py[ii], z = m.pz[ii];
+    const double dt = m.dt[0];
+    if (mode <= 1) {
+        float vx = m.vx[ii], vy = m.vy[ii], vz = m.vz[ii];
+        const CellW<T> c = cic<T>(x, y, z, m);
+        float g[3];
+        cic_accel(static_cast<const T*>(m.phi), m, c, g);
+        const float tau = float(kick == kFullKick ? dt : 0.5 * dt);
+        vx += g[0] * tau;
+        vy += g[1] * tau;
+        vz += g[2] * tau;
+        if (mode == 0) {
+            x = wrap_pos(double(x) + double(vx) * dt, m.lx);
+            y = wrap_pos(double(y) + double(vy) * dt, m.ly);
+            z = wrap_pos(double(z) + double(vz) * dt, m.lz);
+            if (act) {
+                m.px[i] = x;
+                m.py[i] = y;
+                m.pz[i] = z;
+            }
+        }
+        if (act) {
+            m.vx[i] = vx;
+            m.vy[i] = vy;
+            m.vz[i] = vz;
+        }
+        if (mode == 1) return;
+    }
+    const double dv = (m.lx / m.nx) * (m.ly / m.ny) * (m.lz / m.nz);
+    const T q = T(m.particle_mass / dv);
+    const CellW<T> c = cic<T>(x, y, z, m);
+    T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
+    deposit_wave(grid, m, c, q, act);
+}
+
+hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
+                            KickMode kick) {
+    if (max_np <= 0) return hipSuccess;
+    dim3 grid(unsigned((max_np + 255) / 256), unsigned(L.count));
+    if (prec)
+        k_particles<double><<<grid, 256, 0, L.stream>>>(L.members, L.first, mode, int(kick));
+    else
+        k_particles<float><<<grid, 256, 0, L.stream>>>(L.members, L.first, mode, int(kick));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// upload / download (AoS [Np][3] <-> SoA, original order via id)
+// ---------------------------------------------------------------------------
+__global__ void k_upload(MemberDev m, const float* __restrict__ pos, const float* __restrict__ vel) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m.np) return;
+    m.px[i] = wrap_pos(double(pos[3 * i + 0]), m.lx);
+    m.py[i] = wrap_pos(double(pos[3 * i + 1]), m.ly);
+    m.pz[i] = wrap_pos(double(pos[3 * i + 2]), m.lz);
+    m.vx[i] = vel[3 * i + 0];
+    m.vy[i] = vel[3 * i + 1];
+    m.vz[i] = vel[3 * i + 2];
+    m.id[i] = int32_t(i);
+}
+
+__global__ void k_unsort(MemberDev m, float* __restrict__ pos, float* __restrict__ vel) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m.np) return;
+    const int64_t o = m.id[i];
+    if (pos) {
+        pos[3 * o + 0] = m.px[i];
+        pos[3 * o + 1] = m.py[i];
+        pos[3 * o + 2] = m.pz[i];
+    }
+    if (vel) {
+        vel[3 * o + 0] = m.vx[i];
+        vel[3 * o + 1] = m.vy[i];
+        vel[3 * o + 2] = m.vz[i];
+    }
+}
+
+hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float* pos,
+                                  const float* vel) {
+    if (m.np <= 0) return hipSuccess;
+    k_upload<<<unsigned((m.np + 255) / 256), 256, 0, s>>>(m, pos, vel);
+    return hipGetLastError();
+}
+
+hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos, float* vel) {
+    if (m.np <= 0) return hipSuccess;
+    k_unsort<<<unsigned((m.np + 255) / 256), 256, 0, s>>>(m, pos, vel);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of the particles by cell index (8-bit digits)
+// ---------------------------------------------------------------------------
+constexpr int kSortTile = 4096;   // keys per block: 256 lanes x 16 rounds
+
+__global__ void k_make_keys(MemberDev m) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m.np) return;
+    const CellW<float> c = cic<float>(m.px[i], m.py[i], m.pz[i], m);
+    m.key_a[i] = uint32_t((int64_t(c.i) * m.ny + c.j) * m.nz + c.k);
+    m.idx_a[i] = uint32_t(i);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                    int shift, uint32_t* __restrict__ hist,
+                                                    int nblocks) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortTile / 256; ++r) {
+        const int64_t i = b0 + r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of n counters in one block of 1024 lanes.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int64_t n) {
+    __shared__ uint32_t s[1024];
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t b = int64_t(threadIdx.x) * chunk;
+    const int64_t e = b + chunk < n ? b + chunk : n;
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += a[i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = int(threadIdx.x) >= off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin,
+                                                       uint32_t* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout, int64_t n,
+                                                       int shift,
+                                                       const uint32_t* __restrict__ hist,
+                                                       int nblocks) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    base[tid] = hist[int64_t(tid) * nblocks + blockIdx.x];
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortTile / 256; ++r) {
+        const int64_t i = b0 + r * 256 + tid;
+        const bool valid = i < n;
+        const uint32_t k = valid ? kin[i] : 0u;
+        const uint32_t d = (k >> shift) & 255u;
+        unsigned long long mask = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const unsigned long long bb = __ballot(on);
+            mask &= on ? bb : ~bb;
+        }
+        const int rank = __popcll(mask & lt);
+        if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(mask));
+        __syncthreads();
+        if (valid) {
+            uint32_t off = base[d] + uint32_t(rank);
+            for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+            kout[off] = k;
+            vout[off] = vin[i];
+        }
+        __syncthreads();
+        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+    }
+}
+
+__global__ void k_gather_sorted(MemberDev m, const uint32_t* __restrict__ idx) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m.np) return;
+    const uint32_t s = idx[i];
+    m.apx[i] = m.px[s];
+    m.apy[i] = m.py[s];
+    m.apz[i] = m.pz[s];
+    m.avx[i] = m.vx[s];
+    m.avy[i] = m.vy[s];
+    m.avz[i] = m.vz[s];
+    m.aid[i] = m.id[s];
+}
+
+__global__ void k_copy_back(MemberDev m) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m.np) return;
+    m.px[i] = m.apx[i];
+    m.py[i] = m.apy[i];
+    m.pz[i] = m.apz[i];
+    m.vx[i] = m.avx[i];
+    m.vy[i] = m.avy[i];
+    m.vz[i] = m.avz[i];
+    m.id[i] = m.aid[i];
+}
+
+int sort_blocks(int64_t np) { return int((np + kSortTile - 1) / kSortTile); }
+
+hipError_t launch_particle_sort(hipStream_t s, const MemberDev& m, const MemberDev* /*dev*/,
+                                int /*prec*/) {
+    if (m.np <= 1) return hipSuccess;
+    const unsigned g = unsigned((m.np + 255) / 256);
+    k_make_keys<<<g, 256, 0, s>>>(m);
+    const int64_t ncells = int64_t(m.nx) * m.ny * m.nz;
+    int bits = 0;
+    while ((int64_t(1) << bits) < ncells) ++bits;
+    const int nb = sort_blocks(m.np);
+    uint32_t *ka = m.key_a, *kb = m.key_b, *va = m.idx_a, *vb = m.idx_b;
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_radix_hist<<<nb, 256, 0, s>>>(ka, m.np, shift, m.hist, nb);
+        k_scan_u32<<<1, 1024, 0, s>>>(m.hist, int64_t(nb) * 256);
+        k_radix_scatter<<<nb, 256, 0, s>>>(ka, va, kb, vb, m.np, shift, m.hist, nb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    k_gather_sorted<<<g, 256, 0, s>>>(m, va);
+    k_copy_back<<<g, 256, 0, s>>>(m);
+    return hipGetLastError();
+}
+
+}  // namespace wdm

@@ -1,0 +1,293 @@
+// FP64 global reductions (mass, potential energy, particle kinetic energy and
+// momentum, max |Phi|), the CFL time step of Sec. 3.5, and small utility
+// kernels.  Reductions are deterministic: a fixed number of work-groups, each
+// summing a fixed range in a fixed order, then one work-group summing the
+// partials in order -- no floating-point atomics.
+#include "fft_device.hpp"
+#include "wdm_internal.hpp"
+
+namespace wdm {
+
+constexpr int kRedThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// what 0: sum |psi|^2 -> field 0, max |Phi| -> field 7
+// what 1: sum (|psi|^2 + scratch) Phi -> field 2 (scratch holds CIC rho_b)
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __restrict__ mems,
+                                                             int first, int64_t n, int what) {
+    __shared__ double red[kRedThreads];
+    const MemberDev& m = mems[first];
+    const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+    const int64_t b = int64_t(blockIdx.x) * chunk;
+    const int64_t e = b + chunk < n ? b + chunk : n;
+    const cplx<T>* psi = static_cast<const cplx<T>*>(m.psi);
+    const T* phi = static_cast<const T*>(m.phi);
+    const T* rb = static_cast<const T*>(m.scratch);
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = b + threadIdx.x; i < e; i += kRedThreads) {
+        const double re = double(psi[i].re), im = double(psi[i].im);
+        const double rho = re * re + im * im;
+        if (what == 0) {
+            s0 += rho;
+            s1 = fmax(s1, fabs(double(phi[i])));
+        } else {
+            s0 += (rho + double(rb[i])) * double(phi[i]);
+        }
+    }
+    const double t0 = block_sum<T>(s0, red);
+    if (what == 0) {
+        const double t1 = block_max(s1, red);
+        if (threadIdx.x == 0) {
+            m.partials[int64_t(blockIdx.x) * kRedFields + 0] = t0;
+            m.partials[int64_t(blockIdx.x) * kRedFields + 7] = t1;
+        }
+    } else if (threadIdx.x == 0) {
+        m.partials[int64_t(blockIdx.x) * kRedFields + 2] = t0;
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_particles(
+    const MemberDev* __restrict__ mems, int first) {
+    __shared__ double red[kRedThreads];
+    const MemberDev& m = mems[first];
+    const int64_t n = m.np;
+    const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+    const int64_t b = int64_t(blockIdx.x) * chunk;
+    const int64_t e = b + chunk < n ? b + chunk : n;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = b + threadIdx.x; i < e; i += kRedThreads) {
+        const double vx = m.vx[i], vy = m.vy[i], vz = m.vz[i];
+        s[0] += vx * vx + vy * vy + vz * vz;
+        s[1] += vx;
+        s[2] += vy;
+        s[3] += vz;
+    }
+    for (int f = 0; f < 4; ++f) {
+        const double t = block_sum<float>(s[f], red);
+        if (threadIdx.x == 0) m.partials[int64_t(blockIdx.x) * kRedFields + 3 + f] = t;
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_finish(const MemberDev* __restrict__ mems,
+                                                               int first, int field, int nblocks,
+                                                               int is_max) {
+    __shared__ double red[kRedThreads];
+    const MemberDev& m = mems[first];
+    double s = 0.0;
+    for (int i = int(threadIdx.x); i < nblocks; i += kRedThreads) {
+        const double v = m.partials[int64_t(i) * kRedFields + field];
+        s = is_max ? fmax(s, v) : s + v;
+    }
+    const double t = is_max ? block_max(s, red) : block_sum<float>(s, red);
+    if (threadIdx.x == 0) m.results[field] = t;
+}
+
+hipError_t launch_reduce_grid(const Launch& L, int prec, int64_t ncells, int what) {
+    if (prec)
+        k_reduce_grid<double><<<kRedBlocks, kRedThreads, 0, L.stream>>>(L.members, L.first, ncells,
+                                                                        what);
+    else
+        k_reduce_grid<float><<<kRedBlocks, kRedThreads, 0, L.stream>>>(L.members, L.first, ncells,
+                                                                       what);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_particles(const Launch& L, int64_t /*max_np*/) {
+    k_reduce_particles<<<kRedBlocks, kRedThreads, 0, L.stream>>>(L.members, L.first);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_finish(const Launch& L, int field, int nblocks, bool is_max) {
+    k_reduce_finish<<<1, kRedThreads, 0, L.stream>>>(L.members, L.first, field, nblocks,
+                                                     is_max ? 1 : 0);
+    return hipGetLastError();
+}
+
+// dt = zeta * 0.5 * min{c_kin dx_min^2 / eta, 2 pi eta / max|Phi|}; needs
+// results[7] = max |Phi|.  Stored as dt_auto and, unless a per-member dt was
+// set, as the dt in use.
+__global__ void k_dt_auto(const MemberDev* __restrict__ mems, int first, double zeta,
+                          double c_kin) {
+    const MemberDev& m = mems[first + blockIdx.x];
+    const double dx = fmin(m.lx / m.nx, fmin(m.ly / m.ny, m.lz / m.nz));
+    double t = c_kin * dx * dx / m.eta;
+    const double mp = m.results[7];
+    if (mp > 0.0) t = fmin(t, kTwoPi * m.eta / mp);
+    m.dt[1] = zeta * 0.5 * t;
+}
+
+hipError_t launch_dt_auto(const Launch& L, double zeta, double c_kin) {
+    k_dt_auto<<<unsigned(L.count), 1, 0, L.stream>>>(L.members, L.first, zeta, c_kin);
+    return hipGetLastError();
+}
+
+// mode 0: dt in use = dt; 1: dt in use = user dt if set else dt_auto;
+// 2: user dt = dt; 3: time = dt
+__global__ void k_set_dt(const MemberDev* __restrict__ mems, int first, double dt, int mode) {
+    const MemberDev& m = mems[first + blockIdx.x];
+    if (mode == 0)
+        m.dt[0] = dt;
+    else if (mode == 1)
+        m.dt[0] = m.dt[2] != 0.0 ? m.dt[2] : m.dt[1];
+    else if (mode == 2)
+        m.dt[2] = dt;
+    else
+        m.dt[3] = dt;
+}
+
+hipError_t launch_set_dt(const Launch& L, double dt, int mode) {
+    k_set_dt<<<unsigned(L.count), 1, 0, L.stream>>>(L.members, L.first, dt, mode);
+    return hipGetLastError();
+}
+
+__global__ void k_advance_time(const MemberDev* __restrict__ mems, int first, int64_t n) {
+    const MemberDev& m = mems[first + blockIdx.x];
+    m.dt[3] += double(n) * m.dt[0];
+}
+
+hipError_t launch_advance_time(const Launch& L, int64_t nsteps) {
+    k_advance_time<<<unsigned(L.count), 1, 0, L.stream>>>(L.members, L.first, nsteps);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < words;
+         i += int64_t(gridDim.x) * 256)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero(hipStream_t s, void* p, size_t bytes) {
+    const int64_t words = int64_t(bytes / 4);
+    if (words == 0) return hipSuccess;
+    int64_t g = (words + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_zero<<<unsigned(g), 256, 0, s>>>(static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
+template <typename D, typename S>
+__global__ void k_copy_cplx(cplx<D>* __restrict__ dst, const cplx<S>* __restrict__ src, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        dst[i] = cplx<D>{D(src[i].re), D(src[i].im)};
+}
+
+hipError_t launch_copy_complex(hipStream_t s, void* dst, const void* src, int64_t n, int dp,
+                               int sp) {
+    int64_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (dp && sp)
+        k_copy_cplx<double, double><<<unsigned(g), 256, 0, s>>>(
+            static_cast<cplx<double>*>(dst), static_cast<const cplx<double>*>(src), n);
+    else if (dp)
+        k_copy_cplx<double, float><<<unsigned(g), 256, 0, s>>>(
+            static_cast<cplx<double>*>(dst), static_cast<const cplx<float>*>(src), n);
+    else if (sp)
+        k_copy_cplx<float, double><<<unsigned(g), 256, 0, s>>>(
+            static_cast<cplx<float>*>(dst), static_cast<const cplx<double>*>(src), n);
+    else
+        k_copy_cplx<float, float><<<unsigned(g), 256, 0, s>>>(
+            static_cast<cplx<float>*>(dst), static_cast<const cplx<float>*>(src), n);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_copy_real(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_real(hipStream_t s, void* dst, const void* src, int64_t n, int prec) {
+    int64_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (prec)
+        k_copy_real<double><<<unsigned(g), 256, 0, s>>>(static_cast<double*>(dst),
+                                                       static_cast<const double*>(src), n);
+    else
+        k_copy_real<float><<<unsigned(g), 256, 0, s>>>(static_cast<float*>(dst),
+                                                      static_cast<const float*>(src), n);
+    return hipGetLastError();
+}
+
+// rho = |psi|^2 (+ CIC baryon density held in scratch)
+template <typename T>
+__global__ void k_density_out(const MemberDev* __restrict__ mems, int first, int64_t n,
+                              T* __restrict__ out, int inc) {
+    const MemberDev& m = mems[first];
+    const cplx<T>* psi = static_cast<const cplx<T>*>(m.psi);
+    const T* rb = static_cast<const T*>(m.scratch);
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        T r = psi[i].re * psi[i].re + psi[i].im * psi[i].im;
+        if (inc) r += rb[i];
+        out[i] = r;
+    }
+}
+
+hipError_t launch_density_out(const Launch& L, int prec, int64_t n, void* out, int inc) {
+    int64_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (prec)
+        k_density_out<double><<<unsigned(g), 256, 0, L.stream>>>(L.members, L.first, n,
+                                                                static_cast<double*>(out), inc);
+    else
+        k_density_out<float><<<unsigned(g), 256, 0, L.stream>>>(L.members, L.first, n,
+                                                               static_cast<float*>(out), inc);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_scale_cplx(cplx<T>* __restrict__ p, int64_t n, T s) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        p[i] = cscale(p[i], s);
+}
+
+hipError_t launch_scale_complex(hipStream_t s, void* p, int64_t n, double scale, int prec) {
+    int64_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (prec)
+        k_scale_cplx<double><<<unsigned(g), 256, 0, s>>>(static_cast<cplx<double>*>(p), n, scale);
+    else
+        k_scale_cplx<float><<<unsigned(g), 256, 0, s>>>(static_cast<cplx<float>*>(p), n,
+                                                        float(scale));
+    return hipGetLastError();
+}
+
+// Plain streaming copy: the achievable-bandwidth reference for the roofline.
+__global__ __launch_bounds__(256) void k_stream_copy(float4* __restrict__ dst,
+                                                     const float4* __restrict__ src, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        dst[i] = src[i];
+}
+
+hipError_t launch_stream_copy(hipStream_t s, float4* dst, const float4* src, int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    k_stream_copy<<<unsigned(g), 256, 0, s>>>(dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace wdm

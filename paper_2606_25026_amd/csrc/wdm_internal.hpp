@@ -1,0 +1,112 @@
+// Internal declarations shared by the HIP translation units of libwdm.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace wdm {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kTwoPi = 2.0 * kPi;
+
+// Per-member device descriptor (one halo / box).  Lives in device memory so
+// that a single launch can serve a whole size class of an ensemble.
+struct MemberDev {
+    // grids (C order [nx][ny][nz], z contiguous)
+    void* psi;        // complex, n cells
+    void* phi;        // real potential, n cells
+    void* rho_b;      // real baryon density accumulator, n cells (zero between steps)
+    void* spec;       // complex half spectrum [nx][ny][nz/2] (kz = 0 .. nz/2-1)
+    void* spec_nyq;   // complex Nyquist plane [nx][ny] (kz = nz/2)
+    void* scratch;    // complex, n cells (diagnostics only)
+    const void* tw_x;  // W_nx^m, m in [0, nx) (complex, plan precision)
+    const void* tw_y;
+    const void* tw_z;
+    int32_t nx, ny, nz, pad0;
+    double lx, ly, lz;
+    double eta;        // hbar / m
+    double four_pi_G;
+    double dt_ref_unused;
+    // time-step slots (device doubles): [0] dt in use, [1] dt_auto, [2] dt set by user,
+    // [3] current time
+    double* dt;
+    // particles: structure of arrays, sorted by cell between re-sorts
+    int64_t np;
+    float *px, *py, *pz, *vx, *vy, *vz;
+    int32_t* id;       // original index of each slot
+    float *apx, *apy, *apz, *avx, *avy, *avz;  // sort staging
+    int32_t* aid;
+    uint32_t *key_a, *key_b, *idx_a, *idx_b, *hist;
+    double particle_mass;
+    // FP64 reduction staging
+    double* partials;  // [kMaxPartials][kRedFields]
+    double* results;   // [kRedFields]
+};
+
+constexpr int kRedFields = 8;
+constexpr int kRedBlocks = 1024;
+
+// Launch context shared by all launchers.
+struct Launch {
+    hipStream_t stream;
+    const MemberDev* members;   // device table
+    int first;                  // first member index of the size class
+    int count;                  // members in the class
+};
+
+enum KickMode : int { kHalfKick = 0, kFullKick = 1 };
+enum ZOp : int { kZKickFft = 0, kZKickOnly = 1, kZPhiOnly = 2 };
+enum DensOp : int { kDensInvFft = 0, kDensDirect = 1 };
+
+// ---- FFT passes (passes.hip); `prec` is 0 for complex64, 1 for complex128 ----
+bool axis_supported(int n);
+// P1: half spectrum -> Phi (C2R along z), then kick and optionally z-FFT.
+hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, int nz, ZOp op,
+                                   KickMode kick);
+// P2 / P4 on psi, P6 / P8 on the half spectrum (+ Nyquist plane).
+hipError_t launch_y_fft_psi(const Launch& L, int prec, int nx, int ny, int nz, bool inverse);
+hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, bool inverse);
+// P3: x forward, kinetic phase exp(-i eta |k|^2 dt/2)/N, x inverse.
+hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz);
+// P5: z inverse of psi (optional), rho = |psi|^2 + rho_b (rho_b cleared), R2C along z.
+hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op);
+// P7: x forward, Green's function -4 pi G / |k|^2 / N, x inverse (+ Nyquist plane).
+hipError_t launch_x_green(const Launch& L, int prec, int nx, int ny, int nz);
+// Plain 3D transforms between psi-shaped buffers: axis 0 = x, 1 = y, 2 = z.
+// `which` selects the member field: 0 = psi, 1 = scratch.
+hipError_t launch_axis_fft(const Launch& L, int prec, int nx, int ny, int nz, int axis,
+                           bool inverse, int which);
+// FP64 spectral kinetic-energy partials from scratch holding F_z F_y psi.
+hipError_t launch_x_kinetic_energy(const Launch& L, int prec, int nx, int ny, int nz);
+
+// ---- particles (particles.hip) ----
+// mode 0: kick (tau) + drift (dt) + deposit; 1: kick only; 2: deposit only
+// into rho_b; 3: deposit only into scratch (as real grid).
+hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
+                            KickMode kick);
+hipError_t launch_particle_sort(hipStream_t s, const MemberDev& host_copy,
+                                const MemberDev* dev, int prec);
+hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos_out,
+                                  float* vel_out);
+hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float* pos,
+                                  const float* vel);
+
+// ---- reductions and small kernels (reduce.hip) ----
+// fields of `results`: 0 mass, 1 e_kin, 2 sum rho Phi, 3 sum v^2, 4..6 sum v,
+// 7 max |Phi|
+hipError_t launch_reduce_grid(const Launch& L, int prec, int64_t ncells, int what);
+hipError_t launch_reduce_finish(const Launch& L, int field, int nblocks, bool is_max);
+hipError_t launch_reduce_particles(const Launch& L, int64_t max_np);
+hipError_t launch_dt_auto(const Launch& L, double zeta, double c_kin);
+hipError_t launch_set_dt(const Launch& L, double dt, int mode);
+hipError_t launch_advance_time(const Launch& L, int64_t nsteps);
+hipError_t launch_zero(hipStream_t s, void* p, size_t bytes);
+hipError_t launch_copy_complex(hipStream_t s, void* dst, const void* src, int64_t n,
+                               int dst_prec, int src_prec);
+hipError_t launch_density_out(const Launch& L, int prec, int64_t ncells, void* out,
+                              int include_baryons);
+hipError_t launch_copy_real(hipStream_t s, void* dst, const void* src, int64_t n, int prec);
+hipError_t launch_stream_copy(hipStream_t s, float4* dst, const float4* src, int64_t n);
+
+}  // namespace wdm

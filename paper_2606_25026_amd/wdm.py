@@ -1,0 +1,235 @@
+"""ctypes binding of libwdm (include/wdm.h): argument marshalling only.
+
+Every function has the name of the C entry point it wraps, takes torch
+tensors (or raw integer device pointers) where the C call takes device
+pointers, raises :class:`WdmError` with ``wdm_last_error()`` on a non-zero
+status, and does no arithmetic of its own.  The shared library must have been
+built in-tree (``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+LIB_PATH = Path(__file__).resolve().parent / "libwdm.so"
+
+WDM_C64, WDM_C128 = 0, 1
+STATUS = {0: "WDM_OK", 1: "WDM_EINVAL", 2: "WDM_ENOMEM", 3: "WDM_EDEVICE", 4: "WDM_ESTATE",
+          5: "WDM_EUNSTABLE", 6: "WDM_EUNSUPPORTED"}
+
+
+class WdmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class wdm_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("hbar_over_m", C.c_double), ("four_pi_G", C.c_double),
+                ("n_particles", C.c_int64), ("particle_mass", C.c_double),
+                ("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+class wdm_energy_t(C.Structure):
+    _fields_ = [("mass", C.c_double), ("e_kin", C.c_double), ("e_pot", C.c_double),
+                ("e_kin_particles", C.c_double), ("e_total", C.c_double),
+                ("momentum", C.c_double * 3), ("max_abs_phi", C.c_double), ("t", C.c_double),
+                ("dt", C.c_double), ("dt_auto", C.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "momentum"}
+        d["momentum"] = list(self.momentum)
+        return d
+
+
+class wdm_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+_lib = None
+_vp, _i32, _i64, _f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_SIGS = {
+    "wdm_workspace_bytes": (C.c_size_t, [C.POINTER(wdm_config), _i32]),
+    "wdm_plan_create": (C.c_int, [C.POINTER(wdm_config), _i32, _vp, C.c_size_t, _vp,
+                                  C.POINTER(_vp)]),
+    "wdm_plan_destroy": (C.c_int, [_vp]),
+    "wdm_set_state": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _f64]),
+    "wdm_set_member_dt": (C.c_int, [_vp, _i32, _f64]),
+    "wdm_step": (C.c_int, [_vp, _i64, _f64]),
+    "wdm_get_psi": (C.c_int, [_vp, _i32, _vp]),
+    "wdm_density": (C.c_int, [_vp, _i32, _vp, _i32]),
+    "wdm_potential": (C.c_int, [_vp, _i32, _vp]),
+    "wdm_energy": (C.c_int, [_vp, _i32, C.POINTER(wdm_energy_t)]),
+    "wdm_particles": (C.c_int, [_vp, _i32, _vp, _vp]),
+    "wdm_fft3d": (C.c_int, [_vp, _i32, _i32]),
+    "wdm_set_sort_interval": (C.c_int, [_vp, _i32]),
+    "wdm_profile": (C.c_int, [_vp, _i32]),
+    "wdm_profile_read": (C.c_int, [_vp, C.POINTER(wdm_kernel_stat), _i32, C.POINTER(_i32)]),
+    "wdm_copy_bandwidth": (C.c_int, [_vp, _vp, C.c_size_t, _i32, _vp, C.POINTER(_f64)]),
+    "wdm_last_error": (C.c_char_p, []),
+}
+
+
+def load():
+    """Load libwdm.so; raises if the HIP build is missing."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = C.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _check(status: int):
+    if status != 0:
+        raise WdmError(status, load().wdm_last_error().decode())
+
+
+def _cfg_array(configs):
+    if isinstance(configs, wdm_config):
+        configs = [configs]
+    arr = (wdm_config * len(configs))(*configs)
+    return arr, len(configs)
+
+
+def make_config(n, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0, particle_mass=0.0,
+                precision=WDM_C64) -> wdm_config:
+    nx, ny, nz = (n, n, n) if isinstance(n, int) else n
+    lx, ly, lz = (L, L, L) if isinstance(L, (int, float)) else L
+    return wdm_config(nx, ny, nz, lx, ly, lz, hbar_over_m, four_pi_G, int(n_particles),
+                      float(particle_mass), precision, 0)
+
+
+# ---- entry points --------------------------------------------------------
+def wdm_last_error() -> str:
+    return load().wdm_last_error().decode()
+
+
+def wdm_workspace_bytes(configs) -> int:
+    arr, n = _cfg_array(configs)
+    return int(load().wdm_workspace_bytes(arr, n))
+
+
+def wdm_plan_create(configs, workspace, workspace_bytes=None, stream=None):
+    arr, n = _cfg_array(configs)
+    out = C.c_void_p()
+    nbytes = workspace_bytes if workspace_bytes is not None else workspace.numel() * workspace.element_size()
+    _check(load().wdm_plan_create(arr, n, _ptr(workspace), nbytes, _stream(stream), C.byref(out)))
+    return out
+
+
+def wdm_plan_destroy(plan):
+    _check(load().wdm_plan_destroy(plan))
+
+
+def wdm_set_state(plan, member, psi, pos=None, vel=None, t0=0.0):
+    _check(load().wdm_set_state(plan, member, _ptr(psi), _ptr(pos), _ptr(vel), float(t0)))
+
+
+def wdm_set_member_dt(plan, member, dt):
+    _check(load().wdm_set_member_dt(plan, member, float(dt)))
+
+
+def wdm_step(plan, n, dt=0.0):
+    _check(load().wdm_step(plan, int(n), float(dt)))
+
+
+def wdm_get_psi(plan, member, psi_out):
+    _check(load().wdm_get_psi(plan, member, _ptr(psi_out)))
+
+
+def wdm_density(plan, member, rho_out, include_baryons=True):
+    _check(load().wdm_density(plan, member, _ptr(rho_out), 1 if include_baryons else 0))
+
+
+def wdm_potential(plan, member, phi_out):
+    _check(load().wdm_potential(plan, member, _ptr(phi_out)))
+
+
+def wdm_energy(plan, member=0) -> dict:
+    e = wdm_energy_t()
+    _check(load().wdm_energy(plan, member, C.byref(e)))
+    return e.as_dict()
+
+
+def wdm_particles(plan, member, pos_out=None, vel_out=None):
+    _check(load().wdm_particles(plan, member, _ptr(pos_out), _ptr(vel_out)))
+
+
+def wdm_fft3d(plan, member, inverse=False):
+    _check(load().wdm_fft3d(plan, member, 1 if inverse else 0))
+
+
+def wdm_set_sort_interval(plan, interval):
+    _check(load().wdm_set_sort_interval(plan, int(interval)))
+
+
+def wdm_profile(plan, enable=True):
+    _check(load().wdm_profile(plan, 1 if enable else 0))
+
+
+def wdm_profile_read(plan, cap=32) -> list:
+    buf = (wdm_kernel_stat * cap)()
+    cnt = C.c_int32()
+    _check(load().wdm_profile_read(plan, buf, cap, C.byref(cnt)))
+    return [{"name": buf[i].name.decode(), "launches": buf[i].launches,
+             "total_ms": buf[i].total_ms} for i in range(min(cnt.value, cap))]
+
+
+def wdm_copy_bandwidth(dst, src, nbytes, reps=20, stream=None) -> float:
+    ms = C.c_double()
+    _check(load().wdm_copy_bandwidth(_ptr(dst), _ptr(src), int(nbytes), int(reps),
+                                     _stream(stream), C.byref(ms)))
+    return ms.value
+
+
+class Plan:
+    """Owns a torch workspace and a plan handle (marshalling convenience)."""
+
+    def __init__(self, configs, device="cuda"):
+        import torch
+
+        self.configs = [configs] if isinstance(configs, wdm_config) else list(configs)
+        nbytes = wdm_workspace_bytes(self.configs)
+        if nbytes == 0:
+            raise WdmError(1, wdm_last_error())
+        # 256-byte alignment is guaranteed by the caching allocator
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = wdm_plan_create(self.configs, self.workspace, nbytes)
+
+    def close(self):
+        if self.handle is not None:
+            wdm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,65 @@
+"""Full-size parity: the 256^3 + 1e6-particle coupled halo, in the launch
+configuration the benchmark times, against sampled FP64-oracle values written
+by tests/golden/make_coupled_halo_reference.py (65536 cells, 10000 particles).
+"""
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_2606_25026_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = Path(__file__).resolve().parent / "golden" / "coupled_halo_256_steps100.npz"
+
+
+def periodic_diff(a, b, L=1.0):
+    d = a - b
+    return d - L * np.round(d / L)
+
+
+@pytest.fixture(scope="module")
+def halo():
+    return inputs.coupled_halo(n=256, n_particles=1_000_000, seed=0)
+
+
+@pytest.mark.parametrize("sort_interval", [32])
+def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval):
+    g = np.load(GOLDEN)
+    wl = halo
+    # the generator must reproduce the stored initial samples
+    assert np.max(np.abs(wl.psi.ravel()[g["cells"]] - g["psi0"])) < 1e-12
+    steps = int(g["steps"])
+    cfg = wdm.make_config(256, n_particles=wl.n_particles, particle_mass=wl.particle_mass)
+    plan = wdm.Plan(cfg)
+    psi = torch.from_numpy(wl.psi.astype(np.complex64)).cuda()
+    pos = torch.from_numpy(wl.pos).cuda()
+    vel = torch.from_numpy(wl.vel).cuda()
+    wdm.wdm_set_state(plan.handle, 0, psi, pos, vel)
+    wdm.wdm_set_sort_interval(plan.handle, sort_interval)
+    e0 = wdm.wdm_energy(plan.handle, 0)
+    wdm.wdm_step(plan.handle, steps, float(g["dt"]))
+    out = torch.empty_like(psi)
+    wdm.wdm_get_psi(plan.handle, 0, out)
+    p = torch.empty_like(pos)
+    v = torch.empty_like(vel)
+    wdm.wdm_particles(plan.handle, 0, p, v)
+    e1 = wdm.wdm_energy(plan.handle, 0)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().ravel()[g["cells"]].astype(np.complex128)
+    ref = g["psi"]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    pp = p.cpu().numpy()[g["parts"]].astype(np.float64)
+    vv = v.cpu().numpy()[g["parts"]].astype(np.float64)
+    perr = float(np.max(np.abs(periodic_diff(pp, g["pos"]))))
+    verr = float(np.linalg.norm(vv - g["vel"]) / np.linalg.norm(g["vel"]))
+    print(f"256^3 + 1e6 particles, {steps} steps: psi rel L2 (65536 samples) {err:.3e}, "
+          f"max |dx| {perr:.2e}, vel rel L2 {verr:.2e}, mass drift {e1['mass'] / e0['mass'] - 1:.2e}")
+    assert err < 1e-5
+    assert perr < 1e-5
+    assert verr < 1e-4
+    assert abs(e1["mass"] / e0["mass"] - 1) < 1e-6
+    assert e1["mass"] == pytest.approx(float(g["mass"]), rel=1e-6)
+    plan.close()

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: complex64 paths are held to a relative L2 error of 1e-5 on psi
+after 100 KDK steps (the target the method's single-precision path must meet);
+single transforms and potentials, which see one rounding chain, to 1e-6 / 1e-5;
+complex128 paths to 1e-11.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_25026_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TWO_PI = 2 * math.pi
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def check_l2(a, b, tol):
+    err = rel_l2(a, b)
+    assert err < tol, f"relative L2 error {err:.3e} >= {tol:.1e}"
+    return err
+
+
+def cdt(prec):
+    return torch.complex64 if prec == 0 else torch.complex128
+
+
+def rdt(prec):
+    return torch.float32 if prec == 0 else torch.float64
+
+
+class Run:
+    """A single-member plan fed from numpy arrays."""
+
+    def __init__(self, wdm, psi, L=1.0, pos=None, vel=None, mp=0.0, four_pi_G=1.0, eta=1.0,
+                 prec=0):
+        self.wdm = wdm
+        self.prec = prec
+        self.shape = psi.shape
+        npart = 0 if pos is None else pos.shape[0]
+        self.cfg = wdm.make_config(psi.shape, L=L, hbar_over_m=eta, four_pi_G=four_pi_G,
+                                   n_particles=npart, particle_mass=mp, precision=prec)
+        self.plan = wdm.Plan(self.cfg)
+        self.psi = torch.from_numpy(psi).to(cdt(prec)).cuda()
+        self.pos = torch.from_numpy(np.ascontiguousarray(pos, np.float32)).cuda() if npart else None
+        self.vel = torch.from_numpy(np.ascontiguousarray(vel, np.float32)).cuda() if npart else None
+        wdm.wdm_set_state(self.plan.handle, 0, self.psi, self.pos, self.vel)
+
+    def step(self, n, dt):
+        self.wdm.wdm_step(self.plan.handle, n, dt)
+
+    def get_psi(self):
+        out = torch.empty(self.shape, dtype=cdt(self.prec), device="cuda")
+        self.wdm.wdm_get_psi(self.plan.handle, 0, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.complex128)
+
+    def get_phi(self):
+        out = torch.empty(self.shape, dtype=rdt(self.prec), device="cuda")
+        self.wdm.wdm_potential(self.plan.handle, 0, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+    def get_density(self, baryons=True):
+        out = torch.empty(self.shape, dtype=rdt(self.prec), device="cuda")
+        self.wdm.wdm_density(self.plan.handle, 0, out, baryons)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+    def get_particles(self):
+        n = self.pos.shape[0]
+        p = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        v = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        self.wdm.wdm_particles(self.plan.handle, 0, p, v)
+        torch.cuda.synchronize()
+        return p.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+
+    def close(self):
+        self.plan.close()
+
+
+def periodic_diff(a, b, L=1.0):
+    d = a - b
+    return d - L * np.round(d / L)
+
+
+# ------------------------------------------------------------------- FFT
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (16, 64, 96), (96, 32, 128), (64, 192, 16),
+                                   (256, 256, 256)])
+def test_fft3d_matches_oracle(wdm, orc, shape, prec):
+    rng = np.random.default_rng(sum(shape) + prec)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    r = Run(wdm, x, prec=prec, four_pi_G=0.0)
+    wdm.wdm_fft3d(r.plan.handle, 0, inverse=False)
+    got = r.get_psi()
+    ref = orc.fft3d(x, -1)
+    tol = 1e-6 if prec == 0 else 1e-13
+    check_l2(got, ref, tol)
+    wdm.wdm_fft3d(r.plan.handle, 0, inverse=True)
+    back = r.get_psi()
+    check_l2(back, x, tol)
+    r.close()
+
+
+# ------------------------------------------------------------- Poisson
+@pytest.mark.parametrize("prec", [0, 1])
+def test_potential_single_mode_closed_form(wdm, prec):
+    shape = (32, 64, 16)
+    L = (1.0, 2.0, 0.5)
+    xs = [np.arange(n) * (l / n) for n, l in zip(shape, L)]
+    x, y, z = np.meshgrid(*xs, indexing="ij")
+    k = [TWO_PI * 3 / L[0], TWO_PI * -2 / L[1], TWO_PI * 5 / L[2]]
+    arg = k[0] * x + k[1] * y + k[2] * z
+    rho = 1.0 + 0.3 * np.cos(arg)
+    r = Run(wdm, np.sqrt(rho).astype(complex), L=L, four_pi_G=2.0, prec=prec)
+    exact = -2.0 * 0.3 * np.cos(arg) / sum(kk * kk for kk in k)
+    check_l2(r.get_phi(), exact, (1e-5 if prec == 0 else 1e-12))
+    r.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_potential_and_density_with_particles(wdm, orc, prec):
+    n = 64
+    wl = inputs.coupled_halo(n=n, n_particles=5000, seed=3, steps=0)
+    r = Run(wdm, wl.psi, pos=wl.pos, vel=wl.vel, mp=wl.particle_mass, prec=prec)
+    cfg = orc.make_config((n,) * 3, n_particles=5000, particle_mass=wl.particle_mass)
+    pos64 = wl.pos.astype(np.float64)
+    phi_ref = orc.potential(cfg, wl.psi, pos64)
+    rho_ref = np.abs(wl.psi) ** 2 + orc.cic_deposit(cfg, pos64)
+    tol = 1e-5 if prec == 0 else 1e-11
+    check_l2(r.get_phi(), phi_ref, tol)
+    check_l2(r.get_density(True), rho_ref, tol)
+    check_l2(r.get_density(False), np.abs(wl.psi) ** 2, tol)
+    r.close()
+
+
+# ------------------------------------------------------------ stepping
+@pytest.mark.parametrize("prec", [0, 1])
+def test_plane_wave_box_100_steps(wdm, orc, prec):
+    wl = inputs.plane_wave_box(32, seed=0)
+    r = Run(wdm, wl.psi, prec=prec)
+    r.step(100, wl.dt)
+    ref, _, _ = orc.kdk(orc.make_config((32,) * 3), wl.psi, nsteps=100, dt=wl.dt)
+    err = rel_l2(r.get_psi(), ref)
+    print(f"plane-wave box 32^3, 100 steps, prec={prec}: rel L2 {err:.3e}")
+    assert err < (1e-5 if prec == 0 else 1e-11)
+    e = wdm.wdm_energy(r.plan.handle, 0)
+    m0 = float(np.sum(np.abs(wl.psi) ** 2)) / 32 ** 3
+    assert abs(e["mass"] / m0 - 1) < (1e-6 if prec == 0 else 1e-13)
+    assert e["t"] == pytest.approx(100 * wl.dt, rel=1e-12)
+    r.close()
+
+
+def test_free_evolution_exact_on_gpu(wdm):
+    wl = inputs.plane_wave_box(32, seed=5)
+    r = Run(wdm, wl.psi, four_pi_G=0.0)
+    r.step(100, wl.dt)
+    exact = wl.extra["waves"].evaluate(100 * wl.dt)
+    check_l2(r.get_psi(), exact, 1e-5)
+    r.close()
+
+
+def test_split_calls_equal_one_call(wdm):
+    # step(n) + step(m) == step(n + m) up to the merged-vs-split half kicks
+    wl = inputs.plane_wave_box(32, seed=2)
+    a = Run(wdm, wl.psi)
+    b = Run(wdm, wl.psi)
+    a.step(30, wl.dt)
+    b.step(10, wl.dt)
+    b.step(20, wl.dt)
+    check_l2(a.get_psi(), b.get_psi(), 2e-6)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coupled_halo_64_with_particles(wdm, orc, prec):
+    n, npart, steps = 64, 10_000, 20
+    wl = inputs.coupled_halo(n=n, n_particles=npart, seed=1, steps=steps)
+    r = Run(wdm, wl.psi, pos=wl.pos, vel=wl.vel, mp=wl.particle_mass, prec=prec)
+    wdm.wdm_set_sort_interval(r.plan.handle, 8)
+    r.step(steps, wl.dt)
+    cfg = orc.make_config((n,) * 3, n_particles=npart, particle_mass=wl.particle_mass)
+    psi_ref, p_ref, v_ref = orc.kdk(cfg, wl.psi, wl.pos.astype(np.float64),
+                                    wl.vel.astype(np.float64), nsteps=steps, dt=wl.dt)
+    err = rel_l2(r.get_psi(), psi_ref)
+    p, v = r.get_particles()
+    print(f"coupled halo 64^3 + 1e4, {steps} steps, prec={prec}: psi rel L2 {err:.3e}")
+    assert err < (1e-5 if prec == 0 else 1e-11)
+    assert np.max(np.abs(periodic_diff(p, p_ref))) < 1e-6
+    check_l2(v, v_ref, 1e-5)
+    r.close()
+
+
+def test_energy_diagnostics_match_oracle(wdm, orc):
+    n, npart = 64, 3000
+    wl = inputs.coupled_halo(n=n, n_particles=npart, seed=4, steps=0)
+    r = Run(wdm, wl.psi, pos=wl.pos, vel=wl.vel, mp=wl.particle_mass)
+    e = wdm.wdm_energy(r.plan.handle, 0)
+    cfg = orc.make_config((n,) * 3, n_particles=npart, particle_mass=wl.particle_mass)
+    ref = orc.energy(cfg, wl.psi, wl.pos.astype(np.float64), wl.vel.astype(np.float64))
+    for key in ("mass", "e_kin", "e_pot", "e_kin_particles", "max_abs_phi"):
+        assert e[key] == pytest.approx(ref[key], rel=2e-6), key
+    assert e["momentum"][0] == pytest.approx(ref["px"], rel=1e-5, abs=1e-9)
+    phi = r.get_phi()
+    dt_ref = orc.dt_auto(cfg, phi.astype(np.float64))
+    assert e["dt_auto"] == pytest.approx(dt_ref, rel=1e-6)
+    r.close()
+
+
+def test_time_reversibility_on_gpu(wdm):
+    n, npart = 32, 2000
+    wl = inputs.coupled_halo(n=n, n_particles=npart, seed=7, steps=0)
+    r = Run(wdm, wl.psi, pos=wl.pos, vel=wl.vel, mp=wl.particle_mass)
+    r.step(50, wl.dt)
+    r.step(50, -wl.dt)
+    psi = r.get_psi()
+    p, v = r.get_particles()
+    check_l2(psi, wl.psi, 2e-5)
+    assert np.max(np.abs(periodic_diff(p, wl.pos.astype(np.float64)))) < 1e-6
+    r.close()
+
+
+# ---------------------------------------------------------------- errors
+def test_error_paths(wdm):
+    W = wdm
+    with pytest.raises(W.WdmError) as ei:
+        W.Plan(W.make_config(100))
+    assert ei.value.status == 1
+    cfg = W.make_config(32)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(W.WdmError) as ei:
+        W.wdm_plan_create(cfg, small, 1024)
+    assert ei.value.status == 2
+    plan = W.Plan(cfg)
+    with pytest.raises(W.WdmError) as ei:
+        W.wdm_step(plan.handle, 1, 1e-4)
+    assert ei.value.status == 4
+    with pytest.raises(W.WdmError) as ei:
+        W.wdm_set_state(plan.handle, 3, torch.zeros(1, device="cuda"))
+    assert ei.value.status == 1
+    plan.close()
