@@ -144,6 +144,11 @@ wdm_status wdm_particles(wdm_plan* plan, int32_t member, float* pos_out, float* 
  * state unsynchronised: call wdm_set_state before stepping again. */
 wdm_status wdm_fft3d(wdm_plan* plan, int32_t member, int32_t inverse);
 
+/* Replay captured HIP graphs of the merged step (default on).  Off: every
+ * kernel is launched directly on the plan's stream.  Results are the same
+ * either way; profiling always launches directly. */
+wdm_status wdm_use_graphs(wdm_plan* plan, int32_t enable);
+
 /* Re-sort particles by cell every `interval` steps (0 = only in
  * wdm_set_state).  Ordering only affects speed and atomic summation order. */
 wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);

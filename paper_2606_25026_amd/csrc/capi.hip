@@ -180,6 +180,12 @@ struct wdm_plan {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_next = 0;
+    // captured-step machinery: an internal stream pair joined to the caller's
+    // stream by events; the particle kernel runs on a forked graph branch
+    bool use_graphs = true;
+    hipStream_t s_main = nullptr, s_aux = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    hipGraphExec_t g_step[2] = {nullptr, nullptr};   // [0] opening half kick, [1] merged
 };
 
 namespace {
@@ -379,7 +385,14 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
 wdm_status wdm_plan_destroy(wdm_plan* plan) {
     if (!plan) return fail(WDM_EINVAL, "null plan");
     hipStreamSynchronize(plan->stream);
+    if (plan->s_main) hipStreamSynchronize(plan->s_main);
     for (hipEvent_t e : plan->pool) hipEventDestroy(e);
+    for (hipGraphExec_t g : plan->g_step)
+        if (g) hipGraphExecDestroy(g);
+    for (hipEvent_t e : {plan->ev_in, plan->ev_out, plan->ev_fork, plan->ev_join})
+        if (e) hipEventDestroy(e);
+    if (plan->s_main) hipStreamDestroy(plan->s_main);
+    if (plan->s_aux) hipStreamDestroy(plan->s_aux);
     delete plan;
     return WDM_OK;
 }
@@ -418,6 +431,120 @@ wdm_status wdm_set_member_dt(wdm_plan* p, int32_t member, double dt) {
     return WDM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One merged KDK step for every size class (P1, particles, P2 ... P8).  With
+// `aux` set the particle kernel is forked onto it after P1 and joined before
+// P5, so it overlaps the y/x/y passes.
+hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km) {
+    const int prec = p->prec;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+        return e == hipSuccess;
+    };
+    for (const auto& c : p->classes) {
+        const Launch L{s, p->table, c.first, c.count};
+        const bool parts = c.max_np > 0;
+        const bool fork = parts && aux != nullptr;
+        if (!chk(timed(p, kKZPot, [&] {
+                return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km);
+            })))
+            return e;
+        if (fork) {
+            const Launch LA{aux, p->table, c.first, c.count};
+            if (!chk(hipEventRecord(p->ev_fork, s))) return e;
+            if (!chk(hipStreamWaitEvent(aux, p->ev_fork, 0))) return e;
+            if (!chk(launch_particles(LA, prec, c.max_np, 0, km))) return e;
+            if (!chk(hipEventRecord(p->ev_join, aux))) return e;
+        } else if (parts) {
+            if (!chk(timed(p, kKParticles, [&] { return launch_particles(L, prec, c.max_np, 0, km); })))
+                return e;
+        }
+        if (!chk(timed(p, kKYPsiF, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, false); })))
+            return e;
+        if (!chk(timed(p, kKXKin, [&] { return launch_x_kinetic(L, prec, c.nx, c.ny, c.nz); })))
+            return e;
+        if (!chk(timed(p, kKYPsiI, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, true); })))
+            return e;
+        if (fork && !chk(hipStreamWaitEvent(s, p->ev_join, 0))) return e;
+        if (!chk(timed(p, kKZDens, [&] {
+                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft);
+            })))
+            return e;
+        if (!chk(timed(p, kKYSpecF, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, false); })))
+            return e;
+        if (!chk(timed(p, kKXGreen, [&] { return launch_x_green(L, prec, c.nx, c.ny, c.nz); })))
+            return e;
+        if (!chk(timed(p, kKYSpecI, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, true); })))
+            return e;
+    }
+    return e;
+}
+
+hipError_t enqueue_sort(wdm_plan* p, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (const auto& c : p->classes) {
+        if (c.max_np <= 1) continue;
+        e = timed(p, kKSort, [&] {
+            hipError_t r = hipSuccess;
+            for (int d = c.first; d < c.first + c.count && r == hipSuccess; ++d)
+                r = launch_particle_sort(s, p->host[d], p->table, p->prec);
+            return r;
+        });
+        if (e != hipSuccess) return e;
+    }
+    return e;
+}
+
+hipError_t enqueue_close(wdm_plan* p, hipStream_t s, int64_t n) {
+    hipError_t e = hipSuccess;
+    for (const auto& c : p->classes) {
+        const Launch L{s, p->table, c.first, c.count};
+        e = timed(p, kKClose, [&] {
+            return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZKickOnly, kHalfKick);
+        });
+        if (e == hipSuccess && c.max_np > 0)
+            e = timed(p, kKCloseParticles, [&] {
+                return launch_particles(L, p->prec, c.max_np, 1, kHalfKick);
+            });
+        if (e == hipSuccess) e = launch_advance_time(L, n);
+        if (e != hipSuccess) return e;
+    }
+    return e;
+}
+
+bool resort_due(const wdm_plan* p) {
+    return p->sort_interval > 0 && p->steps_done > 0 && p->steps_done % p->sort_interval == 0;
+}
+
+// Capture one step (opening or merged) into an executable graph.
+hipError_t capture_step(wdm_plan* p, int which) {
+    if (p->g_step[which]) return hipSuccess;
+    if (!p->s_main) {
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&p->s_main, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipStreamCreateWithFlags(&p->s_aux, hipStreamNonBlocking)) != hipSuccess) return e;
+        for (hipEvent_t* ev : {&p->ev_in, &p->ev_out, &p->ev_fork, &p->ev_join})
+            if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->s_main, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = enqueue_step(p, p->s_main, p->s_aux, which ? kFullKick : kHalfKick);
+    e = hipStreamEndCapture(p->s_main, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->g_step[which], g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
     if (!p) return fail(WDM_EINVAL, "null plan");
     if (n < 0) return fail(WDM_EINVAL, "n must be >= 0");
@@ -425,55 +552,49 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
     for (size_t i = 0; i < p->has_state.size(); ++i)
         if (!p->has_state[i]) return fail(WDM_ESTATE, "wdm_set_state not called for every member");
     if (n == 0) return WDM_OK;
-    const int prec = p->prec;
+    const bool graphs = p->use_graphs && !p->profiling;
+    if (graphs) {
+        for (int w = 0; w < 2; ++w)
+            if (capture_step(p, w) != hipSuccess) {
+                p->use_graphs = false;   // capture unavailable: launch directly
+                hipGetLastError();
+                return wdm_step(p, n, dt);
+            }
+    }
+    hipStream_t s = graphs ? p->s_main : p->stream;
+    if (graphs) {
+        HIPCHK(hipEventRecord(p->ev_in, p->stream));
+        HIPCHK(hipStreamWaitEvent(s, p->ev_in, 0));
+    }
     for (const auto& c : p->classes) {
-        const Launch L{p->stream, p->table, c.first, c.count};
+        const Launch L{s, p->table, c.first, c.count};
         HIPCHK(dt != 0.0 ? launch_set_dt(L, dt, 0) : launch_set_dt(L, 0.0, 1));
     }
     for (int64_t i = 0; i < n; ++i) {
-        const KickMode km = i == 0 ? kHalfKick : kFullKick;
-        const bool resort = p->sort_interval > 0 && p->steps_done > 0 &&
-                            p->steps_done % p->sort_interval == 0;
-        for (const auto& c : p->classes) {
-            const Launch L{p->stream, p->table, c.first, c.count};
-            if (resort && c.max_np > 1) {
-                HIPCHK(timed(p, kKSort, [&] {
-                    hipError_t e = hipSuccess;
-                    for (int d = c.first; d < c.first + c.count && e == hipSuccess; ++d)
-                        e = launch_particle_sort(p->stream, p->host[d], p->table, prec);
-                    return e;
-                }));
-            }
-            HIPCHK(timed(p, kKZPot, [&] {
-                return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km);
-            }));
-            if (c.max_np > 0)
-                HIPCHK(timed(p, kKParticles, [&] { return launch_particles(L, prec, c.max_np, 0, km); }));
-            HIPCHK(timed(p, kKYPsiF, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, false); }));
-            HIPCHK(timed(p, kKXKin, [&] { return launch_x_kinetic(L, prec, c.nx, c.ny, c.nz); }));
-            HIPCHK(timed(p, kKYPsiI, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, true); }));
-            HIPCHK(timed(p, kKZDens, [&] {
-                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft);
-            }));
-            HIPCHK(timed(p, kKYSpecF, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, false); }));
-            HIPCHK(timed(p, kKXGreen, [&] { return launch_x_green(L, prec, c.nx, c.ny, c.nz); }));
-            HIPCHK(timed(p, kKYSpecI, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, true); }));
-        }
+        if (resort_due(p)) HIPCHK(enqueue_sort(p, s));
+        if (graphs)
+            HIPCHK(hipGraphLaunch(p->g_step[i == 0 ? 0 : 1], s));
+        else
+            HIPCHK(enqueue_step(p, s, nullptr, i == 0 ? kHalfKick : kFullKick));
         p->steps_done++;
     }
-    for (const auto& c : p->classes) {
-        const Launch L{p->stream, p->table, c.first, c.count};
-        HIPCHK(timed(p, kKClose, [&] {
-            return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickOnly, kHalfKick);
-        }));
-        if (c.max_np > 0)
-            HIPCHK(timed(p, kKCloseParticles, [&] {
-                return launch_particles(L, prec, c.max_np, 1, kHalfKick);
-            }));
-        HIPCHK(launch_advance_time(L, n));
+    HIPCHK(enqueue_close(p, s, n));
+    if (graphs) {
+        HIPCHK(hipEventRecord(p->ev_out, s));
+        HIPCHK(hipStreamWaitEvent(p->stream, p->ev_out, 0));
     }
     return WDM_OK;
 }
+
+wdm_status wdm_use_graphs(wdm_plan* p, int32_t enable) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    p->use_graphs = enable != 0;
+    return WDM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 wdm_status wdm_get_psi(wdm_plan* p, int32_t member, void* out) {
     if (wdm_status s = check_member(p, member)) return s;

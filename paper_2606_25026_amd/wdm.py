@@ -65,6 +65,7 @@ _SIGS = {
     "wdm_particles": (C.c_int, [_vp, _i32, _vp, _vp]),
     "wdm_fft3d": (C.c_int, [_vp, _i32, _i32]),
     "wdm_set_sort_interval": (C.c_int, [_vp, _i32]),
+    "wdm_use_graphs": (C.c_int, [_vp, _i32]),
     "wdm_profile": (C.c_int, [_vp, _i32]),
     "wdm_profile_read": (C.c_int, [_vp, C.POINTER(wdm_kernel_stat), _i32, C.POINTER(_i32)]),
     "wdm_copy_bandwidth": (C.c_int, [_vp, _vp, C.c_size_t, _i32, _vp, C.POINTER(_f64)]),
@@ -188,6 +189,10 @@ def wdm_fft3d(plan, member, inverse=False):
 
 def wdm_set_sort_interval(plan, interval):
     _check(load().wdm_set_sort_interval(plan, int(interval)))
+
+
+def wdm_use_graphs(plan, enable=True):
+    _check(load().wdm_use_graphs(plan, 1 if enable else 0))
 
 
 def wdm_profile(plan, enable=True):
