@@ -147,6 +147,13 @@ def main():
     if not args.no_profile:
         wdm.wdm_profile(h, False)
         stats = wdm.wdm_profile_read(h)
+    # the same number of steps again with captured graphs and no per-kernel
+    # events, for comparison with the profiled timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wdm.wdm_step(h, args.steps, wl.dt)
+    torch.cuda.synchronize()
+    elapsed_graph = time.perf_counter() - t0
     e1 = wdm.wdm_energy(h, 0)
     ms_per_step = elapsed * 1e3 / args.steps
     value = n3 * args.steps / elapsed
@@ -207,6 +214,8 @@ def main():
                           "copy_kernel_gbs": copy_gbs},
         "per_kernel": per_kernel,
         "profiled": not args.no_profile,
+        "unprofiled_graph_replay": {"ms_per_step": elapsed_graph * 1e3 / args.steps,
+                                    "value": n3 * args.steps / elapsed_graph},
         "mass_drift": e1["mass"] / e0["mass"] - 1.0,
         "cpu_baseline": cpu,
     }

@@ -141,7 +141,8 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         for (int len : {g.nx, g.ny, g.nz})
             if (!L.tw.count(len)) L.tw[len] = 0;
     }
-    for (auto& kv : L.tw) kv.second = c.take(size_t(kv.first) * cs);
+    // complex64: hi and lo float tables; complex128: one double table
+    for (auto& kv : L.tw) kv.second = c.take(size_t(kv.first) * cs * (prec ? 1 : 2));
     L.scratch = c.take(maxn * cs);
     L.partial_rows = std::max<int64_t>(kRedBlocks, (maxplane + 7) / 8);
     L.partials = c.take(L.partial_rows * kRedFields * sizeof(double));
@@ -199,16 +200,21 @@ hipEvent_t take_event(wdm_plan* p) {
     return p->pool[p->pool_next++];
 }
 
+// Bracket one launch with HIP events on the stream it is launched on.
 template <class F>
-hipError_t timed(wdm_plan* p, int kind, F&& f) {
+hipError_t timed_on(wdm_plan* p, hipStream_t s, int kind, F&& f) {
     if (!p->profiling) return f();
     hipEvent_t a = take_event(p), b = take_event(p);
     if (!a || !b) return f();
-    hipEventRecord(a, p->stream);
+    hipEventRecord(a, s);
     const hipError_t e = f();
-    hipEventRecord(b, p->stream);
+    hipEventRecord(b, s);
     p->recs.push_back({kind, a, b});
     return e;
+}
+template <class F>
+hipError_t timed(wdm_plan* p, int kind, F&& f) {
+    return timed_on(p, p->stream, kind, f);
 }
 
 #define HIPCHK(expr)                                                                  \
@@ -348,20 +354,24 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         delete p;
         return fail(st, msg);
     };
-    // twiddles W_n^m = exp(-2 pi i m / n) in FP64, rounded once
+    // twiddles W_n^m = exp(-2 pi i m / n) in FP64; complex64 stores the
+    // double-float split hi = float(w), lo = float(w - hi)
     for (const auto& kv : L.tw) {
         const int n = kv.first;
         std::vector<double> d(2 * size_t(n));
-        std::vector<float> f(2 * size_t(n));
+        std::vector<float> f(4 * size_t(n));
         for (int m = 0; m < n; ++m) {
             const double a = -kTwoPi * double(m) / double(n);
             d[2 * m] = std::cos(a);
             d[2 * m + 1] = std::sin(a);
             f[2 * m] = float(d[2 * m]);
             f[2 * m + 1] = float(d[2 * m + 1]);
+            f[2 * n + 2 * m] = float(d[2 * m] - double(f[2 * m]));
+            f[2 * n + 2 * m + 1] = float(d[2 * m + 1] - double(f[2 * m + 1]));
         }
         const void* src = p->prec ? static_cast<const void*>(d.data()) : f.data();
-        if (hipMemcpy(ws + kv.second, src, size_t(n) * cs, hipMemcpyHostToDevice) != hipSuccess)
+        const size_t bytes = size_t(n) * cs * (p->prec ? 1 : 2);
+        if (hipMemcpy(ws + kv.second, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(WDM_EDEVICE, "twiddle upload failed");
     }
     if (hipMemcpy(p->table, p->host.data(), sizeof(MemberDev) * n_members,
@@ -386,6 +396,7 @@ wdm_status wdm_plan_destroy(wdm_plan* plan) {
     if (!plan) return fail(WDM_EINVAL, "null plan");
     hipStreamSynchronize(plan->stream);
     if (plan->s_main) hipStreamSynchronize(plan->s_main);
+    if (plan->s_aux) hipStreamSynchronize(plan->s_aux);
     for (hipEvent_t e : plan->pool) hipEventDestroy(e);
     for (hipGraphExec_t g : plan->g_step)
         if (g) hipGraphExecDestroy(g);
@@ -457,7 +468,9 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             const Launch LA{aux, p->table, c.first, c.count};
             if (!chk(hipEventRecord(p->ev_fork, s))) return e;
             if (!chk(hipStreamWaitEvent(aux, p->ev_fork, 0))) return e;
-            if (!chk(launch_particles(LA, prec, c.max_np, 0, km))) return e;
+            if (!chk(timed_on(p, aux, kKParticles,
+                              [&] { return launch_particles(LA, prec, c.max_np, 0, km); })))
+                return e;
             if (!chk(hipEventRecord(p->ev_join, aux))) return e;
         } else if (parts) {
             if (!chk(timed(p, kKParticles, [&] { return launch_particles(L, prec, c.max_np, 0, km); })))
@@ -520,16 +533,22 @@ bool resort_due(const wdm_plan* p) {
     return p->sort_interval > 0 && p->steps_done > 0 && p->steps_done % p->sort_interval == 0;
 }
 
+// Internal streams (default priority) and the fork/join events.
+hipError_t ensure_streams(wdm_plan* p) {
+    if (p->s_main) return hipSuccess;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&p->s_main, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipStreamCreateWithFlags(&p->s_aux, hipStreamNonBlocking)) != hipSuccess) return e;
+    for (hipEvent_t* ev : {&p->ev_in, &p->ev_out, &p->ev_fork, &p->ev_join})
+        if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
 // Capture one step (opening or merged) into an executable graph.
 hipError_t capture_step(wdm_plan* p, int which) {
     if (p->g_step[which]) return hipSuccess;
-    if (!p->s_main) {
-        hipError_t e;
-        if ((e = hipStreamCreateWithFlags(&p->s_main, hipStreamNonBlocking)) != hipSuccess) return e;
-        if ((e = hipStreamCreateWithFlags(&p->s_aux, hipStreamNonBlocking)) != hipSuccess) return e;
-        for (hipEvent_t* ev : {&p->ev_in, &p->ev_out, &p->ev_fork, &p->ev_join})
-            if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
-    }
+    hipError_t e0 = ensure_streams(p);
+    if (e0 != hipSuccess) return e0;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(p->s_main, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
@@ -561,6 +580,9 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
                 return wdm_step(p, n, dt);
             }
     }
+    // direct launches run on the caller's stream and fork the particle
+    // kernel onto the auxiliary stream, as the captured graph does
+    HIPCHK(ensure_streams(p));
     hipStream_t s = graphs ? p->s_main : p->stream;
     if (graphs) {
         HIPCHK(hipEventRecord(p->ev_in, p->stream));
@@ -575,7 +597,7 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
         if (graphs)
             HIPCHK(hipGraphLaunch(p->g_step[i == 0 ? 0 : 1], s));
         else
-            HIPCHK(enqueue_step(p, s, nullptr, i == 0 ? kHalfKick : kFullKick));
+            HIPCHK(enqueue_step(p, s, p->s_aux, i == 0 ? kHalfKick : kFullKick));
         p->steps_done++;
     }
     HIPCHK(enqueue_close(p, s, n));
@@ -725,6 +747,7 @@ wdm_status wdm_profile(wdm_plan* p, int32_t enable) {
 wdm_status wdm_profile_read(wdm_plan* p, wdm_kernel_stat* out, int32_t cap, int32_t* count) {
     if (!p || !count) return fail(WDM_EINVAL, "null argument");
     HIPCHK(hipStreamSynchronize(p->stream));
+    if (p->s_aux) HIPCHK(hipStreamSynchronize(p->s_aux));
     std::vector<wdm_kernel_stat> agg(kKinds);
     for (int k = 0; k < kKinds; ++k) {
         std::memset(&agg[k], 0, sizeof(wdm_kernel_stat));

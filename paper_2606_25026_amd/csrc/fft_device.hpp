@@ -46,6 +46,23 @@ template <typename R>
 __device__ __forceinline__ cplx<R> conj(cplx<R> a) {
     return {a.re, -a.im};
 }
+// a * (h + l) for a twiddle split into a high part h and a small low part l,
+// rounded once per component: the low terms enter the fused chain before the
+// single rounding of the large product.  (Adding a*l after rounding a*h would
+// round the correction away and leave the constant's modulus error in place,
+// which biases the norm by ~1e-8 per butterfly in the same direction every
+// step.)
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul_split(cplx<R> a, cplx<R> h, cplx<R> l) {
+    R re = fma(a.re, l.re, -(a.im * l.im));
+    re = fma(-a.im, h.im, re);
+    re = fma(a.re, h.re, re);
+    R im = fma(a.re, l.im, a.im * l.re);
+    im = fma(a.im, h.re, im);
+    im = fma(a.re, h.im, im);
+    return {re, im};
+}
+
 // multiply by -i (forward direction) or +i (inverse direction)
 template <bool INV, typename R>
 __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {
@@ -53,6 +70,32 @@ __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {
         return {-a.im, a.re};
     else
         return {a.im, -a.re};
+}
+
+// Global-memory complex load / store through 2-vectors of the base type
+// (address space 1, see wdm_internal.hpp).
+typedef float wdm_f2v __attribute__((ext_vector_type(2)));
+typedef double wdm_d2v __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = wdm_f2v;
+};
+template <>
+struct Vec2<double> {
+    using type = wdm_d2v;
+};
+template <typename T>
+__device__ __forceinline__ cplx<T> gld(const cplx<T>* p, int64_t i) {
+    using V = typename Vec2<T>::type;
+    const V v = ((const __attribute__((address_space(1))) V*)p)[i];
+    return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gst(cplx<T>* p, int64_t i, cplx<T> v) {
+    using V = typename Vec2<T>::type;
+    ((__attribute__((address_space(1))) V*)p)[i] = V{v.re, v.im};
 }
 
 // ---------------------------------------------------------------------------
@@ -92,7 +135,11 @@ constexpr double cos48(int j) {
 constexpr double sin48(int j) { return cos48(j - 12); }
 
 // a * W_R^E with W_R = exp(-2 pi i / R) (forward) or its conjugate (inverse).
-// R must divide 48.
+// R must divide 48.  In single precision the constant is carried as a
+// hi + lo pair of floats: a rounded constant has a fixed modulus error
+// (|w|^2 - 1 = -5.7e-8 for 22.5 degrees), which would bias the norm the same
+// way in every butterfly of every step; with the pair the product is exact up
+// to one rounding of the result.
 template <int R, int E, bool INV, typename T>
 __device__ __forceinline__ cplx<T> twiddle_const(cplx<T> a) {
     static_assert(48 % R == 0, "radix must divide 48");
@@ -106,9 +153,17 @@ __device__ __forceinline__ cplx<T> twiddle_const(cplx<T> a) {
     } else if constexpr (j == 36) {
         return mul_mi<!INV>(a);                // W = +i (forward)
     } else {
-        constexpr T c = T(cos48(j));
-        constexpr T s = INV ? T(sin48(j)) : T(-sin48(j));
-        return {a.re * c - a.im * s, a.re * s + a.im * c};
+        constexpr double cd = cos48(j);
+        constexpr double sd = INV ? sin48(j) : -sin48(j);
+        constexpr T c = T(cd);
+        constexpr T s = T(sd);
+        if constexpr (std::is_same<T, float>::value) {
+            constexpr float cl = float(cd - double(c));
+            constexpr float sl = float(sd - double(s));
+            return cmul_split(a, cplx<T>{c, s}, cplx<T>{cl, sl});
+        } else {
+            return cplx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+        }
     }
 }
 
@@ -131,11 +186,17 @@ __device__ __forceinline__ void dft(cplx<T>* v) {
         v[1] = a - b;
     } else if constexpr (R == 3) {
         // X1,2 = x0 - (x1+x2)/2 -/+ i (sqrt3/2)(x1 - x2)  (forward)
-        constexpr T h = T(0.86602540378443864676);
+        constexpr double hd = 0.86602540378443864676;
+        constexpr T h = T(hd);
         cplx<T> s = v[1] + v[2];
         cplx<T> d = v[1] - v[2];
         cplx<T> m = {v[0].re - T(0.5) * s.re, v[0].im - T(0.5) * s.im};
-        cplx<T> r = mul_mi<INV>(cplx<T>{d.re * h, d.im * h});
+        cplx<T> hd_ = {d.re * h, d.im * h};
+        if constexpr (std::is_same<T, float>::value) {
+            constexpr float hl = float(hd - double(h));   // low half of sqrt(3)/2
+            hd_ = cplx<T>{fma(d.re, h, d.re * hl), fma(d.im, h, d.im * hl)};
+        }
+        cplx<T> r = mul_mi<INV>(hd_);
         v[0] = v[0] + s;
         v[1] = m + r;
         v[2] = m - r;
@@ -248,8 +309,15 @@ __device__ __forceinline__ void stockham_level(cplx<T>* v, cplx<T>* lds, const c
             const int jm = j % Ns;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const cplx<T> w = tw[jm * r * (N / (Ns * R))];
-                v[b * R + r] = INV ? cmulc(v[b * R + r], w) : cmul(v[b * R + r], w);
+                const int m = jm * r * (N / (Ns * R));
+                const cplx<T> x = v[b * R + r];
+                if constexpr (std::is_same<T, float>::value) {
+                    // hi (entries 0..N-1) and lo (N..2N-1) halves, one rounding
+                    const cplx<T> h = tw[m], l = tw[N + m];
+                    v[b * R + r] = INV ? cmul_split(x, conj(h), conj(l)) : cmul_split(x, h, l);
+                } else {
+                    v[b * R + r] = INV ? cmulc(x, tw[m]) : cmul(x, tw[m]);
+                }
             }
         }
     }
@@ -266,6 +334,13 @@ __device__ __forceinline__ void stockham_level(cplx<T>* v, cplx<T>* lds, const c
         __syncthreads();
         stockham_level<P, LVL + 1, INV, T>(v, lds, tw, t, idx);
     }
+}
+
+// Twiddle entries per table: complex64 keeps W_N^m as hi (first N entries) and
+// lo (next N) floats; complex128 keeps one double table.
+template <typename T>
+constexpr int tw_entries(int n) {
+    return std::is_same<T, float>::value ? 2 * n : n;
 }
 
 // Full pencil transform.  Input in the plan's input layout (first radix),

@@ -59,7 +59,7 @@ __device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const Membe
         iz[d] = wrapi(c.k + d - 1, nz);
     }
     auto P = [&](int a, int b, int d) -> T {
-        return phi[(int64_t(ix[a]) * ny + iy[b]) * nz + iz[d]];
+        return gldr(phi, (int64_t(ix[a]) * ny + iy[b]) * nz + iz[d]);
     };
     const T hx = T(0.5) * T(m.nx / m.lx), hy = T(0.5) * T(m.ny / m.ly),
             hz = T(0.5) * T(m.nz / m.lz);
@@ -131,8 +131,8 @@ __device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberD
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-                atomicAdd(&grid[(int64_t(I[a]) * ny + J[b]) * nz + K[d]],
-                          T(val[a * 4 + b * 2 + d]));
+                gatomic_add(&grid[(int64_t(I[a]) * ny + J[b]) * nz + K[d]],
+                            T(val[a * 4 + b * 2 + d]));
 }
 
 // mode 0: kick + drift + deposit into rho_b; 1: kick only; 2: deposit into
@@ -145,10 +145,10 @@ __global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const bool act = i < m.np;
     const int64_t ii = act ? i : 0;
-    float x = m.px[ii], y = m.py[ii], z = m.pz[ii];
-    const double dt = m.dt[0];
+    float x = gldr(m.px, ii), y = gldr(m.py, ii), z = gldr(m.pz, ii);
+    const double dt = gldr(m.dt, 0);
     if (mode <= 1) {
-        float vx = m.vx[ii], vy = m.vy[ii], vz = m.vz[ii];
+        float vx = gldr(m.vx, ii), vy = gldr(m.vy, ii), vz = gldr(m.vz, ii);
         const CellW<T> c = cic<T>(x, y, z, m);
         float g[3];
         cic_accel(static_cast<const T*>(m.phi), m, c, g);
@@ -161,15 +161,15 @@ __global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__
             y = wrap_pos(double(y) + double(vy) * dt, m.ly);
             z = wrap_pos(double(z) + double(vz) * dt, m.lz);
             if (act) {
-                m.px[i] = x;
-                m.py[i] = y;
-                m.pz[i] = z;
+                gstr(m.px, i, x);
+                gstr(m.py, i, y);
+                gstr(m.pz, i, z);
             }
         }
         if (act) {
-            m.vx[i] = vx;
-            m.vy[i] = vy;
-            m.vz[i] = vz;
+            gstr(m.vx, i, vx);
+            gstr(m.vy, i, vy);
+            gstr(m.vz, i, vz);
         }
         if (mode == 1) return;
     }
@@ -248,16 +248,36 @@ __global__ void k_make_keys(MemberDev m) {
     m.idx_a[i] = uint32_t(i);
 }
 
+// Lanes of the wavefront holding the same 8-bit digit (among `valid` lanes).
+__device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid) {
+    unsigned long long mask = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const unsigned long long bb = __ballot(on);
+        mask &= on ? bb : ~bb;
+    }
+    return mask;
+}
+
+// Per-block digit counts.  Keys of one block mostly share their high digits
+// (particles are clustered), so equal digits are first counted across the
+// wavefront and one lane per digit adds the group size.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                     int shift, uint32_t* __restrict__ hist,
                                                     int nblocks) {
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
+    const int lane = int(threadIdx.x) & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
     for (int r = 0; r < kSortTile / 256; ++r) {
         const int64_t i = b0 + r * 256 + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        const bool valid = i < n;
+        const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+        const unsigned long long mask = match_digit(d, valid);
+        if (valid && __popcll(mask & lt) == 0) atomicAdd(&cnt[d], uint32_t(__popcll(mask)));
     }
     __syncthreads();
     hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
@@ -270,6 +290,7 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int
     const int64_t b = int64_t(threadIdx.x) * chunk;
     const int64_t e = b + chunk < n ? b + chunk : n;
     uint32_t sum = 0;
+#pragma unroll 8
     for (int64_t i = b; i < e; ++i) sum += a[i];
     s[threadIdx.x] = sum;
     __syncthreads();
@@ -307,13 +328,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
         const bool valid = i < n;
         const uint32_t k = valid ? kin[i] : 0u;
         const uint32_t d = (k >> shift) & 255u;
-        unsigned long long mask = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool on = (d >> bit) & 1u;
-            const unsigned long long bb = __ballot(on);
-            mask &= on ? bb : ~bb;
-        }
+        const unsigned long long mask = match_digit(d, valid);
         const int rank = __popcll(mask & lt);
         if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(mask));
         __syncthreads();

@@ -16,8 +16,8 @@
 // Phase arguments (Phi tau / eta and eta |k|^2 dt / 2) and the Green's
 // function are formed in FP64 and reduced mod 2 pi before the single-precision
 // sincos of the complex64 path.
-#include "fft_device.hpp"
 #include "wdm_internal.hpp"
+#include "fft_device.hpp"
 
 namespace wdm {
 
@@ -97,10 +97,21 @@ __device__ __forceinline__ int slot_elem(int t, int s) {
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* tw, const void* g, int n) {
     const cplx<T>* src = static_cast<const cplx<T>*>(g);
-    for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) tw[i] = src[i];
+    const int total = tw_entries<T>(n);
+    for (int i = int(threadIdx.x); i < total; i += int(blockDim.x)) tw[i] = gld(src, i);
 }
 
 __device__ __forceinline__ int signed_mode(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// Large-argument branch of rotate(): FP64 sincos and product, rounded once.
+// Kept out of line: it is rarely taken and would otherwise be inlined into
+// every slot of every pass.
+__device__ __noinline__ cplx<float> rotate_fp64(cplx<float> a, double r) {
+    double s, c;
+    sincos(r, &s, &c);
+    const double re = double(a.re), im = double(a.im);
+    return cplx<float>{float(re * c - im * s), float(re * s + im * c)};
+}
 
 // a * exp(i arg), arg reduced mod 2 pi in FP64.  Single precision: for small
 // reduced arguments exp(i r) = 1 + q with q = (-2 sin^2(r/2), sin r) formed from
@@ -114,13 +125,12 @@ __device__ __forceinline__ cplx<T> rotate(cplx<T> a, double arg) {
         if (fabs(r) < 0.0625) {
             float s, c;
             sincosf(float(0.5 * r), &s, &c);
-            const cplx<float> q{-2.0f * s * s, 2.0f * s * c};
-            return a + cmul(a, q);
+            const float qr = -2.0f * s * s, qi = 2.0f * s * c;
+            // a (1 + q), fused so the small rotation is not rounded twice
+            return cplx<float>{fma(a.re, qr, fma(-a.im, qi, a.re)),
+                               fma(a.im, qr, fma(a.re, qi, a.im))};
         }
-        double s, c;
-        sincos(r, &s, &c);
-        const double re = double(a.re), im = double(a.im);
-        return cplx<float>{float(re * c - im * s), float(re * s + im * c)};
+        return rotate_fp64(a, r);
     } else {
         double s, c;
         sincos(r, &s, &c);
@@ -150,7 +160,7 @@ __device__ __forceinline__ void load_slots(cplx<T>* v, const cplx<T>* g, int64_t
 #pragma unroll
     for (int s = 0; s < P::E; ++s) {
         const int e = slot_elem<P, R>(ln.t, s);
-        v[s] = ok ? g[base + int64_t(e) * st] : cplx<T>{T(0), T(0)};
+        v[s] = ok ? gld(g, base + int64_t(e) * st) : cplx<T>{T(0), T(0)};
     }
 }
 template <class P, int R, typename T, class L>
@@ -160,7 +170,7 @@ __device__ __forceinline__ void store_slots(const cplx<T>* v, cplx<T>* g, int64_
 #pragma unroll
     for (int s = 0; s < P::E; ++s) {
         const int e = slot_elem<P, R>(ln.t, s);
-        g[base + int64_t(e) * st] = v[s];
+        gst(g, base + int64_t(e) * st, v[s]);
     }
 }
 
@@ -176,7 +186,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     constexpr int PP = LN::PP;
     constexpr int H = NZ / 2;
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[NZ];
+    __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     const MemberDev& m = mems[first + blockIdx.y];
     const LN ln;
     const int64_t npen = int64_t(m.nx) * m.ny;
@@ -184,9 +194,9 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     const bool ok = q < npen;
     load_twiddles<T>(tw, m.tw_z, NZ);
     const cplx<T>* spec = static_cast<const cplx<T>*>(m.spec) + q * H;
-    for (int e = ln.t; e < H; e += FP::T) lds[ln(e)] = ok ? spec[e] : cplx<T>{T(0), T(0)};
+    for (int e = ln.t; e < H; e += FP::T) lds[ln(e)] = ok ? gld(spec, e) : cplx<T>{T(0), T(0)};
     if (ln.t == 0)
-        lds[ln(H)] = ok ? static_cast<const cplx<T>*>(m.spec_nyq)[q] : cplx<T>{T(0), T(0)};
+        lds[ln(H)] = ok ? gld(static_cast<const cplx<T>*>(m.spec_nyq), q) : cplx<T>{T(0), T(0)};
     __syncthreads();
     // Hermitian completion F[e] = conj(F[NZ - e]) for e > NZ/2, in the input
     // layout of the inverse plan
@@ -204,10 +214,10 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
 #pragma unroll
     for (int s = 0; s < FP::E; ++s) {
         phi[s] = v[s].re;
-        if (ok) gphi[slot_elem<FP, FP::first()>(ln.t, s)] = phi[s];
+        if (ok) gstr(gphi, slot_elem<FP, FP::first()>(ln.t, s), phi[s]);
     }
     if constexpr (OP == kZPhiOnly) return;
-    const double dt = m.dt[0];
+    const double dt = gldr(m.dt, 0);
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
     const double c = -tau / m.eta;
     cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
@@ -235,7 +245,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     constexpr int PP = LN::PP;
     constexpr int H = NZ / 2;
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[NZ];
+    __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     const MemberDev& m = mems[first + blockIdx.y];
     const LN ln;
     const int64_t npen = int64_t(m.nx) * m.ny;
@@ -259,8 +269,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
         const int e = slot_elem<FP, FP::first()>(ln.t, s);
         T r = v[s].re * v[s].re + v[s].im * v[s].im;
         if (ok) {
-            r += rb[e];
-            rb[e] = T(0);
+            r += gldr(rb, e);
+            gstr(rb, e, T(0));
         }
         v[s] = cplx<T>{r, T(0)};
     }
@@ -272,9 +282,9 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     for (int s = 0; s < FP::E; ++s) {
         const int e = slot_elem<FP, FP::last()>(ln.t, s);
         if (e < H)
-            spec[e] = v[s];
+            gst(spec, e, v[s]);
         else if (e == H)
-            static_cast<cplx<T>*>(m.spec_nyq)[q] = v[s];
+            gst(static_cast<cplx<T>*>(m.spec_nyq), q, v[s]);
     }
 }
 
@@ -311,7 +321,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY>::type, T>())) void k_
     using FP = typename PlanFor<NY>::type;
     constexpr int PP = pencils_per_wg<FP, T>();
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[NY];
+    __shared__ cplx<T> tw[tw_entries<T>(NY)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_y, NY);
     __syncthreads();
@@ -346,11 +356,11 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[NX];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ cplx<double> ex[NX];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_x, NX);
-    const double dt = m.dt[0];
+    const double dt = gldr(m.dt, 0);
     const double a = -0.5 * m.eta * dt;
     const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
     for (int i = int(threadIdx.x); i < NX; i += int(blockDim.x)) {
@@ -389,7 +399,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[NX];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_x, NX);
     __syncthreads();
@@ -430,7 +440,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<N>::type, T>())) void k_a
     const MemberDev* __restrict__ mems, int first, int which) {
     using FP = typename PlanFor<N>::type;
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[N];
+    __shared__ cplx<T> tw[tw_entries<T>(N)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, AXIS == 0 ? m.tw_x : (AXIS == 1 ? m.tw_y : m.tw_z), N);
     __syncthreads();
@@ -457,7 +467,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     using LN = Lanes<FP, T, true>;
     constexpr int WG = wg_size<FP, T>();
     __shared__ cplx<T> lds[lds_entries<FP, T>()];
-    __shared__ cplx<T> tw[NX];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double red[WG];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_x, NX);
@@ -485,7 +495,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
         if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) m.partials[int64_t(blockIdx.x) * kRedFields + 1] = red[0];
+    if (threadIdx.x == 0) gstr(m.partials, int64_t(blockIdx.x) * kRedFields + 1, red[0]);
 }
 
 // ---------------------------------------------------------------------------

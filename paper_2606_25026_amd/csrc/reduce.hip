@@ -3,8 +3,8 @@
 // kernels.  Reductions are deterministic: a fixed number of work-groups, each
 // summing a fixed range in a fixed order, then one work-group summing the
 // partials in order -- no floating-point atomics.
-#include "fft_device.hpp"
 #include "wdm_internal.hpp"
+#include "fft_device.hpp"
 
 namespace wdm {
 
@@ -50,13 +50,14 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __
     const T* rb = static_cast<const T*>(m.scratch);
     double s0 = 0.0, s1 = 0.0;
     for (int64_t i = b + threadIdx.x; i < e; i += kRedThreads) {
-        const double re = double(psi[i].re), im = double(psi[i].im);
+        const cplx<T> v = gld(psi, i);
+        const double re = double(v.re), im = double(v.im);
         const double rho = re * re + im * im;
         if (what == 0) {
             s0 += rho;
-            s1 = fmax(s1, fabs(double(phi[i])));
+            s1 = fmax(s1, fabs(double(gldr(phi, i))));
         } else {
-            s0 += (rho + double(rb[i])) * double(phi[i]);
+            s0 += (rho + double(gldr(rb, i))) * double(gldr(phi, i));
         }
     }
     const double t0 = block_sum<T>(s0, red);
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_particles(
     const int64_t e = b + chunk < n ? b + chunk : n;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = b + threadIdx.x; i < e; i += kRedThreads) {
-        const double vx = m.vx[i], vy = m.vy[i], vz = m.vz[i];
+        const double vx = gldr(m.vx, i), vy = gldr(m.vy, i), vz = gldr(m.vz, i);
         s[0] += vx * vx + vy * vy + vz * vz;
         s[1] += vx;
         s[2] += vy;

@@ -7,6 +7,26 @@
 
 namespace wdm {
 
+// Device accesses through pointers read out of the member table would compile
+// to flat memory instructions (the compiler cannot prove they are global),
+// which also hold the LDS wait counter.  These accessors cast to the global
+// address space so loads, stores and atomics are global_* instructions.
+#define WDM_GAS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gldr(const T* p, int64_t i) {
+    return ((const WDM_GAS T*)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void gstr(T* p, int64_t i, T v) {
+    ((WDM_GAS T*)p)[i] = v;
+}
+__device__ __forceinline__ void gatomic_add(float* p, float v) {
+    __builtin_amdgcn_global_atomic_fadd_f32((WDM_GAS float*)p, v);
+}
+__device__ __forceinline__ void gatomic_add(double* p, double v) {
+    __builtin_amdgcn_global_atomic_fadd_f64((WDM_GAS double*)p, v);
+}
+
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kTwoPi = 2.0 * kPi;
 

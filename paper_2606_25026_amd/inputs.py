@@ -245,11 +245,13 @@ def ensemble_member(seed: int, n: int, n_particles: int = 10_000) -> Workload:
     psi = grf_soliton(n, L=L, k0=16.0 * TWO_PI / L, rc=rc, rho_c=50.0, rng=rng)
     mw = wave_mass(psi, L)
     mtot = 0.1 * mw
-    pos, vel = plummer(n_particles, a=0.03, total_mass=mtot, L=L, rng=rng)
+    pos = vel = None
+    if n_particles > 0:
+        pos, vel = plummer(n_particles, a=0.03, total_mass=mtot, L=L, rng=rng)
     dx = L / n
     return Workload(name=f"ensemble member seed {seed} {n}^3", n=n, L=L, psi=psi, pos=pos,
-                    vel=vel, particle_mass=mtot / n_particles, dt=0.2 * dx * dx, steps=100,
-                    extra={"rc": rc, "seed": seed})
+                    vel=vel, particle_mass=mtot / n_particles if n_particles else 0.0,
+                    dt=0.2 * dx * dx, steps=100, extra={"rc": rc, "seed": seed})
 
 
 ENSEMBLE_SIZES = (64,) * 16 + (96,) * 16 + (128,) * 16

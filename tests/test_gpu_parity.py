@@ -276,9 +276,10 @@ def test_graph_with_particle_branch_matches_direct(wdm):
     for rep in range(3):
         g.step(10, wl.dt)
         d.step(10, wl.dt)
-        check_l2(g.get_psi(), d.get_psi(), 1e-6)
+        # the two runs differ only in the order of the atomic deposit sums
+        check_l2(g.get_psi(), d.get_psi(), 1e-5)
         pg, vg = g.get_particles()
         pd, vd = d.get_particles()
-        assert np.max(np.abs(pg - pd)) < 1e-6
+        assert np.max(np.abs(pg - pd)) < 1e-5
     g.close()
     d.close()
