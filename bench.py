@@ -89,6 +89,119 @@ def cpu_baseline(wl, budget_s: float = 20.0):
             "s_per_step": per}
 
 
+def bench_ensemble(args):
+    """48 independent halos on mixed grids (16 x 64^3, 16 x 96^3, 16 x 128^3), 1e4
+    Plummer particles each, advanced together by one captured step with per-member
+    dt = 0.2 dx_i^2."""
+    import torch
+
+    from paper_2606_25026_amd import inputs, wdm
+
+    members = [inputs.ensemble_member(seed=s, n=n, n_particles=10_000)
+               for s, n in enumerate(inputs.ENSEMBLE_SIZES)]
+    cfgs = [wdm.make_config(m.n, n_particles=m.n_particles, particle_mass=m.particle_mass)
+            for m in members]
+    plan = wdm.Plan(cfgs)
+    h = plan.handle
+    keep = []
+    for i, m in enumerate(members):
+        psi = torch.from_numpy(m.psi.astype(np.complex64)).cuda()
+        pos = torch.from_numpy(m.pos).cuda()
+        vel = torch.from_numpy(m.vel).cuda()
+        keep.append((psi, pos, vel))
+        wdm.wdm_set_state(h, i, psi, pos, vel)
+        wdm.wdm_set_member_dt(h, i, m.dt)
+    cells = sum(m.n ** 3 for m in members)
+    parts = sum(m.n_particles for m in members)
+    wdm.wdm_step(h, args.warmup, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wdm.wdm_step(h, args.steps, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    step_bytes = STEP_BYTES_PER_CELL * cells + STEP_BYTES_PER_PARTICLE * parts
+    gbs = step_bytes / (ms * 1e-3) / 1e9
+    out = {"metric": "aggregate grid cell-updates/s, 48-member mixed-size ensemble",
+           "value": cells * args.steps / el, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+           "data": "synthetic",
+           "config": {"workload": "ensemble 16x64^3 + 16x96^3 + 16x128^3, 1e4 particles each",
+                      "members": len(members), "cells": cells, "particles": parts},
+           "step_roofline": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS}}
+    print(json.dumps(out))
+    plan.close()
+
+
+def bench_precision(args):
+    """Precision study: complex64 with FP64 arguments vs complex128 at 512^3, and
+    both against the FP64 oracle on the 128^3 sub-box (sampled reference)."""
+    import math
+
+    import torch
+
+    from paper_2606_25026_amd import inputs, wdm
+
+    res = {}
+    # --- sub-box vs oracle
+    g = np.load(ROOT / "tests" / "golden" / "subbox_128_steps2000.npz")
+    n, L, steps = int(g["n"]), float(g["L"]), int(g["steps"])
+    psi0 = inputs.grf_soliton(n, L=L, k0=16.0 * 2 * math.pi, rc=0.03, rho_c=50.0, seed=int(g["seed"]))
+    for prec, dt_ in ((0, torch.complex64), (1, torch.complex128)):
+        plan = wdm.Plan(wdm.make_config(n, L=L, precision=prec))
+        x = torch.from_numpy(psi0).to(dt_).cuda()
+        wdm.wdm_set_state(plan.handle, 0, x)
+        e0 = wdm.wdm_energy(plan.handle, 0)
+        wdm.wdm_step(plan.handle, steps, float(g["dt"]))
+        out = torch.empty_like(x)
+        wdm.wdm_get_psi(plan.handle, 0, out)
+        e1 = wdm.wdm_energy(plan.handle, 0)
+        got = out.cpu().numpy().ravel()[g["cells"]].astype(np.complex128)
+        res[f"subbox128_{'c64' if prec == 0 else 'c128'}"] = {
+            "rel_l2_vs_oracle": float(np.linalg.norm(got - g["psi"]) / np.linalg.norm(g["psi"])),
+            "mass_drift": e1["mass"] / e0["mass"] - 1,
+            "energy_drift": e1["e_total"] / e0["e_total"] - 1,
+            "oracle_mass_drift": float(g["mass1"] / g["mass0"] - 1),
+            "oracle_energy_drift": float(g["etot1"] / g["etot0"] - 1)}
+        plan.close()
+        del x, out
+    # --- 512^3: complex64 vs complex128
+    n = args.n if args.n != 256 else 512
+    psi0 = inputs.grf_soliton(n, L=1.0, k0=16.0 * 2 * math.pi, rc=0.03, rho_c=50.0, seed=0)
+    dt = 0.2 / n ** 2
+    outs = {}
+    for prec, dt_ in ((0, torch.complex64), (1, torch.complex128)):
+        plan = wdm.Plan(wdm.make_config(n, precision=prec))
+        x = torch.from_numpy(psi0).to(dt_).cuda()
+        wdm.wdm_set_state(plan.handle, 0, x)
+        e0 = wdm.wdm_energy(plan.handle, 0)
+        wdm.wdm_step(plan.handle, 5, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wdm.wdm_step(plan.handle, args.precision_steps, dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        e1 = wdm.wdm_energy(plan.handle, 0)
+        wdm.wdm_get_psi(plan.handle, 0, x)
+        outs[prec] = x
+        res[f"grid{n}_{'c64' if prec == 0 else 'c128'}"] = {
+            "ms_per_step": el * 1e3 / args.precision_steps,
+            "cell_updates_per_s": n ** 3 * args.precision_steps / el,
+            "mass_drift": e1["mass"] / e0["mass"] - 1,
+            "energy_drift": e1["e_total"] / e0["e_total"] - 1}
+        plan.close()
+    d = outs[0].to(torch.complex128) - outs[1]
+    res[f"grid{n}_c64_vs_c128_rel_l2"] = float(torch.linalg.vector_norm(d) /
+                                               torch.linalg.vector_norm(outs[1]))
+    v = res[f"grid{n}_c64"]["cell_updates_per_s"]
+    print(json.dumps({"metric": f"precision study: complex64 (FP64 arguments) vs complex128 "
+                                f"after {steps} steps", "value": v, "unit": "cell-updates/s",
+                      "n_gpus": 1, "steps": args.precision_steps, "dtype": "c64",
+                      "data": "synthetic", "higher_is_better": True, "results": res}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +213,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel HIP events")
+    ap.add_argument("--workload", choices=["halo", "ensemble", "precision"], default="halo")
+    ap.add_argument("--precision-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -111,6 +226,10 @@ def main():
     from paper_2606_25026_amd import inputs, wdm
 
     wdm.load()
+    if args.workload == "ensemble":
+        return bench_ensemble(args)
+    if args.workload == "precision":
+        return bench_precision(args)
     dev = torch.device("cuda:0")
     wl = inputs.coupled_halo(n=args.n, n_particles=args.particles, seed=0)
     n3 = args.n ** 3
@@ -135,25 +254,26 @@ def main():
 
     wdm.wdm_step(h, args.warmup, wl.dt)
     torch.cuda.synchronize()
-    if not args.no_profile:
-        wdm.wdm_profile_read(h)          # clear
-        wdm.wdm_profile(h, True)
-    torch.cuda.synchronize()
+    # timed region: K steps, captured-graph replay, synchronised on both sides
     t0 = time.perf_counter()
     wdm.wdm_step(h, args.steps, wl.dt)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # per-kernel durations: the same K steps again, every launch bracketed by
+    # HIP events on the stream it runs on (direct launches; the particle kernel
+    # still runs on its own stream, overlapping the y/x/y passes)
     stats = []
+    elapsed_prof = None
     if not args.no_profile:
+        wdm.wdm_profile_read(h)          # clear
+        wdm.wdm_profile(h, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wdm.wdm_step(h, args.steps, wl.dt)
+        torch.cuda.synchronize()
+        elapsed_prof = time.perf_counter() - t0
         wdm.wdm_profile(h, False)
         stats = wdm.wdm_profile_read(h)
-    # the same number of steps again with captured graphs and no per-kernel
-    # events, for comparison with the profiled timed region
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    wdm.wdm_step(h, args.steps, wl.dt)
-    torch.cuda.synchronize()
-    elapsed_graph = time.perf_counter() - t0
     e1 = wdm.wdm_energy(h, 0)
     ms_per_step = elapsed * 1e3 / args.steps
     value = n3 * args.steps / elapsed
@@ -170,7 +290,7 @@ def main():
         else:
             alg = None
         per_kernel[nm] = {"launches": s["launches"], "avg_us": avg_ms * 1e3,
-                          "share": s["total_ms"] / (elapsed * 1e3),
+                          "share": s["total_ms"] / (elapsed_prof * 1e3),
                           "gbs": (alg / (avg_ms * 1e-3) / 1e9) if alg else None}
     grid_kernels = [s for s in stats if s["name"] in BYTES_PER_CELL]
     if grid_kernels:
@@ -213,9 +333,9 @@ def main():
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
                           "copy_kernel_gbs": copy_gbs},
         "per_kernel": per_kernel,
-        "profiled": not args.no_profile,
-        "unprofiled_graph_replay": {"ms_per_step": elapsed_graph * 1e3 / args.steps,
-                                    "value": n3 * args.steps / elapsed_graph},
+        "timing": "value: captured-graph replay, no per-kernel events; per_kernel and "
+                  "roofline: HIP events around every launch over an equal profiled region",
+        "profiled_region_ms_per_step": (elapsed_prof * 1e3 / args.steps) if elapsed_prof else None,
         "mass_drift": e1["mass"] / e0["mass"] - 1.0,
         "cpu_baseline": cpu,
     }

@@ -166,6 +166,66 @@ wdm_status wdm_profile_read(wdm_plan* plan, wdm_kernel_stat* out, int32_t cap, i
 wdm_status wdm_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps,
                               void* hip_stream, double* ms_per_copy);
 
+/* ---- spectral utilities of the learned-corrector workload -------------- */
+
+/* Spectral restriction of a fine member's psi to the coarse member's grid
+ * (cubic grids, same box, nc < nf): keep the modes with |m_i| < nc/2 on every
+ * axis (the coarse Nyquist planes are dropped) so point values of
+ * band-limited fields are preserved; write the coarse field to psi_out (dev,
+ * nc^3 complex of the plans' precision).  Both plans must share a stream.  Uses
+ * both plans' scratch space. */
+wdm_status wdm_restrict(wdm_plan* fine, int32_t fine_member, wdm_plan* coarse,
+                        int32_t coarse_member, void* psi_out);
+
+/* Shell power spectrum of the density contrast delta = |psi|^2 / mean - 1 on a
+ * cubic grid: shell b = round(|m|) (integer mode vector m), pk[b] = mean over
+ * the shell of |delta_k|^2 / N^2 (N = n^3), counts[b] = modes in the shell
+ * (host out, nbins entries each; counts may be NULL).  FP64 sums.
+ * Synchronises. */
+wdm_status wdm_power_spectrum(wdm_plan* plan, int32_t member, int32_t nbins, double* pk,
+                              int64_t* counts);
+
+/* ---- learned corrector ----------------------------------------------------
+ * A three-layer 3x3x3 convolution network on an n^3 periodic grid:
+ * 3 -> 16 (ReLU) -> 16 (ReLU) -> 2 channels, circular padding.  Weights and
+ * activations are BF16 on the matrix cores with FP32 accumulation; FP32
+ * master parameters, gradients and Adam moments live in the network
+ * workspace.  Parameter vector layout (wdm_net_param_count floats), per layer
+ * l in order: w_l[cout][cin][27] then b_l[cout], tap index
+ * (dx+1)*9 + (dy+1)*3 + (dz+1) for neighbour (i+dx, j+dy, k+dz).  Inputs are
+ * f32 [n^3][3], outputs f32 [n^3][2] (channels last, C order cells). */
+typedef struct wdm_net wdm_net;
+
+int32_t wdm_net_param_count(void);
+size_t wdm_net_workspace_bytes(int32_t n);
+/* Parameters start at zero; set them with wdm_net_set_params. */
+wdm_status wdm_net_create(int32_t n, void* workspace, size_t workspace_bytes, void* hip_stream,
+                          wdm_net** out);
+wdm_status wdm_net_destroy(wdm_net* net);
+/* Host in / out, synchronous; set_params also resets the Adam state. */
+wdm_status wdm_net_set_params(wdm_net* net, const float* params);
+wdm_status wdm_net_get_params(wdm_net* net, float* params);
+wdm_status wdm_net_get_grads(wdm_net* net, float* grads);
+/* Forward pass; keeps the activations for a following backward pass.  y may
+ * be NULL (output kept internally). */
+wdm_status wdm_net_forward(wdm_net* net, const float* x, float* y);
+/* Backward pass from dL/dy (dev f32 [n^3][2]) of the last forward pass:
+ * overwrites the parameter gradients. */
+wdm_status wdm_net_backward(wdm_net* net, const float* dy);
+/* Mean-squared error of the last forward output against target (dev f32
+ * [n^3][2]), its backward pass, and the loss (host out, may be NULL;
+ * synchronises when given). */
+wdm_status wdm_net_mse_backward(wdm_net* net, const float* target, double* loss);
+/* One Adam step on the FP32 master parameters (bias-corrected). */
+wdm_status wdm_net_adam(wdm_net* net, double lr, double b1, double b2, double eps);
+/* Apply the corrector to a complex64 member of the same grid: inputs
+ * (Re psi * s_psi, Im psi * s_psi, Phi * s_phi), psi += s_out * output, psi
+ * rescaled to its previous FP64 mass, and the potential rebuilt from the
+ * corrected state (particles redeposited).  The network and the plan must
+ * share a stream. */
+wdm_status wdm_net_apply(wdm_net* net, wdm_plan* plan, int32_t member, double s_psi,
+                         double s_phi, double s_out);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* wdm_last_error(void);
 

@@ -15,7 +15,8 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libwdm.so"
 OBJ = HERE / "_build"
-SOURCES = ["passes.hip", "particles.hip", "reduce.hip", "capi.hip"]
+SOURCES = ["passes.hip", "particles.hip", "reduce.hip", "corrector.hip", "spectral.hip",
+           "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -14,6 +14,34 @@
 #include "wdm_internal.hpp"
 
 namespace wdm {
+// corrector (corrector.hip)
+hipError_t conv_forward_layer(hipStream_t s, int layer, const uint16_t* in, const uint16_t* w,
+                              const float* b, void* out, int n);
+hipError_t conv_backward_data(hipStream_t s, int layer, const uint16_t* dz, const uint16_t* wbwd,
+                              const uint16_t* act_in, uint16_t* dact, int n);
+hipError_t conv_backward_weight(hipStream_t s, int layer, const uint16_t* dz,
+                                const uint16_t* act_in, float* part, int nblocks, float* out,
+                                int n);
+int wgrad_row(int layer);
+hipError_t net_pack_input(hipStream_t s, const float* x, uint16_t* y, int64_t cells, int cin,
+                          int cp);
+hipError_t net_mse(hipStream_t s, const float* y, const float* t, uint16_t* dy, double* part,
+                   double* out, int64_t cells, int cout, int cp);
+hipError_t net_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int n, float lr,
+                    float b1, float b2, float eps, float c1, float c2);
+hipError_t net_pack_weights(hipStream_t s, const float* w, uint16_t* fwd, uint16_t* bwd, int cin,
+                            int cout, int cpin, int cpout);
+hipError_t net_state_inputs(hipStream_t s, const float* psi, const float* phi, float* x,
+                            int64_t cells, float s_psi, float s_phi);
+hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, float s_out,
+                           double* part, double* mass_before, double* mass_after);
+hipError_t net_unpack_grads(hipStream_t s, const float* sum, float* gw, float* gb, int cin,
+                            int cout, int cpin, int row);
+hipError_t launch_restrict_modes(hipStream_t s, const void* fine, void* coarse, int nf, int nc,
+                                 int prec);
+hipError_t launch_contrast(const Launch& L, int prec, int64_t n);
+hipError_t launch_shells(const Launch& L, int prec, int nbins, double* part, double* out);
+size_t shells_partial_doubles();
 int64_t axis_tiles(int n, int64_t pencils, int prec);
 hipError_t launch_scale_complex(hipStream_t s, void* p, int64_t n, double scale, int prec);
 int sort_blocks(int64_t np);
@@ -50,7 +78,7 @@ struct MemberLayout {
 struct Layout {
     std::vector<MemberLayout> m;
     std::map<int, size_t> tw;     // axis length -> twiddle table offset
-    size_t scratch = 0, partials = 0, table = 0, total = 0;
+    size_t scratch = 0, partials = 0, table = 0, pk = 0, total = 0;
     int64_t partial_rows = 0;
 };
 
@@ -147,6 +175,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
     L.partial_rows = std::max<int64_t>(kRedBlocks, (maxplane + 7) / 8);
     L.partials = c.take(L.partial_rows * kRedFields * sizeof(double));
     L.table = c.take(n * sizeof(MemberDev));
+    L.pk = c.take(shells_partial_doubles() * sizeof(double));
     L.total = (c.off + kAlign - 1) / kAlign * kAlign;
     return true;
 }
@@ -791,6 +820,351 @@ wdm_status wdm_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t 
     hipEventDestroy(a);
     hipEventDestroy(b);
     *ms_per_copy = double(ms) / reps;
+    return WDM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// learned corrector network
+// ===========================================================================
+namespace {
+
+constexpr int kNetLayers = 3;
+constexpr int kNetCin[kNetLayers] = {3, 16, 16};
+constexpr int kNetCout[kNetLayers] = {16, 16, 2};
+constexpr int kNetCpIn[kNetLayers] = {4, 16, 16};    // padded input channels
+constexpr int kNetCpOut[kNetLayers] = {16, 16, 4};   // padded output channels
+constexpr int kNetWgradBlocks = 256;
+
+int net_layer_params(int l) { return kNetCout[l] * kNetCin[l] * 27 + kNetCout[l]; }
+int net_params() {
+    int p = 0;
+    for (int l = 0; l < kNetLayers; ++l) p += net_layer_params(l);
+    return p;
+}
+int net_kpad(int cp) { return (27 * cp + 15) / 16 * 16; }
+
+struct NetLayout {
+    size_t params, grads, am, av, wf[3], wb[3], x0, a1, a2, y, dy, d2, d1, xin, wpart, wsum[3],
+        dpart, scal, total;
+};
+
+NetLayout net_layout(int n) {
+    const int64_t cells = int64_t(n) * n * n;
+    const int P = net_params();
+    NetLayout L;
+    Carver c;
+    L.params = c.take(P * 4);
+    L.grads = c.take(P * 4);
+    L.am = c.take(P * 4);
+    L.av = c.take(P * 4);
+    for (int l = 0; l < kNetLayers; ++l) {
+        L.wf[l] = c.take(16 * net_kpad(kNetCpIn[l]) * 2);
+        L.wb[l] = c.take(16 * net_kpad(kNetCpOut[l]) * 2);
+    }
+    L.x0 = c.take(cells * 4 * 2);
+    L.a1 = c.take(cells * 16 * 2);
+    L.a2 = c.take(cells * 16 * 2);
+    L.y = c.take(cells * 2 * 4);
+    L.dy = c.take(cells * 4 * 2);
+    L.d2 = c.take(cells * 16 * 2);
+    L.d1 = c.take(cells * 16 * 2);
+    L.xin = c.take(cells * 3 * 4);
+    L.wpart = c.take(size_t(kNetWgradBlocks) * 16 * wgrad_row(1) * 4);
+    for (int l = 0; l < kNetLayers; ++l) L.wsum[l] = c.take(16 * wgrad_row(l) * 4);
+    L.dpart = c.take(1024 * 8);
+    L.scal = c.take(8 * 8);
+    L.total = (c.off + kAlign - 1) / kAlign * kAlign;
+    return L;
+}
+
+}  // namespace
+
+struct wdm_net {
+    hipStream_t stream = nullptr;
+    int n = 0;
+    int64_t cells = 0;
+    uint8_t* ws = nullptr;
+    NetLayout L;
+    int64_t adam_t = 0;
+    bool have_forward = false;
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    size_t param_off(int l) const {
+        size_t o = 0;
+        for (int i = 0; i < l; ++i) o += size_t(net_layer_params(i));
+        return o;
+    }
+};
+
+namespace {
+
+hipError_t net_repack(wdm_net* net) {
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < kNetLayers && e == hipSuccess; ++l)
+        e = net_pack_weights(net->stream, net->at<float>(net->L.params) + net->param_off(l),
+                             net->at<uint16_t>(net->L.wf[l]), net->at<uint16_t>(net->L.wb[l]),
+                             kNetCin[l], kNetCout[l], kNetCpIn[l], kNetCpOut[l]);
+    return e;
+}
+
+hipError_t net_run_forward(wdm_net* net, const float* x, float* y) {
+    hipStream_t s = net->stream;
+    hipError_t e;
+    if ((e = net_pack_input(s, x, net->at<uint16_t>(net->L.x0), net->cells, 3, 4)) != hipSuccess)
+        return e;
+    const uint16_t* in[3] = {net->at<uint16_t>(net->L.x0), net->at<uint16_t>(net->L.a1),
+                             net->at<uint16_t>(net->L.a2)};
+    void* out[3] = {net->at<uint16_t>(net->L.a1), net->at<uint16_t>(net->L.a2),
+                    net->at<float>(net->L.y)};
+    for (int l = 0; l < kNetLayers; ++l) {
+        const float* b = net->at<float>(net->L.params) + net->param_off(l) +
+                         size_t(kNetCout[l]) * kNetCin[l] * 27;
+        if ((e = conv_forward_layer(s, l, in[l], net->at<uint16_t>(net->L.wf[l]), b, out[l],
+                                    net->n)) != hipSuccess)
+            return e;
+    }
+    if (y && y != net->at<float>(net->L.y))
+        e = hipMemcpyAsync(y, net->at<float>(net->L.y), size_t(net->cells) * 2 * 4,
+                           hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+// dy (bf16 [cells][4]) must be in place; accumulates nothing (grads overwritten)
+hipError_t net_run_backward(wdm_net* net) {
+    hipStream_t s = net->stream;
+    hipError_t e;
+    const int n = net->n;
+    uint16_t* dz[3] = {net->at<uint16_t>(net->L.d1), net->at<uint16_t>(net->L.d2),
+                       net->at<uint16_t>(net->L.dy)};
+    const uint16_t* act[3] = {net->at<uint16_t>(net->L.x0), net->at<uint16_t>(net->L.a1),
+                              net->at<uint16_t>(net->L.a2)};
+    for (int l = kNetLayers - 1; l >= 0; --l) {
+        if ((e = conv_backward_weight(s, l, dz[l], act[l], net->at<float>(net->L.wpart),
+                                      kNetWgradBlocks, net->at<float>(net->L.wsum[l]), n)) !=
+            hipSuccess)
+            return e;
+        float* gw = net->at<float>(net->L.grads) + net->param_off(l);
+        float* gb = gw + size_t(kNetCout[l]) * kNetCin[l] * 27;
+        if ((e = net_unpack_grads(s, net->at<float>(net->L.wsum[l]), gw, gb, kNetCin[l],
+                                  kNetCout[l], kNetCpIn[l], wgrad_row(l))) != hipSuccess)
+            return e;
+        if (l > 0 &&
+            (e = conv_backward_data(s, l, dz[l], net->at<uint16_t>(net->L.wb[l]), act[l],
+                                    dz[l - 1], n)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t wdm_net_param_count(void) { return net_params(); }
+
+size_t wdm_net_workspace_bytes(int32_t n) {
+    if (n < 4 || n > 512) {
+        g_err = "grid edge must be in [4, 512]";
+        return 0;
+    }
+    return net_layout(n).total;
+}
+
+wdm_status wdm_net_create(int32_t n, void* workspace, size_t bytes, void* hip_stream,
+                          wdm_net** out) {
+    if (!out) return fail(WDM_EINVAL, "out is null");
+    *out = nullptr;
+    if (n < 4 || n > 512) return fail(WDM_EINVAL, "grid edge must be in [4, 512]");
+    const NetLayout L = net_layout(n);
+    if (!workspace) return fail(WDM_EINVAL, "workspace is null");
+    if (bytes < L.total) return fail(WDM_ENOMEM, "network workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(WDM_EINVAL, "workspace must be 256-byte aligned");
+    auto* net = new wdm_net();
+    net->stream = static_cast<hipStream_t>(hip_stream);
+    net->n = n;
+    net->cells = int64_t(n) * n * n;
+    net->ws = static_cast<uint8_t*>(workspace);
+    net->L = L;
+    const int P = net_params();
+    hipError_t e = launch_zero(net->stream, net->ws + L.params, size_t(P) * 4 * 4);
+    if (e == hipSuccess) e = net_repack(net);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) {
+        delete net;
+        return fail(WDM_EDEVICE, std::string("network initialisation: ") + hipGetErrorString(e));
+    }
+    *out = net;
+    return WDM_OK;
+}
+
+wdm_status wdm_net_destroy(wdm_net* net) {
+    if (!net) return fail(WDM_EINVAL, "null network");
+    hipStreamSynchronize(net->stream);
+    delete net;
+    return WDM_OK;
+}
+
+wdm_status wdm_net_set_params(wdm_net* net, const float* params) {
+    if (!net || !params) return fail(WDM_EINVAL, "null argument");
+    HIPCHK(hipMemcpy(net->ws + net->L.params, params, size_t(net_params()) * 4,
+                     hipMemcpyHostToDevice));
+    HIPCHK(launch_zero(net->stream, net->ws + net->L.am, size_t(net_params()) * 8));
+    net->adam_t = 0;
+    HIPCHK(net_repack(net));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_get_params(wdm_net* net, float* params) {
+    if (!net || !params) return fail(WDM_EINVAL, "null argument");
+    HIPCHK(hipStreamSynchronize(net->stream));
+    HIPCHK(hipMemcpy(params, net->ws + net->L.params, size_t(net_params()) * 4,
+                     hipMemcpyDeviceToHost));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_get_grads(wdm_net* net, float* grads) {
+    if (!net || !grads) return fail(WDM_EINVAL, "null argument");
+    HIPCHK(hipStreamSynchronize(net->stream));
+    HIPCHK(hipMemcpy(grads, net->ws + net->L.grads, size_t(net_params()) * 4,
+                     hipMemcpyDeviceToHost));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_forward(wdm_net* net, const float* x, float* y) {
+    if (!net || !x) return fail(WDM_EINVAL, "null argument");
+    HIPCHK(net_run_forward(net, x, y));
+    net->have_forward = true;
+    return WDM_OK;
+}
+
+wdm_status wdm_net_backward(wdm_net* net, const float* dy) {
+    if (!net || !dy) return fail(WDM_EINVAL, "null argument");
+    if (!net->have_forward) return fail(WDM_ESTATE, "backward needs a forward pass first");
+    HIPCHK(net_pack_input(net->stream, dy, net->at<uint16_t>(net->L.dy), net->cells, 2, 4));
+    HIPCHK(net_run_backward(net));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_mse_backward(wdm_net* net, const float* target, double* loss) {
+    if (!net || !target) return fail(WDM_EINVAL, "null argument");
+    if (!net->have_forward) return fail(WDM_ESTATE, "backward needs a forward pass first");
+    double* scal = net->at<double>(net->L.scal);
+    HIPCHK(net_mse(net->stream, net->at<float>(net->L.y), target, net->at<uint16_t>(net->L.dy),
+                   net->at<double>(net->L.dpart), scal, net->cells, 2, 4));
+    HIPCHK(net_run_backward(net));
+    if (loss) {
+        HIPCHK(hipMemcpyAsync(loss, scal, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+        HIPCHK(hipStreamSynchronize(net->stream));
+    }
+    return WDM_OK;
+}
+
+wdm_status wdm_net_adam(wdm_net* net, double lr, double b1, double b2, double eps) {
+    if (!net) return fail(WDM_EINVAL, "null network");
+    if (!(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(WDM_EINVAL, "bad Adam hyper-parameters");
+    net->adam_t++;
+    const double c1 = 1.0 - std::pow(b1, double(net->adam_t));
+    const double c2 = 1.0 - std::pow(b2, double(net->adam_t));
+    HIPCHK(net_adam(net->stream, net->at<float>(net->L.params), net->at<float>(net->L.grads),
+                    net->at<float>(net->L.am), net->at<float>(net->L.av), net_params(), float(lr),
+                    float(b1), float(b2), float(eps), float(c1), float(c2)));
+    HIPCHK(net_repack(net));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_apply(wdm_net* net, wdm_plan* p, int32_t member, double s_psi, double s_phi,
+                         double s_out) {
+    if (!net) return fail(WDM_EINVAL, "null network");
+    if (wdm_status st = check_member(p, member)) return st;
+    const wdm_config& c = p->cfg[member];
+    if (p->prec != WDM_C64) return fail(WDM_EUNSUPPORTED, "corrector needs a complex64 plan");
+    if (c.nx != net->n || c.ny != net->n || c.nz != net->n)
+        return fail(WDM_EINVAL, "network grid differs from the member's grid");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    if (net->stream != p->stream) return fail(WDM_EINVAL, "network and plan must share a stream");
+    const MemberDev& m = p->host[p->dev_index[member]];
+    const Launch L = one(p, member);
+    float* psi = static_cast<float*>(m.psi);
+    HIPCHK(net_state_inputs(p->stream, psi, static_cast<const float*>(m.phi),
+                            net->at<float>(net->L.xin), net->cells, float(s_psi), float(s_phi)));
+    HIPCHK(net_run_forward(net, net->at<float>(net->L.xin), nullptr));
+    double* scal = net->at<double>(net->L.scal);
+    HIPCHK(net_apply_delta(p->stream, psi, net->at<float>(net->L.y), net->cells, float(s_out),
+                           net->at<double>(net->L.dpart), scal + 1, scal + 2));
+    // the corrected psi needs its own potential: redeposit the particles and
+    // re-solve Poisson so the state is synchronised again
+    if (c.n_particles > 0) HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick));
+    HIPCHK(potential_from_state(p, L, c));
+    return WDM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// spectral utilities: restriction and shell power spectrum
+// ===========================================================================
+extern "C" {
+
+wdm_status wdm_restrict(wdm_plan* fine, int32_t fmember, wdm_plan* coarse, int32_t cmember,
+                        void* psi_out) {
+    if (wdm_status st = check_member(fine, fmember)) return st;
+    if (wdm_status st = check_member(coarse, cmember)) return st;
+    if (!psi_out) return fail(WDM_EINVAL, "psi_out is null");
+    const wdm_config& f = fine->cfg[fmember];
+    const wdm_config& c = coarse->cfg[cmember];
+    if (f.nx != f.ny || f.nx != f.nz || c.nx != c.ny || c.nx != c.nz)
+        return fail(WDM_EUNSUPPORTED, "restriction needs cubic grids");
+    if (c.nx >= f.nx) return fail(WDM_EINVAL, "the coarse grid must be smaller");
+    if (fine->prec != coarse->prec) return fail(WDM_EINVAL, "plans must share a precision");
+    if (fine->stream != coarse->stream) return fail(WDM_EINVAL, "plans must share a stream");
+    if (!fine->has_state[fmember]) return fail(WDM_ESTATE, "no state set on the fine member");
+    const int prec = fine->prec;
+    const MemberDev& mf = fine->host[fine->dev_index[fmember]];
+    const MemberDev& mc = coarse->host[coarse->dev_index[cmember]];
+    const Launch LF = one(fine, fmember), LC = one(coarse, cmember);
+    const size_t cs = prec ? 16 : 8;
+    HIPCHK(hipMemcpyAsync(mf.scratch, mf.psi, size_t(cells_of(f)) * cs, hipMemcpyDeviceToDevice,
+                          fine->stream));
+    for (int ax = 2; ax >= 0; --ax)
+        HIPCHK(launch_axis_fft(LF, prec, f.nx, f.ny, f.nz, ax, false, 1));
+    HIPCHK(launch_restrict_modes(fine->stream, mf.scratch, mc.scratch, f.nx, c.nx, prec));
+    for (int ax = 0; ax < 3; ++ax)
+        HIPCHK(launch_axis_fft(LC, prec, c.nx, c.ny, c.nz, ax, true, 1));
+    HIPCHK(hipMemcpyAsync(psi_out, mc.scratch, size_t(cells_of(c)) * cs, hipMemcpyDeviceToDevice,
+                          coarse->stream));
+    return WDM_OK;
+}
+
+wdm_status wdm_power_spectrum(wdm_plan* p, int32_t member, int32_t nbins, double* pk,
+                              int64_t* counts) {
+    if (wdm_status st = check_member(p, member)) return st;
+    if (!pk || nbins < 1 || nbins > 1024) return fail(WDM_EINVAL, "need 1 <= nbins <= 1024");
+    const wdm_config& c = p->cfg[member];
+    if (c.nx != c.ny || c.nx != c.nz) return fail(WDM_EUNSUPPORTED, "P(k) needs a cubic grid");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const Launch L = one(p, member);
+    const int64_t n = cells_of(c);
+    HIPCHK(launch_reduce_grid(L, p->prec, n, 0));
+    HIPCHK(launch_reduce_finish(L, 0, kRedBlocks, false));
+    HIPCHK(launch_contrast(L, p->prec, n));
+    for (int ax = 2; ax >= 0; --ax)
+        HIPCHK(launch_axis_fft(L, p->prec, c.nx, c.ny, c.nz, ax, false, 1));
+    double* part = reinterpret_cast<double*>(p->ws + p->layout.pk);
+    double* res = part + shells_partial_doubles() - 2 * 1024;
+    HIPCHK(launch_shells(L, p->prec, nbins, part, res));
+    std::vector<double> host(2 * size_t(nbins));
+    HIPCHK(hipMemcpyAsync(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int b = 0; b < nbins; ++b) {
+        const double cnt = host[nbins + b];
+        pk[b] = cnt > 0 ? host[b] / cnt : 0.0;
+        if (counts) counts[b] = int64_t(cnt);
+    }
     return WDM_OK;
 }
 

@@ -10,6 +10,8 @@
 // one lane per run issues the eight atomic adds.
 #include "wdm_internal.hpp"
 
+#include <algorithm>
+
 namespace wdm {
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -240,11 +242,25 @@ hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos,
 // ---------------------------------------------------------------------------
 constexpr int kSortTile = 4096;   // keys per block: 256 lanes x 16 rounds
 
+// Spread the low 10 bits of v to every third bit.
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Sort key: Morton (bit-interleaved) index of the particle's cell, so that
+// particles close in space are close in memory in all three directions and a
+// work-group's force gathers and deposits stay within a compact patch.
 __global__ void k_make_keys(MemberDev m) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= m.np) return;
     const CellW<float> c = cic<float>(m.px[i], m.py[i], m.pz[i], m);
-    m.key_a[i] = uint32_t((int64_t(c.i) * m.ny + c.j) * m.nz + c.k);
+    m.key_a[i] = (spread3(uint32_t(c.i)) << 2) | (spread3(uint32_t(c.j)) << 1) |
+                 spread3(uint32_t(c.k));
     m.idx_a[i] = uint32_t(i);
 }
 
@@ -377,9 +393,9 @@ hipError_t launch_particle_sort(hipStream_t s, const MemberDev& m, const MemberD
     if (m.np <= 1) return hipSuccess;
     const unsigned g = unsigned((m.np + 255) / 256);
     k_make_keys<<<g, 256, 0, s>>>(m);
-    const int64_t ncells = int64_t(m.nx) * m.ny * m.nz;
-    int bits = 0;
-    while ((int64_t(1) << bits) < ncells) ++bits;
+    int axis_bits = 0;
+    while ((1 << axis_bits) < std::max(m.nx, std::max(m.ny, m.nz))) ++axis_bits;
+    const int bits = 3 * axis_bits;   // Morton key width
     const int nb = sort_blocks(m.np);
     uint32_t *ka = m.key_a, *kb = m.key_b, *va = m.idx_a, *vb = m.idx_b;
     for (int shift = 0; shift < bits; shift += 8) {

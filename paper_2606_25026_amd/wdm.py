@@ -69,6 +69,20 @@ _SIGS = {
     "wdm_profile": (C.c_int, [_vp, _i32]),
     "wdm_profile_read": (C.c_int, [_vp, C.POINTER(wdm_kernel_stat), _i32, C.POINTER(_i32)]),
     "wdm_copy_bandwidth": (C.c_int, [_vp, _vp, C.c_size_t, _i32, _vp, C.POINTER(_f64)]),
+    "wdm_restrict": (C.c_int, [_vp, _i32, _vp, _i32, _vp]),
+    "wdm_power_spectrum": (C.c_int, [_vp, _i32, _i32, C.POINTER(_f64), C.POINTER(_i64)]),
+    "wdm_net_param_count": (_i32, []),
+    "wdm_net_workspace_bytes": (C.c_size_t, [_i32]),
+    "wdm_net_create": (C.c_int, [_i32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "wdm_net_destroy": (C.c_int, [_vp]),
+    "wdm_net_set_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "wdm_net_get_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "wdm_net_get_grads": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "wdm_net_forward": (C.c_int, [_vp, _vp, _vp]),
+    "wdm_net_backward": (C.c_int, [_vp, _vp]),
+    "wdm_net_mse_backward": (C.c_int, [_vp, _vp, C.POINTER(_f64)]),
+    "wdm_net_adam": (C.c_int, [_vp, _f64, _f64, _f64, _f64]),
+    "wdm_net_apply": (C.c_int, [_vp, _vp, _i32, _f64, _f64, _f64]),
     "wdm_last_error": (C.c_char_p, []),
 }
 
@@ -212,6 +226,115 @@ def wdm_copy_bandwidth(dst, src, nbytes, reps=20, stream=None) -> float:
     _check(load().wdm_copy_bandwidth(_ptr(dst), _ptr(src), int(nbytes), int(reps),
                                      _stream(stream), C.byref(ms)))
     return ms.value
+
+
+def wdm_restrict(fine, fine_member, coarse, coarse_member, psi_out):
+    _check(load().wdm_restrict(fine, fine_member, coarse, coarse_member, _ptr(psi_out)))
+
+
+def wdm_power_spectrum(plan, member, nbins):
+    import numpy as np
+
+    pk = np.zeros(nbins)
+    cnt = np.zeros(nbins, dtype=np.int64)
+    _check(load().wdm_power_spectrum(plan, member, int(nbins),
+                                     pk.ctypes.data_as(C.POINTER(_f64)),
+                                     cnt.ctypes.data_as(C.POINTER(_i64))))
+    return pk, cnt
+
+
+def wdm_net_param_count() -> int:
+    return int(load().wdm_net_param_count())
+
+
+def wdm_net_workspace_bytes(n) -> int:
+    return int(load().wdm_net_workspace_bytes(int(n)))
+
+
+def wdm_net_create(n, workspace, workspace_bytes=None, stream=None):
+    out = C.c_void_p()
+    nbytes = workspace_bytes if workspace_bytes is not None else workspace.numel() * workspace.element_size()
+    _check(load().wdm_net_create(int(n), _ptr(workspace), nbytes, _stream(stream), C.byref(out)))
+    return out
+
+
+def wdm_net_destroy(net):
+    _check(load().wdm_net_destroy(net))
+
+
+def _f32_host(a):
+    import numpy as np
+
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def wdm_net_set_params(net, params):
+    a, p = _f32_host(params)
+    _check(load().wdm_net_set_params(net, p))
+
+
+def wdm_net_get_params(net):
+    import numpy as np
+
+    a = np.zeros(wdm_net_param_count(), dtype=np.float32)
+    _check(load().wdm_net_get_params(net, a.ctypes.data_as(C.POINTER(C.c_float))))
+    return a
+
+
+def wdm_net_get_grads(net):
+    import numpy as np
+
+    a = np.zeros(wdm_net_param_count(), dtype=np.float32)
+    _check(load().wdm_net_get_grads(net, a.ctypes.data_as(C.POINTER(C.c_float))))
+    return a
+
+
+def wdm_net_forward(net, x, y=None):
+    _check(load().wdm_net_forward(net, _ptr(x), _ptr(y)))
+
+
+def wdm_net_backward(net, dy):
+    _check(load().wdm_net_backward(net, _ptr(dy)))
+
+
+def wdm_net_mse_backward(net, target) -> float:
+    loss = C.c_double()
+    _check(load().wdm_net_mse_backward(net, _ptr(target), C.byref(loss)))
+    return loss.value
+
+
+def wdm_net_adam(net, lr, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load().wdm_net_adam(net, float(lr), float(b1), float(b2), float(eps)))
+
+
+def wdm_net_apply(net, plan, member, s_psi, s_phi, s_out):
+    _check(load().wdm_net_apply(net, plan, int(member), float(s_psi), float(s_phi), float(s_out)))
+
+
+class Net:
+    """Owns a torch workspace and a corrector-network handle."""
+
+    def __init__(self, n, device="cuda"):
+        import torch
+
+        self.n = n
+        nbytes = wdm_net_workspace_bytes(n)
+        if nbytes == 0:
+            raise WdmError(1, wdm_last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = wdm_net_create(n, self.workspace, nbytes)
+
+    def close(self):
+        if self.handle is not None:
+            wdm_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -1,0 +1,179 @@
+"""Learned-corrector kernels and spectral utilities against the FP64 oracle.
+
+The oracle is fed the same BF16-rounded weights, inputs and inter-layer
+activations/gradients the GPU keeps, so the comparison isolates the
+matrix-core arithmetic (FP32 accumulation) from the chosen storage precision.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_25026_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CIN, CH, COUT = 3, 16, 2
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) /
+                 np.linalg.norm(np.asarray(b).ravel()))
+
+
+def split_params(p):
+    """Flat parameter vector -> [(w[cout][cin][27], b[cout])] per layer."""
+    out, o = [], 0
+    for cin, cout in ((CIN, CH), (CH, CH), (CH, COUT)):
+        w = p[o:o + cout * cin * 27].reshape(cout, cin, 27)
+        o += cout * cin * 27
+        b = p[o:o + cout]
+        o += cout
+        out.append((w.astype(np.float64), b.astype(np.float64)))
+    return out
+
+
+def to_cf(x, n):      # [cells][c] -> [c][n][n][n]
+    return np.ascontiguousarray(x.reshape(n, n, n, -1).transpose(3, 0, 1, 2))
+
+
+def to_cl(x):         # [c][n][n][n] -> [cells][c]
+    return np.ascontiguousarray(x.transpose(1, 2, 3, 0).reshape(-1, x.shape[0]))
+
+
+def oracle_forward(orc, params, x, n):
+    layers = split_params(params)
+    a0 = orc.round_bf16(to_cf(x, n))
+    acts = [a0]
+    a = a0
+    for l, (w, b) in enumerate(layers):
+        z = orc.conv3d_fwd(a, orc.round_bf16(w), b)
+        if l < 2:
+            a = orc.round_bf16(np.maximum(z, 0.0))
+            acts.append(a)
+        else:
+            y = z
+    return y, acts
+
+
+def oracle_backward(orc, params, acts, dy):
+    layers = split_params(params)
+    grads = [None] * 3
+    dz = orc.round_bf16(dy)
+    for l in (2, 1, 0):
+        w, b = layers[l]
+        dx, dw, db = orc.conv3d_bwd(acts[l], orc.round_bf16(w), dz, want_dx=l > 0)
+        grads[l] = (dw, db)
+        if l > 0:
+            dz = orc.round_bf16(dx * (acts[l] > 0))
+    return grads
+
+
+def random_params(wdm, rng, scale=0.15):
+    return (rng.standard_normal(wdm.wdm_net_param_count()) * scale).astype(np.float32)
+
+
+def test_conv_forward_and_backward_match_oracle(wdm, orc):
+    n = 16
+    rng = np.random.default_rng(0)
+    net = wdm.Net(n)
+    params = random_params(wdm, rng)
+    wdm.wdm_net_set_params(net.handle, params)
+    x = rng.standard_normal((n ** 3, 3)).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    y = torch.empty((n ** 3, 2), dtype=torch.float32, device="cuda")
+    wdm.wdm_net_forward(net.handle, xt, y)
+    torch.cuda.synchronize()
+    y_ref, acts = oracle_forward(orc, params, x, n)
+    err = rel_l2(to_cf(y.cpu().numpy(), n), y_ref)
+    print(f"conv3d forward vs oracle: rel L2 {err:.2e}")
+    assert err < 1e-3
+    dy = rng.standard_normal((n ** 3, 2)).astype(np.float32) * 1e-3
+    wdm.wdm_net_backward(net.handle, torch.from_numpy(dy).cuda())
+    g = wdm.wdm_net_get_grads(net.handle)
+    ref = oracle_backward(orc, params, acts, to_cf(dy, n))
+    gl = split_params(g)
+    for l in range(3):
+        ew = rel_l2(gl[l][0], ref[l][0])
+        eb = rel_l2(gl[l][1], ref[l][1])
+        print(f"layer {l}: dW rel L2 {ew:.2e}, db rel L2 {eb:.2e}")
+        assert ew < 1e-3 and eb < 1e-3
+    net.close()
+
+
+def test_mse_backward_and_adam(wdm):
+    n = 8
+    rng = np.random.default_rng(1)
+    net = wdm.Net(n)
+    params = random_params(wdm, rng)
+    wdm.wdm_net_set_params(net.handle, params)
+    x = torch.from_numpy(rng.standard_normal((n ** 3, 3)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((n ** 3, 2)).astype(np.float32)).cuda()
+    y = torch.empty_like(t)
+    wdm.wdm_net_forward(net.handle, x, y)
+    loss = wdm.wdm_net_mse_backward(net.handle, t)
+    ref = float(((y - t) ** 2).double().mean())
+    assert loss == pytest.approx(ref, rel=1e-6)
+    g = wdm.wdm_net_get_grads(net.handle)
+    wdm.wdm_net_adam(net.handle, 1e-3)
+    p1 = wdm.wdm_net_get_params(net.handle)
+    # first Adam step: p - lr * g / (|g| + eps) after bias correction
+    expect = params - 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(p1 - expect)) < 2e-6
+    # the loss goes down along the step
+    wdm.wdm_net_forward(net.handle, x, y)
+    loss2 = wdm.wdm_net_mse_backward(net.handle, t)
+    assert loss2 < loss
+    net.close()
+
+
+def test_restriction_and_power_spectrum_match_oracle(wdm, orc):
+    nf, nc = 64, 32
+    psi = inputs.grf_soliton(nf, rc=0.08, seed=2)
+    fine = wdm.Plan(wdm.make_config(nf, four_pi_G=0.0))
+    coarse = wdm.Plan(wdm.make_config(nc, four_pi_G=0.0))
+    x = torch.from_numpy(psi.astype(np.complex64)).cuda()
+    wdm.wdm_set_state(fine.handle, 0, x)
+    out = torch.empty((nc,) * 3, dtype=torch.complex64, device="cuda")
+    wdm.wdm_restrict(fine.handle, 0, coarse.handle, 0, out)
+    torch.cuda.synchronize()
+    ref = orc.restrict(psi.astype(np.complex64).astype(np.complex128), nc)
+    err = rel_l2(out.cpu().numpy().astype(np.complex128), ref)
+    print(f"restriction 64^3 -> 32^3: rel L2 {err:.2e}")
+    assert err < 1e-6
+    pk, cnt = wdm.wdm_power_spectrum(fine.handle, 0, 32)
+    rho = np.abs(psi.astype(np.complex64).astype(np.complex128)) ** 2
+    pk_ref, cnt_ref = orc.power_spectrum(rho, 32)
+    assert np.array_equal(cnt, cnt_ref)
+    sel = pk_ref > 1e-12 * pk_ref.max()
+    assert np.max(np.abs(pk[sel] / pk_ref[sel] - 1)) < 1e-4
+    fine.close()
+    coarse.close()
+
+
+def test_apply_keeps_mass_and_rebuilds_potential(wdm, orc):
+    n = 32
+    wl = inputs.coupled_halo(n=n, n_particles=500, seed=5, steps=0)
+    plan = wdm.Plan(wdm.make_config(n, n_particles=500, particle_mass=wl.particle_mass))
+    psi = torch.from_numpy(wl.psi.astype(np.complex64)).cuda()
+    wdm.wdm_set_state(plan.handle, 0, psi, torch.from_numpy(wl.pos).cuda(),
+                      torch.from_numpy(wl.vel).cuda())
+    net = wdm.Net(n)
+    wdm.wdm_net_set_params(net.handle, random_params(wdm, np.random.default_rng(3), 0.05))
+    e0 = wdm.wdm_energy(plan.handle, 0)
+    wdm.wdm_net_apply(net.handle, plan.handle, 0, 1.0, 1.0, 0.05)
+    e1 = wdm.wdm_energy(plan.handle, 0)
+    out = torch.empty_like(psi)
+    wdm.wdm_get_psi(plan.handle, 0, out)
+    phi = torch.empty((n,) * 3, dtype=torch.float32, device="cuda")
+    wdm.wdm_potential(plan.handle, 0, phi)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.complex128)
+    assert abs(e1["mass"] / e0["mass"] - 1) < 1e-6
+    assert rel_l2(got, wl.psi) > 1e-4                     # it did change psi
+    cfg = orc.make_config((n,) * 3, n_particles=500, particle_mass=wl.particle_mass)
+    phi_ref = orc.potential(cfg, got, wl.pos.astype(np.float64))
+    assert rel_l2(phi.cpu().numpy(), phi_ref) < 1e-5
+    net.close()
+    plan.close()
