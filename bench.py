@@ -202,6 +202,27 @@ def bench_precision(args):
                       "data": "synthetic", "higher_is_better": True, "results": res}))
 
 
+def bench_learned(args):
+    """Learned coarse corrector: 128^3 coarse + corrector vs the 256^3 plain solve."""
+    from paper_2606_25026_amd import learned
+
+    cfg = learned.LearnedConfig()
+    if args.learned_small:
+        cfg = learned.LearnedConfig(n_fine=64, n_coarse=32, n_particles=10_000,
+                                    train_seeds=tuple(range(6)), windows=4,
+                                    heldout_seeds=(100, 101), epochs=30)
+    res = learned.run(cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps({
+        "metric": "seconds per simulated time unit: plain fine solve / (coarse + corrector)",
+        "value": res["effective_speedup"], "unit": "x", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "c64 solver, bf16 corrector", "data": "synthetic",
+        "config": {"workload": f"learned corrector {cfg.n_coarse}^3 coarse vs {cfg.n_fine}^3 fine, "
+                               f"{cfg.n_particles} particles, {res['pairs']} training pairs",
+                   "every": cfg.every, "judge_steps": cfg.judge_steps},
+        "results": {k: v for k, v in res.items() if k != "train_losses"},
+        "train_loss_first_last": [res["train_losses"][0], res["train_losses"][-1]]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,7 +234,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel HIP events")
-    ap.add_argument("--workload", choices=["halo", "ensemble", "precision"], default="halo")
+    ap.add_argument("--workload", choices=["halo", "ensemble", "precision", "learned"],
+                    default="halo")
+    ap.add_argument("--learned-small", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -230,6 +253,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     dev = torch.device("cuda:0")
     wl = inputs.coupled_halo(n=args.n, n_particles=args.particles, seed=0)
     n3 = args.n ** 3

@@ -165,7 +165,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         m.key_b = c.take(np * 4);
         m.idx_a = c.take(np * 4);
         m.idx_b = c.take(np * 4);
-        m.hist = c.take(int64_t(256) * std::max(1, sort_blocks(np)) * 4);
+        m.hist = c.take(int64_t(256) * (std::max(1, sort_blocks(np)) + 1) * 4);
         for (int len : {g.nx, g.ny, g.nz})
             if (!L.tw.count(len)) L.tw[len] = 0;
     }
@@ -353,6 +353,12 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.lz = c.lz;
         m.eta = c.hbar_over_m;
         m.four_pi_G = c.four_pi_G;
+        m.inv_dx = double(c.nx) / c.lx;
+        m.inv_dy = double(c.ny) / c.ly;
+        m.inv_dz = double(c.nz) / c.lz;
+        m.inv_lx = 1.0 / c.lx;
+        m.inv_ly = 1.0 / c.ly;
+        m.inv_lz = 1.0 / c.lz;
         m.dt = reinterpret_cast<double*>(ws + ml.dt);
         m.np = c.n_particles;
         float** pp[6] = {&m.px, &m.py, &m.pz, &m.vx, &m.vy, &m.vz};
@@ -989,7 +995,9 @@ wdm_status wdm_net_create(int32_t n, void* workspace, size_t bytes, void* hip_st
     net->ws = static_cast<uint8_t*>(workspace);
     net->L = L;
     const int P = net_params();
-    hipError_t e = launch_zero(net->stream, net->ws + L.params, size_t(P) * 4 * 4);
+    hipError_t e = hipSuccess;
+    for (size_t off : {L.params, L.grads, L.am, L.av})   // separately aligned sections
+        if (e == hipSuccess) e = launch_zero(net->stream, net->ws + off, size_t(P) * 4);
     if (e == hipSuccess) e = net_repack(net);
     if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
     if (e != hipSuccess) {
@@ -1011,7 +1019,8 @@ wdm_status wdm_net_set_params(wdm_net* net, const float* params) {
     if (!net || !params) return fail(WDM_EINVAL, "null argument");
     HIPCHK(hipMemcpy(net->ws + net->L.params, params, size_t(net_params()) * 4,
                      hipMemcpyHostToDevice));
-    HIPCHK(launch_zero(net->stream, net->ws + net->L.am, size_t(net_params()) * 8));
+    HIPCHK(launch_zero(net->stream, net->ws + net->L.am, size_t(net_params()) * 4));
+    HIPCHK(launch_zero(net->stream, net->ws + net->L.av, size_t(net_params()) * 4));
     net->adam_t = 0;
     HIPCHK(net_repack(net));
     return WDM_OK;

@@ -14,9 +14,9 @@
 
 namespace wdm {
 
+// i in [-n, 2n): periodic index without an integer division
 __device__ __forceinline__ int wrapi(int i, int n) {
-    i %= n;
-    return i < 0 ? i + n : i;
+    return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
 template <typename T>
@@ -30,8 +30,7 @@ struct CellW {
 template <typename T>
 __device__ __forceinline__ CellW<T> cic(float x, float y, float z, const MemberDev& m) {
     CellW<T> c;
-    const double s[3] = {double(x) * (double(m.nx) / m.lx), double(y) * (double(m.ny) / m.ly),
-                         double(z) * (double(m.nz) / m.lz)};
+    const double s[3] = {double(x) * m.inv_dx, double(y) * m.inv_dy, double(z) * m.inv_dz};
     const int n[3] = {m.nx, m.ny, m.nz};
     int ii[3];
 #pragma unroll
@@ -63,8 +62,7 @@ __device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const Membe
     auto P = [&](int a, int b, int d) -> T {
         return gldr(phi, (int64_t(ix[a]) * ny + iy[b]) * nz + iz[d]);
     };
-    const T hx = T(0.5) * T(m.nx / m.lx), hy = T(0.5) * T(m.ny / m.ly),
-            hz = T(0.5) * T(m.nz / m.lz);
+    const T hx = T(0.5 * m.inv_dx), hy = T(0.5 * m.inv_dy), hz = T(0.5 * m.inv_dz);
     T gx = 0, gy = 0, gz = 0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -83,8 +81,8 @@ __device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const Membe
     g[2] = float(gz);
 }
 
-__device__ __forceinline__ float wrap_pos(double x, double L) {
-    x -= L * floor(x / L);
+__device__ __forceinline__ float wrap_pos(double x, double L, double inv_l) {
+    x -= L * floor(x * inv_l);
     float f = float(x);
     if (f >= float(L) || f < 0.0f) f = 0.0f;
     return f;
@@ -159,9 +157,9 @@ __global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__
         vy += g[1] * tau;
         vz += g[2] * tau;
         if (mode == 0) {
-            x = wrap_pos(double(x) + double(vx) * dt, m.lx);
-            y = wrap_pos(double(y) + double(vy) * dt, m.ly);
-            z = wrap_pos(double(z) + double(vz) * dt, m.lz);
+            x = wrap_pos(double(x) + double(vx) * dt, m.lx, m.inv_lx);
+            y = wrap_pos(double(y) + double(vy) * dt, m.ly, m.inv_ly);
+            z = wrap_pos(double(z) + double(vz) * dt, m.lz, m.inv_lz);
             if (act) {
                 gstr(m.px, i, x);
                 gstr(m.py, i, y);
@@ -175,8 +173,7 @@ __global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__
         }
         if (mode == 1) return;
     }
-    const double dv = (m.lx / m.nx) * (m.ly / m.ny) * (m.lz / m.nz);
-    const T q = T(m.particle_mass / dv);
+    const T q = T(m.particle_mass * m.inv_dx * m.inv_dy * m.inv_dz);
     const CellW<T> c = cic<T>(x, y, z, m);
     T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
     deposit_wave(grid, m, c, q, act);
@@ -199,9 +196,9 @@ hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
 __global__ void k_upload(MemberDev m, const float* __restrict__ pos, const float* __restrict__ vel) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= m.np) return;
-    m.px[i] = wrap_pos(double(pos[3 * i + 0]), m.lx);
-    m.py[i] = wrap_pos(double(pos[3 * i + 1]), m.ly);
-    m.pz[i] = wrap_pos(double(pos[3 * i + 2]), m.lz);
+    m.px[i] = wrap_pos(double(pos[3 * i + 0]), m.lx, m.inv_lx);
+    m.py[i] = wrap_pos(double(pos[3 * i + 1]), m.ly, m.inv_ly);
+    m.pz[i] = wrap_pos(double(pos[3 * i + 2]), m.lz, m.inv_lz);
     m.vx[i] = vel[3 * i + 0];
     m.vy[i] = vel[3 * i + 1];
     m.vz[i] = vel[3 * i + 2];
@@ -299,29 +296,45 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of n counters in one block of 1024 lanes.
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int64_t n) {
-    __shared__ uint32_t s[1024];
-    const int64_t chunk = (n + 1023) / 1024;
-    const int64_t b = int64_t(threadIdx.x) * chunk;
-    const int64_t e = b + chunk < n ? b + chunk : n;
-    uint32_t sum = 0;
-#pragma unroll 8
-    for (int64_t i = b; i < e; ++i) sum += a[i];
-    s[threadIdx.x] = sum;
+// Exclusive scan of the digit-major histogram hist[d * nb + b] in two small
+// kernels: each of 256 blocks scans one digit's column over the nb tile blocks
+// (and records the digit total); one block then scans the 256 totals, which
+// k_radix_scatter adds as the digit base.
+__global__ __launch_bounds__(256) void k_scan_digit(uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ totals, int nb) {
+    __shared__ uint32_t s[256];
+    uint32_t* col = hist + int64_t(blockIdx.x) * nb;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        const int b = b0 + int(threadIdx.x);
+        const uint32_t v = b < nb ? col[b] : 0u;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t t = int(threadIdx.x) >= off ? s[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (b < nb) col[b] = carry + s[threadIdx.x] - v;
+        carry += s[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_totals(uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s[256];
+    const uint32_t v = totals[threadIdx.x];
+    s[threadIdx.x] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = int(threadIdx.x) >= off ? s[threadIdx.x - off] : 0u;
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t t = int(threadIdx.x) >= off ? s[threadIdx.x - off] : 0u;
         __syncthreads();
-        s[threadIdx.x] += v;
+        s[threadIdx.x] += t;
         __syncthreads();
     }
-    uint32_t run = s[threadIdx.x] - sum;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
+    totals[threadIdx.x] = s[threadIdx.x] - v;
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin,
@@ -330,11 +343,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
                                                        uint32_t* __restrict__ vout, int64_t n,
                                                        int shift,
                                                        const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ totals,
                                                        int nblocks) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
-    base[tid] = hist[int64_t(tid) * nblocks + blockIdx.x];
+    base[tid] = totals[tid] + hist[int64_t(tid) * nblocks + blockIdx.x];
     for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -398,10 +412,12 @@ hipError_t launch_particle_sort(hipStream_t s, const MemberDev& m, const MemberD
     const int bits = 3 * axis_bits;   // Morton key width
     const int nb = sort_blocks(m.np);
     uint32_t *ka = m.key_a, *kb = m.key_b, *va = m.idx_a, *vb = m.idx_b;
+    uint32_t* totals = m.hist + int64_t(256) * nb;   // 256 digit bases after the histogram
     for (int shift = 0; shift < bits; shift += 8) {
         k_radix_hist<<<nb, 256, 0, s>>>(ka, m.np, shift, m.hist, nb);
-        k_scan_u32<<<1, 1024, 0, s>>>(m.hist, int64_t(nb) * 256);
-        k_radix_scatter<<<nb, 256, 0, s>>>(ka, va, kb, vb, m.np, shift, m.hist, nb);
+        k_scan_digit<<<256, 256, 0, s>>>(m.hist, totals, nb);
+        k_scan_totals<<<1, 256, 0, s>>>(totals);
+        k_radix_scatter<<<nb, 256, 0, s>>>(ka, va, kb, vb, m.np, shift, m.hist, totals, nb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }

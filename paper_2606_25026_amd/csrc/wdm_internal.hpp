@@ -47,7 +47,8 @@ struct MemberDev {
     double lx, ly, lz;
     double eta;        // hbar / m
     double four_pi_G;
-    double dt_ref_unused;
+    double inv_dx, inv_dy, inv_dz;   // n / L per axis
+    double inv_lx, inv_ly, inv_lz;   // 1 / L per axis
     // time-step slots (device doubles): [0] dt in use, [1] dt_auto, [2] dt set by user,
     // [3] current time
     double* dt;
