@@ -10,7 +10,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/wdm.h"
+#include "wdm.h"
 #include "wdm_internal.hpp"
 
 namespace wdm {
@@ -235,9 +235,9 @@ hipError_t timed_on(wdm_plan* p, hipStream_t s, int kind, F&& f) {
     if (!p->profiling) return f();
     hipEvent_t a = take_event(p), b = take_event(p);
     if (!a || !b) return f();
-    hipEventRecord(a, s);
+    if (const hipError_t r = hipEventRecord(a, s); r != hipSuccess) return r;
     const hipError_t e = f();
-    hipEventRecord(b, s);
+    if (const hipError_t r = hipEventRecord(b, s); r != hipSuccess) return r;
     p->recs.push_back({kind, a, b});
     return e;
 }
@@ -416,9 +416,10 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
     for (int d = 0; d < n_members; ++d) {
         const MemberDev& m = p->host[d];
         const int64_t cells = int64_t(m.nx) * m.ny * m.nz;
-        launch_zero(p->stream, m.rho_b, size_t(cells) * (p->prec ? 8 : 4));
-        launch_zero(p->stream, m.dt, 4 * sizeof(double));
-        launch_zero(p->stream, m.results, kRedFields * sizeof(double));
+        if (launch_zero(p->stream, m.rho_b, size_t(cells) * (p->prec ? 8 : 4)) != hipSuccess ||
+            launch_zero(p->stream, m.dt, 4 * sizeof(double)) != hipSuccess ||
+            launch_zero(p->stream, m.results, kRedFields * sizeof(double)) != hipSuccess)
+            return cleanup(WDM_EDEVICE, "plan initialisation failed");
     }
     if (hipStreamSynchronize(p->stream) != hipSuccess)
         return cleanup(WDM_EDEVICE, "plan initialisation failed");
@@ -429,16 +430,16 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
 
 wdm_status wdm_plan_destroy(wdm_plan* plan) {
     if (!plan) return fail(WDM_EINVAL, "null plan");
-    hipStreamSynchronize(plan->stream);
-    if (plan->s_main) hipStreamSynchronize(plan->s_main);
-    if (plan->s_aux) hipStreamSynchronize(plan->s_aux);
-    for (hipEvent_t e : plan->pool) hipEventDestroy(e);
+    (void)hipStreamSynchronize(plan->stream);
+    if (plan->s_main) (void)hipStreamSynchronize(plan->s_main);
+    if (plan->s_aux) (void)hipStreamSynchronize(plan->s_aux);
+    for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
     for (hipGraphExec_t g : plan->g_step)
-        if (g) hipGraphExecDestroy(g);
+        if (g) (void)hipGraphExecDestroy(g);
     for (hipEvent_t e : {plan->ev_in, plan->ev_out, plan->ev_fork, plan->ev_join})
-        if (e) hipEventDestroy(e);
-    if (plan->s_main) hipStreamDestroy(plan->s_main);
-    if (plan->s_aux) hipStreamDestroy(plan->s_aux);
+        if (e) (void)hipEventDestroy(e);
+    if (plan->s_main) (void)hipStreamDestroy(plan->s_main);
+    if (plan->s_aux) (void)hipStreamDestroy(plan->s_aux);
     delete plan;
     return WDM_OK;
 }
@@ -591,7 +592,7 @@ hipError_t capture_step(wdm_plan* p, int which) {
     e = hipStreamEndCapture(p->s_main, &g);
     if (le != hipSuccess) e = le;
     if (e == hipSuccess) e = hipGraphInstantiate(&p->g_step[which], g, nullptr, nullptr, 0);
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return e;
 }
 
@@ -611,7 +612,7 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
         for (int w = 0; w < 2; ++w)
             if (capture_step(p, w) != hipSuccess) {
                 p->use_graphs = false;   // capture unavailable: launch directly
-                hipGetLastError();
+                (void)hipGetLastError();
                 return wdm_step(p, n, dt);
             }
     }
@@ -823,8 +824,8 @@ wdm_status wdm_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t 
     HIPCHK(hipEventSynchronize(b));
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, a, b));
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     *ms_per_copy = double(ms) / reps;
     return WDM_OK;
 }
@@ -1010,7 +1011,7 @@ wdm_status wdm_net_create(int32_t n, void* workspace, size_t bytes, void* hip_st
 
 wdm_status wdm_net_destroy(wdm_net* net) {
     if (!net) return fail(WDM_EINVAL, "null network");
-    hipStreamSynchronize(net->stream);
+    (void)hipStreamSynchronize(net->stream);
     delete net;
     return WDM_OK;
 }

@@ -4,10 +4,11 @@
 // cloud-in-cell weights; particles are kicked, drifted and deposited back onto
 // the grid with the same weights.
 //
-// The deposit sorts nothing per step: particles are kept ordered by cell (a
-// stable LSD radix sort, re-run periodically), so lanes of a wavefront mostly
-// share cells; each wavefront sums its contributions per run of equal cells and
-// one lane per run issues the eight atomic adds.
+// The deposit sorts nothing per step: particles are kept in Morton order of
+// their cells (a stable LSD radix sort, re-run periodically), so the particles
+// of a work-group fill a compact box of cells.  Each wavefront sums its
+// contributions per run of equal cells; the runs are accumulated in an LDS box
+// and each non-zero node costs one global atomic add per work-group.
 #include "wdm_internal.hpp"
 
 #include <algorithm>
@@ -88,14 +89,15 @@ __device__ __forceinline__ float wrap_pos(double x, double L, double inv_l) {
     return f;
 }
 
-// Deposit q * w into `grid` at the 8 nodes of cell c.  All 64 lanes of the
-// wavefront must call this together; inactive lanes pass act = false.
+// Per-run sums of the eight CIC contributions q * w of a wavefront: lanes
+// holding the same base cell (consecutive after the cell sort) form a run; on
+// return the run's first lane holds the run's sums in val[] and head = true.
+// All 64 lanes of the wavefront must call this together.
 template <typename T>
-__device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberDev& m,
-                                             const CellW<T>& c, T q, bool act) {
+__device__ __forceinline__ bool wave_runs(const MemberDev& m, const CellW<T>& c, T q, bool act,
+                                          T val[8]) {
     const int lane = int(__lane_id());
     const int64_t key = act ? (int64_t(c.i) * m.ny + c.j) * m.nz + c.k : -1 - lane;
-    T val[8];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -119,7 +121,16 @@ __device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberD
             if (take) val[v] += o;
         }
     }
-    if (!(head && act)) return;
+    return head && act;
+}
+
+// Deposit q * w into `grid` at the 8 nodes of cell c, one global atomic add
+// per node and wavefront run.
+template <typename T>
+__device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberDev& m,
+                                             const CellW<T>& c, T q, bool act) {
+    T val[8];
+    if (!wave_runs(m, c, q, act, val)) return;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int i1 = c.i + 1 == nx ? 0 : c.i + 1;
     const int j1 = c.j + 1 == ny ? 0 : c.j + 1;
@@ -135,14 +146,105 @@ __device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberD
                             T(val[a * 4 + b * 2 + d]));
 }
 
+// LDS staging of a work-group's deposit: 16 KB of nodes.
+template <typename T>
+constexpr int tile_nodes() {
+    return 16384 / int(sizeof(T));
+}
+constexpr int kParticleWG = 256;
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Work-group deposit.  The particles of a work-group are consecutive in
+// Morton order, so their cells usually fill a small box: if that box (plus the
+// upper CIC node) holds at most tile_nodes<T>() nodes, the group accumulates
+// into LDS and issues one global atomic add per non-zero node; otherwise each
+// wavefront deposits its runs directly.  Every lane of the work-group must
+// call this (inactive lanes pass act = false).
+template <typename T>
+__device__ __forceinline__ void deposit_group(T* __restrict__ grid, const MemberDev& m,
+                                              const CellW<T>& c, T q, bool act) {
+    __shared__ T tile[tile_nodes<T>()];
+    __shared__ int box[6];
+    const int tid = int(threadIdx.x);
+    constexpr int kBig = 1 << 30;
+    const int lo0 = wave_min(act ? c.i : kBig), lo1 = wave_min(act ? c.j : kBig),
+              lo2 = wave_min(act ? c.k : kBig);
+    const int hi0 = wave_max(act ? c.i : -1), hi1 = wave_max(act ? c.j : -1),
+              hi2 = wave_max(act ? c.k : -1);
+    if (tid == 0) {
+        box[0] = box[1] = box[2] = kBig;
+        box[3] = box[4] = box[5] = -1;
+    }
+    __syncthreads();
+    if (__lane_id() == 0) {
+        atomicMin(&box[0], lo0);
+        atomicMin(&box[1], lo1);
+        atomicMin(&box[2], lo2);
+        atomicMax(&box[3], hi0);
+        atomicMax(&box[4], hi1);
+        atomicMax(&box[5], hi2);
+    }
+    __syncthreads();
+    if (box[3] < 0) return;  // no particle in the work-group (uniform)
+    const int i0 = box[0], j0 = box[1], k0 = box[2];
+    const int ex = box[3] - i0 + 2, ey = box[4] - j0 + 2, ez = box[5] - k0 + 2;
+    // extents are at most n + 1 <= 513 each, so the product fits in int64
+    const int64_t vol64 = int64_t(ex) * ey * ez;
+    if (vol64 > tile_nodes<T>()) {
+        deposit_wave(grid, m, c, q, act);
+        return;
+    }
+    const int vol = int(vol64);
+    for (int t = tid; t < vol; t += kParticleWG) tile[t] = T(0);
+    __syncthreads();
+    T val[8];
+    if (wave_runs(m, c, q, act, val)) {
+        const int base = ((c.i - i0) * ey + (c.j - j0)) * ez + (c.k - k0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int d = 0; d < 2; ++d)
+                    atomicAdd(&tile[base + (a * ey + b) * ez + d], val[a * 4 + b * 2 + d]);
+    }
+    __syncthreads();
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    const int eyz = ey * ez;
+    for (int t = tid; t < vol; t += kParticleWG) {
+        const T v = tile[t];
+        if (v == T(0)) continue;
+        const int ti = t / eyz;
+        const int r = t - ti * eyz;
+        const int tj = r / ez;
+        const int tk = r - tj * ez;
+        // i0 + ti <= max cell + 1 <= n: one wrap at most
+        int gi = i0 + ti, gj = j0 + tj, gk = k0 + tk;
+        if (gi >= nx) gi -= nx;
+        if (gj >= ny) gj -= ny;
+        if (gk >= nz) gk -= nz;
+        gatomic_add(&grid[(int64_t(gi) * ny + gj) * nz + gk], v);
+    }
+}
+
 // mode 0: kick + drift + deposit into rho_b; 1: kick only; 2: deposit into
 // rho_b; 3: deposit into scratch (as a real grid).
 template <typename T>
-__global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__ mems, int first,
-                                                   int mode, int kick) {
+__global__ __launch_bounds__(kParticleWG) void k_particles(const MemberDev* __restrict__ mems,
+                                                           int first, int mode, int kick) {
     const MemberDev& m = mems[first + blockIdx.y];
-    if (int64_t(blockIdx.x) * 256 >= m.np) return;  // uniform per block
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (int64_t(blockIdx.x) * kParticleWG >= m.np) return;  // uniform per block
+    const int64_t i = int64_t(blockIdx.x) * kParticleWG + threadIdx.x;
     const bool act = i < m.np;
     const int64_t ii = act ? i : 0;
     float x = gldr(m.px, ii), y = gldr(m.py, ii), z = gldr(m.pz, ii);
@@ -176,17 +278,19 @@ __global__ __launch_bounds__(256) void k_particles(const MemberDev* __restrict__
     const T q = T(m.particle_mass * m.inv_dx * m.inv_dy * m.inv_dz);
     const CellW<T> c = cic<T>(x, y, z, m);
     T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
-    deposit_wave(grid, m, c, q, act);
+    deposit_group(grid, m, c, q, act);
 }
 
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
                             KickMode kick) {
     if (max_np <= 0) return hipSuccess;
-    dim3 grid(unsigned((max_np + 255) / 256), unsigned(L.count));
+    dim3 grid(unsigned((max_np + kParticleWG - 1) / kParticleWG), unsigned(L.count));
     if (prec)
-        k_particles<double><<<grid, 256, 0, L.stream>>>(L.members, L.first, mode, int(kick));
+        k_particles<double><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first, mode,
+                                                                  int(kick));
     else
-        k_particles<float><<<grid, 256, 0, L.stream>>>(L.members, L.first, mode, int(kick));
+        k_particles<float><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first, mode,
+                                                                 int(kick));
     return hipGetLastError();
 }
 

@@ -56,10 +56,10 @@ template <class P, typename T>
 constexpr int wg_size() {
     return pencils_per_wg<P, T>() * P::T;
 }
-template <class P, typename T>
+template <class P, typename T, bool STRIDED>
 constexpr int lds_entries() {
     // strided layout: N * PP entries; contiguous layout: PP * (N + N/16)
-    return pencils_per_wg<P, T>() * (P::N + P::N / 16);
+    return pencils_per_wg<P, T>() * (STRIDED ? P::N : P::N + P::N / 16);
 }
 
 // Lane coordinates and LDS addressing for the two pencil mappings.
@@ -114,18 +114,25 @@ __device__ __noinline__ cplx<float> rotate_fp64(cplx<float> a, double r) {
 }
 
 // a * exp(i arg), arg reduced mod 2 pi in FP64.  Single precision: for small
-// reduced arguments exp(i r) = 1 + q with q = (-2 sin^2(r/2), sin r) formed from
-// one sincosf(r/2), so the factor's rounding error scales with |r| instead of
-// sitting at the unit-modulus level; larger arguments take FP64 sincos and an
-// FP64 product, rounded once.
+// reduced arguments exp(i r) = 1 + q with q = (cos r - 1, sin r) from their
+// Taylor series (|r| < 1/16: the first omitted terms are below 1e-13 of the
+// kept ones), so the factor's rounding error scales with |r| instead of sitting
+// at the unit-modulus level; larger arguments take FP64 sincos and an FP64
+// product, rounded once.
 template <typename T>
 __device__ __forceinline__ cplx<T> rotate(cplx<T> a, double arg) {
     const double r = arg - kTwoPi * rint(arg * (1.0 / kTwoPi));
     if constexpr (std::is_same<T, float>::value) {
         if (fabs(r) < 0.0625) {
-            float s, c;
-            sincosf(float(0.5 * r), &s, &c);
-            const float qr = -2.0f * s * s, qi = 2.0f * s * c;
+            const float x = float(r), x2 = x * x;
+            // cos x - 1 = -x^2/2! + x^4/4! - x^6/6! + x^8/8!
+            const float qr =
+                x2 * fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f),
+                          -0.5f);
+            // sin x = x - x^3/3! + x^5/5! - x^7/7!
+            const float qi =
+                x * fmaf(x2, fmaf(x2, fmaf(x2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f),
+                         1.0f);
             // a (1 + q), fused so the small rotation is not rounded twice
             return cplx<float>{fma(a.re, qr, fma(-a.im, qi, a.re)),
                                fma(a.im, qr, fma(a.re, qi, a.im))};
@@ -153,25 +160,28 @@ __device__ __forceinline__ cplx<T> mul64(cplx<T> a, cplx<double> f) {
     return cplx<T>{T(re * f.re - im * f.im), T(re * f.im + im * f.re)};
 }
 
-// Generic load / store of the lane's slots of pencil `base`, element stride `st`.
+// Generic load / store of the lane's slots of pencil `base`, element stride
+// `st`.  Element slot_elem(t, s) = t + c_s with a compile-time c_s, so the
+// lane's address is formed once and each slot adds the uniform c_s * st.
+template <class P, int R>
+__device__ __forceinline__ constexpr int slot_const(int s) {
+    return P::T * (s / R) + (s % R) * (P::N / R);
+}
 template <class P, int R, typename T, class L>
 __device__ __forceinline__ void load_slots(cplx<T>* v, const cplx<T>* g, int64_t base,
                                            int64_t st, bool ok, const L& ln) {
+    const cplx<T>* lane = g + (base + int64_t(ln.t) * st);
 #pragma unroll
-    for (int s = 0; s < P::E; ++s) {
-        const int e = slot_elem<P, R>(ln.t, s);
-        v[s] = ok ? gld(g, base + int64_t(e) * st) : cplx<T>{T(0), T(0)};
-    }
+    for (int s = 0; s < P::E; ++s)
+        v[s] = ok ? gld(lane, int64_t(slot_const<P, R>(s)) * st) : cplx<T>{T(0), T(0)};
 }
 template <class P, int R, typename T, class L>
 __device__ __forceinline__ void store_slots(const cplx<T>* v, cplx<T>* g, int64_t base,
                                             int64_t st, bool ok, const L& ln) {
     if (!ok) return;
+    cplx<T>* lane = g + (base + int64_t(ln.t) * st);
 #pragma unroll
-    for (int s = 0; s < P::E; ++s) {
-        const int e = slot_elem<P, R>(ln.t, s);
-        gst(g, base + int64_t(e) * st, v[s]);
-    }
+    for (int s = 0; s < P::E; ++s) gst(lane, int64_t(slot_const<P, R>(s)) * st, v[s]);
 }
 
 // ===========================================================================
@@ -185,7 +195,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     using LN = Lanes<FP, T, false>;
     constexpr int PP = LN::PP;
     constexpr int H = NZ / 2;
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     const MemberDev& m = mems[first + blockIdx.y];
     const LN ln;
@@ -244,7 +254,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     using LN = Lanes<FP, T, false>;
     constexpr int PP = LN::PP;
     constexpr int H = NZ / 2;
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     const MemberDev& m = mems[first + blockIdx.y];
     const LN ln;
@@ -320,7 +330,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY>::type, T>())) void k_
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NY>::type;
     constexpr int PP = pencils_per_wg<FP, T>();
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    __shared__ cplx<T> lds[lds_entries<FP, T, !SPEC>()];
     __shared__ cplx<T> tw[tw_entries<T>(NY)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_y, NY);
@@ -346,18 +356,23 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY>::type, T>())) void k_
 }
 
 // P3: x forward, kinetic phase, x inverse.  The factor
-// exp(-i eta dt |k|^2 / 2) / N is formed and applied in FP64 as
-// e_x(k_x) * e_yz(k_y, k_z): each mode gets the same factor every step, so
-// rounding it to single precision would add up coherently over a run.
+// exp(-i eta dt |k|^2 / 2) / N = e_x(k_x) e_yz(k_y, k_z) is formed in FP64:
+// each mode gets the same factor every step, so a factor rounded to single
+// precision would add up coherently over a run.  The complex64 path keeps each
+// FP64 factor as an unevaluated sum hi + lo of two complex64 numbers and
+// multiplies by it with one rounding (cmul_split), first by e_x, then by e_yz;
+// the complex128 path multiplies by the FP64 product directly.
 template <int NX, typename T>
 __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_kinetic(
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NX>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    constexpr bool kSplit = std::is_same<T, float>::value;
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
-    __shared__ cplx<double> ex[NX];
+    // complex64: hi in [0, NX), lo in [NX, 2 NX); complex128: the factor
+    __shared__ cplx<T> ex[kSplit ? 2 * NX : NX];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_x, NX);
     const double dt = gldr(m.dt, 0);
@@ -365,7 +380,14 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
     for (int i = int(threadIdx.x); i < NX; i += int(blockDim.x)) {
         const double kx = cx * signed_mode(i, NX);
-        ex[i] = expi64(a * kx * kx);
+        const cplx<double> e = expi64(a * kx * kx);
+        if constexpr (kSplit) {
+            const cplx<float> h{float(e.re), float(e.im)};
+            ex[i] = h;
+            ex[NX + i] = cplx<float>{float(e.re - double(h.re)), float(e.im - double(h.im))};
+        } else {
+            ex[i] = e;
+        }
     }
     __syncthreads();
     const LN ln;
@@ -373,35 +395,62 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     const int64_t plane = ny * nz;
     const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
     const bool ok = q < plane;
-    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
-    cplx<T> v[FP::E];
-    load_slots<FP, FP::first()>(v, psi, q, plane, ok, ln);
-    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+    // the pencil's factor, formed before its data is live
     const double ky = cy * signed_mode(int(q / nz), int(ny));
     const double kz = cz * signed_mode(int(q % nz), int(nz));
     const double inv_n = 1.0 / (double(m.nx) * double(ny) * double(nz));
     cplx<double> eyz = expi64(a * (ky * ky + kz * kz));
     eyz = cplx<double>{eyz.re * inv_n, eyz.im * inv_n};
+    const cplx<float> yh{float(eyz.re), float(eyz.im)};
+    const cplx<float> yl{float(eyz.re - double(yh.re)), float(eyz.im - double(yh.im))};
+    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
+    cplx<T> v[FP::E];
+    load_slots<FP, FP::first()>(v, psi, q, plane, ok, ln);
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s)
-        v[s] = mul64(v[s], cmul(ex[slot_elem<FP, FP::last()>(ln.t, s)], eyz));
+        for (int s = 0; s < FP::E; ++s) {
+            const int e = slot_elem<FP, FP::last()>(ln.t, s);
+            v[s] = cmul_split(cmul_split(v[s], ex[e], ex[NX + e]), yh, yl);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < FP::E; ++s)
+            v[s] = cmul(v[s], cmul(ex[slot_elem<FP, FP::last()>(ln.t, s)], eyz));
+    }
     __syncthreads();
     pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
     store_slots<IP, IP::last()>(v, psi, q, plane, ok, ln);
 }
 
+// 1 / x for normal x: hardware reciprocal refined by one Newton step in single
+// precision (within about one unit in the last place); FP64 division otherwise.
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // P7: x forward, Green's function, x inverse, on the half spectrum and the
-// Nyquist plane.
+// Nyquist plane.  |k|^2 is summed in FP64 from a per-work-group table of k_x^2;
+// the quotient -4 pi G / (|k|^2 N) is taken in the grid precision (its
+// rounding perturbs Phi by one unit in the last place, recomputed every step).
 template <int NX, typename T>
 __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_green(
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NX>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
+    __shared__ double kx2[NX];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, m.tw_x, NX);
+    const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
+    for (int i = int(threadIdx.x); i < NX; i += int(blockDim.x)) {
+        const double kx = cx * signed_mode(i, NX);
+        kx2[i] = kx * kx;
+    }
     __syncthreads();
     const LN ln;
     const int64_t ny = m.ny, h = m.nz / 2;
@@ -411,23 +460,20 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     const int64_t plane = nyq ? ny : ny * h;
     const int64_t q = tile * LN::PP + ln.p;
     const bool ok = q < plane;
-    cplx<T>* data = static_cast<cplx<T>*>(nyq ? m.spec_nyq : m.spec);
-    cplx<T> v[FP::E];
-    load_slots<FP, FP::first()>(v, data, q, plane, ok, ln);
-    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
-    const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
     const int64_t iy = nyq ? q : q / h;
     const int64_t iz = nyq ? h : q % h;
     const double ky = cy * signed_mode(int(iy), int(ny));
     const double kz = cz * double(iz);
     const double kyz2 = ky * ky + kz * kz;
-    const double gscale = -m.four_pi_G / (double(m.nx) * double(ny) * double(m.nz));
+    const T gscale = T(-m.four_pi_G / (double(m.nx) * double(ny) * double(m.nz)));
+    cplx<T>* data = static_cast<cplx<T>*>(nyq ? m.spec_nyq : m.spec);
+    cplx<T> v[FP::E];
+    load_slots<FP, FP::first()>(v, data, q, plane, ok, ln);
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
 #pragma unroll
     for (int s = 0; s < FP::E; ++s) {
-        const double kx = cx * signed_mode(slot_elem<FP, FP::last()>(ln.t, s), NX);
-        const double k2 = kx * kx + kyz2;
-        const T g = k2 > 0.0 ? T(gscale / k2) : T(0);
-        v[s] = cscale(v[s], g);
+        const T k2 = T(kx2[slot_elem<FP, FP::last()>(ln.t, s)] + kyz2);
+        v[s] = cscale(v[s], k2 > T(0) ? gscale * recip(k2) : T(0));
     }
     __syncthreads();
     pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
@@ -439,7 +485,7 @@ template <int N, typename T, bool INV, int AXIS>
 __global__ __launch_bounds__((wg_size<typename PlanFor<N>::type, T>())) void k_axis_fft(
     const MemberDev* __restrict__ mems, int first, int which) {
     using FP = typename PlanFor<N>::type;
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(N)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<T>(tw, AXIS == 0 ? m.tw_x : (AXIS == 1 ? m.tw_y : m.tw_z), N);
@@ -466,7 +512,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     using FP = typename PlanFor<NX>::type;
     using LN = Lanes<FP, T, true>;
     constexpr int WG = wg_size<FP, T>();
-    __shared__ cplx<T> lds[lds_entries<FP, T>()];
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double red[WG];
     const MemberDev& m = mems[first + blockIdx.y];
