@@ -49,20 +49,11 @@ __device__ __forceinline__ CellW<T> cic(float x, float y, float z, const MemberD
 }
 
 // g = -grad Phi (central differences at the 8 CIC nodes), interpolated.
-template <typename T>
-__device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const MemberDev& m,
-                                          const CellW<T>& c, float g[3]) {
-    const int nx = m.nx, ny = m.ny, nz = m.nz;
-    int ix[4], iy[4], iz[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        ix[d] = wrapi(c.i + d - 1, nx);
-        iy[d] = wrapi(c.j + d - 1, ny);
-        iz[d] = wrapi(c.k + d - 1, nz);
-    }
-    auto P = [&](int a, int b, int d) -> T {
-        return gldr(phi, (int64_t(ix[a]) * ny + iy[b]) * nz + iz[d]);
-    };
+// P(a, b, d) returns Phi at cell (c.i - 1 + a, c.j - 1 + b, c.k - 1 + d),
+// a, b, d in [0, 4); 32 of the 64 cells of that neighbourhood are read.
+template <typename T, class F>
+__device__ __forceinline__ void accel_from(const MemberDev& m, const CellW<T>& c, F&& P,
+                                           float g[3]) {
     const T hx = T(0.5 * m.inv_dx), hy = T(0.5 * m.inv_dy), hz = T(0.5 * m.inv_dz);
     T gx = 0, gy = 0, gz = 0;
 #pragma unroll
@@ -80,6 +71,66 @@ __device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const Membe
     g[0] = float(gx);
     g[1] = float(gy);
     g[2] = float(gz);
+}
+
+// 4- and 2-float rows at 4-byte alignment (global memory, address space 1).
+typedef float wdm_row4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef float wdm_row2 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <typename T>
+__device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const MemberDev& m,
+                                          const CellW<T>& c, float g[3]) {
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    int ix[4], iy[4], iz[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        ix[d] = wrapi(c.i + d - 1, nx);
+        iy[d] = wrapi(c.j + d - 1, ny);
+        iz[d] = wrapi(c.k + d - 1, nz);
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        // The stencil's 32 values lie on 12 z-rows: 4 rows of 4 (a, b in
+        // {1, 2}) and 8 rows of 2 (one of a, b in {0, 3}, d in {1, 2}).  Away
+        // from the z faces each row is one vector load.
+        if (c.k >= 1 && c.k + 2 < nz) {
+            float v[4][4][4];
+            auto row = [&](int a, int b) {
+                return phi + (int64_t(ix[a]) * ny + iy[b]) * nz;
+            };
+#pragma unroll
+            for (int a = 1; a < 3; ++a)
+#pragma unroll
+                for (int b = 1; b < 3; ++b) {
+                    const wdm_row4 r =
+                        *(const __attribute__((address_space(1))) wdm_row4*)(row(a, b) + c.k - 1);
+                    v[a][b][0] = r.x;
+                    v[a][b][1] = r.y;
+                    v[a][b][2] = r.z;
+                    v[a][b][3] = r.w;
+                }
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+#pragma unroll
+                for (int u = 1; u < 3; ++u) {
+                    const int e = o * 3;  // 0 or 3
+                    const wdm_row2 rx =
+                        *(const __attribute__((address_space(1))) wdm_row2*)(row(e, u) + c.k);
+                    v[e][u][1] = rx.x;
+                    v[e][u][2] = rx.y;
+                    const wdm_row2 ry =
+                        *(const __attribute__((address_space(1))) wdm_row2*)(row(u, e) + c.k);
+                    v[u][e][1] = ry.x;
+                    v[u][e][2] = ry.y;
+                }
+            accel_from(m, c, [&](int a, int b, int d) -> float { return v[a][b][d]; }, g);
+            return;
+        }
+    }
+    accel_from(m, c,
+               [&](int a, int b, int d) -> T {
+                   return gldr(phi, (int64_t(ix[a]) * ny + iy[b]) * nz + iz[d]);
+               },
+               g);
 }
 
 __device__ __forceinline__ float wrap_pos(double x, double L, double inv_l) {

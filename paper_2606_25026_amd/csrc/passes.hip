@@ -94,11 +94,25 @@ __device__ __forceinline__ int slot_elem(int t, int s) {
     return t + P::T * (s / R) + (s % R) * (P::N / R);
 }
 
-template <typename T>
-__device__ __forceinline__ void load_twiddles(cplx<T>* tw, const void* g, int n) {
+// Twiddle table of an N-point plan into LDS by a work-group of WG lanes.  The
+// trip count is a compile-time constant so that every load is issued before
+// the first wait.
+template <int N, int WG, typename T>
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw, const void* g) {
     const cplx<T>* src = static_cast<const cplx<T>*>(g);
-    const int total = tw_entries<T>(n);
-    for (int i = int(threadIdx.x); i < total; i += int(blockDim.x)) tw[i] = gld(src, i);
+    constexpr int total = tw_entries<T>(N);
+    constexpr int iters = (total + WG - 1) / WG;
+    cplx<T> r[iters];
+#pragma unroll
+    for (int k = 0; k < iters; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        r[k] = (total % WG == 0 || i < total) ? gld(src, i) : cplx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int k = 0; k < iters; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        if (total % WG == 0 || i < total) tw[i] = r[k];
+    }
 }
 
 __device__ __forceinline__ int signed_mode(int i, int n) { return i < n / 2 ? i : i - n; }
@@ -202,11 +216,24 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     const int64_t npen = int64_t(m.nx) * m.ny;
     const int64_t q = int64_t(blockIdx.x) * PP + ln.p;
     const bool ok = q < npen;
-    load_twiddles<T>(tw, m.tw_z, NZ);
-    const cplx<T>* spec = static_cast<const cplx<T>*>(m.spec) + q * H;
-    for (int e = ln.t; e < H; e += FP::T) lds[ln(e)] = ok ? gld(spec, e) : cplx<T>{T(0), T(0)};
-    if (ln.t == 0)
-        lds[ln(H)] = ok ? gld(static_cast<const cplx<T>*>(m.spec_nyq), q) : cplx<T>{T(0), T(0)};
+    load_twiddles<NZ, wg_size<FP, T>()>(tw, m.tw_z);
+    // psi is loaded together with the spectrum: one memory wait per pass
+    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
+    cplx<T> w[OP == kZPhiOnly ? 1 : FP::E];
+    if constexpr (OP != kZPhiOnly) load_slots<FP, FP::first()>(w, psi, q * NZ, 1, ok, ln);
+    // half spectrum e in [0, H) (H / T per lane) and the Nyquist element e = H,
+    // all loads issued before the LDS writes
+    static_assert(H % FP::T == 0, "half pencil must split evenly over the lanes");
+    constexpr int HE = H / FP::T;
+    const cplx<T>* spec = static_cast<const cplx<T>*>(m.spec) + q * H + ln.t;
+    cplx<T> hs[HE + 1];
+#pragma unroll
+    for (int k = 0; k < HE; ++k) hs[k] = ok ? gld(spec, k * FP::T) : cplx<T>{T(0), T(0)};
+    hs[HE] = (ok && ln.t == 0) ? gld(static_cast<const cplx<T>*>(m.spec_nyq), q)
+                               : cplx<T>{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < HE; ++k) lds[ln(ln.t + k * FP::T)] = hs[k];
+    if (ln.t == 0) lds[ln(H)] = hs[HE];
     __syncthreads();
     // Hermitian completion F[e] = conj(F[NZ - e]) for e > NZ/2, in the input
     // layout of the inverse plan
@@ -230,10 +257,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     const double dt = gldr(m.dt, 0);
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
     const double c = -tau / m.eta;
-    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
-    load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s) v[s] = rotate(v[s], double(phi[s]) * c);
+    for (int s = 0; s < FP::E; ++s) v[s] = rotate(w[s], double(phi[s]) * c);
     if constexpr (OP == kZKickOnly) {
         store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
         return;
@@ -261,9 +286,14 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     const int64_t npen = int64_t(m.nx) * m.ny;
     const int64_t q = int64_t(blockIdx.x) * PP + ln.p;
     const bool ok = q < npen;
-    load_twiddles<T>(tw, m.tw_z, NZ);
+    load_twiddles<NZ, wg_size<FP, T>()>(tw, m.tw_z);
     cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
     cplx<T> v[FP::E];
+    // the baryon density is loaded together with psi: one memory wait per pass
+    T* rb = static_cast<T*>(m.rho_b) + q * NZ + ln.t;
+    T rbv[FP::E];
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) rbv[s] = ok ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
     if constexpr (OP == kDensInvFft) {
         load_slots<IP, IP::first()>(v, psi, q * NZ, 1, ok, ln);
         __syncthreads();
@@ -273,16 +303,10 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
         load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
         __syncthreads();
     }
-    T* rb = static_cast<T*>(m.rho_b) + q * NZ;
 #pragma unroll
     for (int s = 0; s < FP::E; ++s) {
-        const int e = slot_elem<FP, FP::first()>(ln.t, s);
-        T r = v[s].re * v[s].re + v[s].im * v[s].im;
-        if (ok) {
-            r += gldr(rb, e);
-            gstr(rb, e, T(0));
-        }
-        v[s] = cplx<T>{r, T(0)};
+        v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
+        if (ok) gstr(rb, slot_const<FP, FP::first()>(s), T(0));
     }
     __syncthreads();
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
@@ -333,7 +357,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY>::type, T>())) void k_
     __shared__ cplx<T> lds[lds_entries<FP, T, !SPEC>()];
     __shared__ cplx<T> tw[tw_entries<T>(NY)];
     const MemberDev& m = mems[first + blockIdx.y];
-    load_twiddles<T>(tw, m.tw_y, NY);
+    load_twiddles<NY, wg_size<FP, T>()>(tw, m.tw_y);
     __syncthreads();
     const int64_t nx = m.nx, ny = m.ny, nz = m.nz;
     if constexpr (!SPEC) {
@@ -374,7 +398,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     // complex64: hi in [0, NX), lo in [NX, 2 NX); complex128: the factor
     __shared__ cplx<T> ex[kSplit ? 2 * NX : NX];
     const MemberDev& m = mems[first + blockIdx.y];
-    load_twiddles<T>(tw, m.tw_x, NX);
+    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
     const double dt = gldr(m.dt, 0);
     const double a = -0.5 * m.eta * dt;
     const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
@@ -445,7 +469,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double kx2[NX];
     const MemberDev& m = mems[first + blockIdx.y];
-    load_twiddles<T>(tw, m.tw_x, NX);
+    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
     const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
     for (int i = int(threadIdx.x); i < NX; i += int(blockDim.x)) {
         const double kx = cx * signed_mode(i, NX);
@@ -488,7 +512,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<N>::type, T>())) void k_a
     __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(N)];
     const MemberDev& m = mems[first + blockIdx.y];
-    load_twiddles<T>(tw, AXIS == 0 ? m.tw_x : (AXIS == 1 ? m.tw_y : m.tw_z), N);
+    load_twiddles<N, wg_size<FP, T>()>(tw, AXIS == 0 ? m.tw_x : (AXIS == 1 ? m.tw_y : m.tw_z));
     __syncthreads();
     cplx<T>* data = static_cast<cplx<T>*>(which ? m.scratch : m.psi);
     const int64_t nx = m.nx, ny = m.ny, nz = m.nz;
@@ -516,7 +540,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double red[WG];
     const MemberDev& m = mems[first + blockIdx.y];
-    load_twiddles<T>(tw, m.tw_x, NX);
+    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
     __syncthreads();
     const LN ln;
     const int64_t ny = m.ny, nz = m.nz, plane = ny * nz;
