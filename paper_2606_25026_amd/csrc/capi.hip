@@ -71,7 +71,7 @@ struct Carver {
 };
 
 struct MemberLayout {
-    size_t psi, phi, rho_b, spec, nyq, dt, results;
+    size_t psi, phi, rho_b, spec, nyq, kin, dt, results;
     size_t p[7], a[7], key_a, key_b, idx_a, idx_b, hist;
 };
 
@@ -156,6 +156,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         m.rho_b = c.take(cells * rs);
         m.spec = c.take(int64_t(g.nx) * g.ny * (g.nz / 2) * cs);
         m.nyq = c.take(int64_t(g.nx) * g.ny * cs);
+        m.kin = c.take((int64_t(g.nx) + int64_t(g.ny) * g.nz) * 16);
         m.dt = c.take(4 * sizeof(double));
         m.results = c.take(kRedFields * sizeof(double));
         const int64_t np = std::max<int64_t>(g.n_particles, 0);
@@ -342,6 +343,7 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.spec = ws + ml.spec;
         m.spec_nyq = ws + ml.nyq;
         m.scratch = ws + L.scratch;
+        m.kin = ws + ml.kin;
         m.tw_x = ws + L.tw.at(c.nx);
         m.tw_y = ws + L.tw.at(c.ny);
         m.tw_z = ws + L.tw.at(c.nz);

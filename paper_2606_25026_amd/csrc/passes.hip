@@ -198,6 +198,43 @@ __device__ __forceinline__ void store_slots(const cplx<T>* v, cplx<T>* g, int64_
     for (int s = 0; s < P::E; ++s) gst(lane, int64_t(slot_const<P, R>(s)) * st, v[s]);
 }
 
+// Kinetic factor tables of the drift exp(-i eta dt |k|^2 / 2) / N (Sec. 3.1),
+// factored as e_x(k_x) e_yz(k_y, k_z) and formed in FP64: each mode gets the
+// same factor every step, so a factor rounded to single precision would add up
+// coherently over a run.  complex64 keeps each factor as an unevaluated sum
+// hi + lo of two complex64 numbers.  Written by the threads of P1's merged
+// variant (grid-stride over nx + ny nz entries), read by P3 of the same step.
+template <typename T>
+__device__ __forceinline__ void write_kinetic_table(const MemberDev& m, double dt, int64_t nthr,
+                                                    int64_t gtid) {
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    const int64_t total = int64_t(nx) + int64_t(ny) * nz;
+    const double a = -0.5 * m.eta * dt;
+    const double inv_n = 1.0 / (double(nx) * double(ny) * double(nz));
+    for (int64_t t = gtid; t < total; t += nthr) {
+        cplx<double> e;
+        if (t < nx) {
+            const double kx = (kTwoPi / m.lx) * signed_mode(int(t), nx);
+            e = expi64(a * kx * kx);
+        } else {
+            const int64_t u = t - nx;
+            const double ky = (kTwoPi / m.ly) * signed_mode(int(u / nz), ny);
+            const double kz = (kTwoPi / m.lz) * signed_mode(int(u % nz), nz);
+            e = expi64(a * (ky * ky + kz * kz));
+            e = cplx<double>{e.re * inv_n, e.im * inv_n};
+        }
+        if constexpr (std::is_same<T, float>::value) {
+            const cplx<float> h{float(e.re), float(e.im)};
+            const cplx<float> l{float(e.re - double(h.re)), float(e.im - double(h.im))};
+            cplx<float>* k = static_cast<cplx<float>*>(m.kin);
+            gst(k, 2 * t, h);
+            gst(k, 2 * t + 1, l);
+        } else {
+            gst(static_cast<cplx<double>*>(m.kin), t, e);
+        }
+    }
+}
+
 // ===========================================================================
 // P1: potential from the half spectrum, kick, optional forward z-FFT.
 // ===========================================================================
@@ -266,6 +303,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ>::type, T>())) void k_
     __syncthreads();
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
     store_slots<FP, FP::last()>(v, psi, q * NZ, 1, ok, ln);
+    write_kinetic_table<T>(m, dt, int64_t(gridDim.x) * blockDim.x,
+                           int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 // ===========================================================================
@@ -379,57 +418,56 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY>::type, T>())) void k_
     }
 }
 
-// P3: x forward, kinetic phase, x inverse.  The factor
-// exp(-i eta dt |k|^2 / 2) / N = e_x(k_x) e_yz(k_y, k_z) is formed in FP64:
-// each mode gets the same factor every step, so a factor rounded to single
-// precision would add up coherently over a run.  The complex64 path keeps each
-// FP64 factor as an unevaluated sum hi + lo of two complex64 numbers and
-// multiplies by it with one rounding (cmul_split), first by e_x, then by e_yz;
-// the complex128 path multiplies by the FP64 product directly.
+// P3: x forward, kinetic phase, x inverse, with the factor tables P1 wrote
+// for this step: complex64 multiplies by each hi + lo pair with one rounding
+// (cmul_split), first by e_x, then by e_yz; complex128 by the FP64 product.
 template <int NX, typename T>
 __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_kinetic(
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NX>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
+    constexpr int WG = wg_size<FP, T>();
     constexpr bool kSplit = std::is_same<T, float>::value;
     __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     // complex64: hi in [0, NX), lo in [NX, 2 NX); complex128: the factor
     __shared__ cplx<T> ex[kSplit ? 2 * NX : NX];
     const MemberDev& m = mems[first + blockIdx.y];
-    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
-    const double dt = gldr(m.dt, 0);
-    const double a = -0.5 * m.eta * dt;
-    const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
-    for (int i = int(threadIdx.x); i < NX; i += int(blockDim.x)) {
-        const double kx = cx * signed_mode(i, NX);
-        const cplx<double> e = expi64(a * kx * kx);
-        if constexpr (kSplit) {
-            const cplx<float> h{float(e.re), float(e.im)};
-            ex[i] = h;
-            ex[NX + i] = cplx<float>{float(e.re - double(h.re)), float(e.im - double(h.im))};
-        } else {
-            ex[i] = e;
-        }
+    load_twiddles<NX, WG>(tw, m.tw_x);
+    const cplx<T>* kin = static_cast<const cplx<T>*>(m.kin);
+    constexpr int KE = kSplit ? 2 * NX : NX;   // complex entries of e_x
+    constexpr int KI = (KE + WG - 1) / WG;
+    cplx<T> kr[KI];
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        kr[k] = (KE % WG == 0 || i < KE) ? gld(kin, i) : cplx<T>{T(0), T(0)};
     }
-    __syncthreads();
     const LN ln;
     const int64_t ny = m.ny, nz = m.nz;
     const int64_t plane = ny * nz;
     const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
     const bool ok = q < plane;
-    // the pencil's factor, formed before its data is live
-    const double ky = cy * signed_mode(int(q / nz), int(ny));
-    const double kz = cz * signed_mode(int(q % nz), int(nz));
-    const double inv_n = 1.0 / (double(m.nx) * double(ny) * double(nz));
-    cplx<double> eyz = expi64(a * (ky * ky + kz * kz));
-    eyz = cplx<double>{eyz.re * inv_n, eyz.im * inv_n};
-    const cplx<float> yh{float(eyz.re), float(eyz.im)};
-    const cplx<float> yl{float(eyz.re - double(yh.re)), float(eyz.im - double(yh.im))};
+    // this pencil's e_yz
+    const int64_t qe = NX + (ok ? q : 0);
+    const cplx<T> yh = gld(kin, kSplit ? 2 * qe : qe);
+    const cplx<T> yl = kSplit ? gld(kin, 2 * qe + 1) : cplx<T>{T(0), T(0)};
     cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
     cplx<T> v[FP::E];
     load_slots<FP, FP::first()>(v, psi, q, plane, ok, ln);
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        if (KE % WG == 0 || i < KE) {
+            // complex64 entries alternate hi, lo
+            if constexpr (kSplit)
+                ex[(i & 1) * NX + (i >> 1)] = kr[k];
+            else
+                ex[i] = kr[k];
+        }
+    }
+    __syncthreads();
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
     if constexpr (kSplit) {
 #pragma unroll
@@ -440,7 +478,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     } else {
 #pragma unroll
         for (int s = 0; s < FP::E; ++s)
-            v[s] = cmul(v[s], cmul(ex[slot_elem<FP, FP::last()>(ln.t, s)], eyz));
+            v[s] = cmul(v[s], cmul(ex[slot_elem<FP, FP::last()>(ln.t, s)], yh));
     }
     __syncthreads();
     pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);

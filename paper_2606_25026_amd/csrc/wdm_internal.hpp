@@ -40,6 +40,10 @@ struct MemberDev {
     void* spec;       // complex half spectrum [nx][ny][nz/2] (kz = 0 .. nz/2-1)
     void* spec_nyq;   // complex Nyquist plane [nx][ny] (kz = nz/2)
     void* scratch;    // complex, n cells (diagnostics only)
+    // kinetic factors of the step's dt, written by P1 and read by P3:
+    // [0, nx) e_x(k_x); [nx, nx + ny nz) e_yz(k_y, k_z) / N at q = iy nz + iz.
+    // 16 bytes per entry: (hi, lo) complex64 pair, or one complex128.
+    void* kin;
     const void* tw_x;  // W_nx^m, m in [0, nx) (complex, plan precision)
     const void* tw_y;
     const void* tw_z;
