@@ -148,6 +148,10 @@ def bench_precision(args):
     from paper_2606_25026_amd import inputs, wdm
 
     res = {}
+
+    def log(msg):
+        print(f"# {msg}", file=sys.stderr, flush=True)
+
     # --- sub-box vs oracle
     g = np.load(ROOT / "tests" / "golden" / "subbox_128_steps2000.npz")
     n, L, steps = int(g["n"]), float(g["L"]), int(g["steps"])
@@ -170,8 +174,10 @@ def bench_precision(args):
             "oracle_energy_drift": float(g["etot1"] / g["etot0"] - 1)}
         plan.close()
         del x, out
+        log(f"sub-box {n}^3 {'c64' if prec == 0 else 'c128'} done: {res[f'subbox128_' + ('c64' if prec == 0 else 'c128')]}")
     # --- 512^3: complex64 vs complex128
     n = args.n if args.n != 256 else 512
+    log(f"generating the {n}^3 field")
     psi0 = inputs.grf_soliton(n, L=1.0, k0=16.0 * 2 * math.pi, rc=0.03, rho_c=50.0, seed=0)
     dt = 0.2 / n ** 2
     outs = {}
@@ -195,6 +201,7 @@ def bench_precision(args):
             "mass_drift": e1["mass"] / e0["mass"] - 1,
             "energy_drift": e1["e_total"] / e0["e_total"] - 1}
         plan.close()
+        log(f"{n}^3 {'c64' if prec == 0 else 'c128'} done: {res[f'grid{n}_' + ('c64' if prec == 0 else 'c128')]}")
     d = outs[0].to(torch.complex128) - outs[1]
     res[f"grid{n}_c64_vs_c128_rel_l2"] = float(torch.linalg.vector_norm(d) /
                                                torch.linalg.vector_norm(outs[1]))

@@ -153,6 +153,27 @@ wdm_status wdm_use_graphs(wdm_plan* plan, int32_t enable);
  * wdm_set_state).  Ordering only affects speed and atomic summation order. */
 wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);
 
+/* Autotuning of the step's FFT passes.  Each tunable pass (P1, P2/P4, P3, P5,
+ * P6/P8, P7) of each size class has two FFT plans where its axis length allows
+ * (32, 64, 128, 256, 384, 512): the default, and one with twice the lanes per
+ * pencil and half the values per lane.  wdm_autotune times both on the plan's
+ * stream (one warm-up and `reps` timed launches each, reps in [1, 1000], on
+ * zeroed fields) and keeps the faster.  It overwrites the members' states:
+ * call it before wdm_set_state, or set every state again afterwards
+ * (wdm_step returns WDM_ESTATE until then).  Synchronises.  Both plans give
+ * the same results up to rounding.
+ *
+ * wdm_tuning_entries: number of int32 entries of the choice table (size
+ * classes in ascending (nx, ny, nz) order, six passes each in the order above;
+ * 0 for a null plan).  wdm_get_tuning / wdm_set_tuning copy the table to / from
+ * a host array of exactly that length (values 0 or 1; 1 only where the axis
+ * has a second plan, else WDM_EINVAL and nothing changes), e.g. to reuse a
+ * cached choice without re-timing. */
+wdm_status wdm_autotune(wdm_plan* plan, int32_t reps);
+int32_t wdm_tuning_entries(const wdm_plan* plan);
+wdm_status wdm_get_tuning(wdm_plan* plan, int32_t* out, int32_t n);
+wdm_status wdm_set_tuning(wdm_plan* plan, const int32_t* in, int32_t n);
+
 /* Per-pass timing: while enabled, every kernel launch of wdm_step is
  * bracketed by HIP events on the plan's stream.  wdm_profile_read
  * synchronises, reports one entry per pass (up to `cap`, host array) and

@@ -15,8 +15,8 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libwdm.so"
 OBJ = HERE / "_build"
-SOURCES = ["passes.hip", "particles.hip", "reduce.hip", "corrector.hip", "spectral.hip",
-           "capi.hip"]
+SOURCES = ["passes_z.hip", "passes_y.hip", "passes_x.hip", "particles.hip", "reduce.hip",
+           "corrector.hip", "spectral.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -181,10 +181,14 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
     return true;
 }
 
+// Step passes whose FFT plan the autotuner chooses (per size class).
+enum TuneSlot : int { kTzPot = 0, kTyPsi, kTxKin, kTzDens, kTySpec, kTxGreen, kTuneSlots };
+
 struct SizeClass {
     int first, count;       // device-table range
     int nx, ny, nz;
     int64_t max_np;
+    int var[kTuneSlots] = {0, 0, 0, 0, 0, 0};   // plan variant per tunable pass
 };
 
 struct Rec {
@@ -499,7 +503,8 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
         const bool parts = c.max_np > 0;
         const bool fork = parts && aux != nullptr;
         if (!chk(timed(p, kKZPot, [&] {
-                return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km);
+                return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km,
+                                               c.var[kTzPot]);
             })))
             return e;
         if (fork) {
@@ -514,22 +519,34 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             if (!chk(timed(p, kKParticles, [&] { return launch_particles(L, prec, c.max_np, 0, km); })))
                 return e;
         }
-        if (!chk(timed(p, kKYPsiF, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, false); })))
+        if (!chk(timed(p, kKYPsiF, [&] {
+                return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, false, c.var[kTyPsi]);
+            })))
             return e;
-        if (!chk(timed(p, kKXKin, [&] { return launch_x_kinetic(L, prec, c.nx, c.ny, c.nz); })))
+        if (!chk(timed(p, kKXKin, [&] {
+                return launch_x_kinetic(L, prec, c.nx, c.ny, c.nz, c.var[kTxKin]);
+            })))
             return e;
-        if (!chk(timed(p, kKYPsiI, [&] { return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, true); })))
+        if (!chk(timed(p, kKYPsiI, [&] {
+                return launch_y_fft_psi(L, prec, c.nx, c.ny, c.nz, true, c.var[kTyPsi]);
+            })))
             return e;
         if (fork && !chk(hipStreamWaitEvent(s, p->ev_join, 0))) return e;
         if (!chk(timed(p, kKZDens, [&] {
-                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft);
+                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft, c.var[kTzDens]);
             })))
             return e;
-        if (!chk(timed(p, kKYSpecF, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, false); })))
+        if (!chk(timed(p, kKYSpecF, [&] {
+                return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, false, c.var[kTySpec]);
+            })))
             return e;
-        if (!chk(timed(p, kKXGreen, [&] { return launch_x_green(L, prec, c.nx, c.ny, c.nz); })))
+        if (!chk(timed(p, kKXGreen, [&] {
+                return launch_x_green(L, prec, c.nx, c.ny, c.nz, c.var[kTxGreen]);
+            })))
             return e;
-        if (!chk(timed(p, kKYSpecI, [&] { return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, true); })))
+        if (!chk(timed(p, kKYSpecI, [&] {
+                return launch_y_fft_spec(L, prec, c.nx, c.ny, c.nz, true, c.var[kTySpec]);
+            })))
             return e;
     }
     return e;
@@ -649,6 +666,137 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
 wdm_status wdm_use_graphs(wdm_plan* p, int32_t enable) {
     if (!p) return fail(WDM_EINVAL, "null plan");
     p->use_graphs = enable != 0;
+    return WDM_OK;
+}
+
+// ---- autotuning of the step passes' FFT plans ------------------------------
+
+namespace {
+
+// Axis length that decides each tunable pass's plan.
+int tune_axis(const SizeClass& c, int slot) {
+    switch (slot) {
+        case kTzPot: case kTzDens: return c.nz;
+        case kTyPsi: case kTySpec: return c.ny;
+        default: return c.nx;
+    }
+}
+
+// One launch of a tunable pass with plan variant v (both directions of the
+// y-passes, so a timing covers the pair the step runs).
+hipError_t tune_launch(wdm_plan* p, const Launch& L, const SizeClass& c, int slot, int v) {
+    hipError_t e;
+    switch (slot) {
+        case kTzPot:
+            return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZKickFft, kFullKick, v);
+        case kTyPsi:
+            if ((e = launch_y_fft_psi(L, p->prec, c.nx, c.ny, c.nz, false, v)) != hipSuccess) return e;
+            return launch_y_fft_psi(L, p->prec, c.nx, c.ny, c.nz, true, v);
+        case kTxKin:
+            return launch_x_kinetic(L, p->prec, c.nx, c.ny, c.nz, v);
+        case kTzDens:
+            return launch_z_density(L, p->prec, c.nx, c.ny, c.nz, kDensInvFft, v);
+        case kTySpec:
+            if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, false, v)) != hipSuccess) return e;
+            return launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, true, v);
+        default:
+            return launch_x_green(L, p->prec, c.nx, c.ny, c.nz, v);
+    }
+}
+
+void drop_graphs(wdm_plan* p) {
+    for (hipGraphExec_t& g : p->g_step)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+}  // namespace
+
+int32_t wdm_tuning_entries(const wdm_plan* p) {
+    return p ? int32_t(p->classes.size()) * kTuneSlots : 0;
+}
+
+wdm_status wdm_get_tuning(wdm_plan* p, int32_t* out, int32_t n) {
+    if (!p || !out) return fail(WDM_EINVAL, "null argument");
+    if (n != wdm_tuning_entries(p)) return fail(WDM_EINVAL, "n must equal wdm_tuning_entries");
+    for (size_t k = 0; k < p->classes.size(); ++k)
+        for (int j = 0; j < kTuneSlots; ++j) out[k * kTuneSlots + j] = p->classes[k].var[j];
+    return WDM_OK;
+}
+
+wdm_status wdm_set_tuning(wdm_plan* p, const int32_t* in, int32_t n) {
+    if (!p || !in) return fail(WDM_EINVAL, "null argument");
+    if (n != wdm_tuning_entries(p)) return fail(WDM_EINVAL, "n must equal wdm_tuning_entries");
+    for (size_t k = 0; k < p->classes.size(); ++k)
+        for (int j = 0; j < kTuneSlots; ++j) {
+            const int v = in[k * kTuneSlots + j];
+            if (v != 0 && v != 1) return fail(WDM_EINVAL, "plan variants are 0 or 1");
+            if (v == 1 && !axis_has_variant(tune_axis(p->classes[k], j)))
+                return fail(WDM_EINVAL, "no second plan for this axis length");
+        }
+    for (size_t k = 0; k < p->classes.size(); ++k)
+        for (int j = 0; j < kTuneSlots; ++j) p->classes[k].var[j] = in[k * kTuneSlots + j];
+    drop_graphs(p);
+    return WDM_OK;
+}
+
+wdm_status wdm_autotune(wdm_plan* p, int32_t reps) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    if (reps < 1 || reps > 1000) return fail(WDM_EINVAL, "reps must be in [1, 1000]");
+    if (p->profiling) return fail(WDM_ESTATE, "switch profiling off before tuning");
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(WDM_EDEVICE, "hipEventCreate failed");
+    }
+    hipError_t e = hipSuccess;
+    // the timings run on zeroed fields (FFT timing does not depend on the
+    // values); the members' states are overwritten
+    for (size_t k = 0; k < p->classes.size() && e == hipSuccess; ++k) {
+        SizeClass& c = p->classes[k];
+        const Launch L{p->stream, p->table, c.first, c.count};
+        const size_t cs = p->prec ? 16 : 8, rs = p->prec ? 8 : 4;
+        const int64_t cells = int64_t(c.nx) * c.ny * c.nz;
+        for (int d = c.first; d < c.first + c.count && e == hipSuccess; ++d) {
+            const MemberDev& m = p->host[d];
+            if (e == hipSuccess) e = launch_zero(p->stream, m.psi, size_t(cells) * cs);
+            if (e == hipSuccess) e = launch_zero(p->stream, m.phi, size_t(cells) * rs);
+            if (e == hipSuccess) e = launch_zero(p->stream, m.rho_b, size_t(cells) * rs);
+            if (e == hipSuccess)
+                e = launch_zero(p->stream, m.spec, size_t(c.nx) * c.ny * (c.nz / 2) * cs);
+            if (e == hipSuccess) e = launch_zero(p->stream, m.spec_nyq, size_t(c.nx) * c.ny * cs);
+            if (e == hipSuccess) e = launch_zero(p->stream, m.dt, 4 * sizeof(double));
+        }
+        for (int j = 0; j < kTuneSlots && e == hipSuccess; ++j) {
+            const int nv = axis_has_variant(tune_axis(c, j)) ? 2 : 1;
+            float best = 0.0f;
+            int pick = 0;
+            for (int v = 0; v < nv && e == hipSuccess; ++v) {
+                // one warm-up launch, then reps timed launches
+                if ((e = tune_launch(p, L, c, j, v)) != hipSuccess) break;
+                if ((e = hipEventRecord(a, p->stream)) != hipSuccess) break;
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = tune_launch(p, L, c, j, v);
+                if (e != hipSuccess) break;
+                if ((e = hipEventRecord(b, p->stream)) != hipSuccess) break;
+                if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+                float ms = 0.0f;
+                if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+                if (v == 0 || ms < best) {
+                    best = ms;
+                    pick = v;
+                }
+            }
+            c.var[j] = pick;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    drop_graphs(p);
+    std::fill(p->has_state.begin(), p->has_state.end(), false);
+    if (e != hipSuccess) return fail(WDM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
     return WDM_OK;
 }
 

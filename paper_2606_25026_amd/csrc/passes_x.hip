@@ -1,0 +1,234 @@
+// P3 and P7: the passes along x (kinetic phase, Green's function), and the
+// spectral kinetic energy.
+#include "passes_common.hpp"
+
+namespace wdm {
+
+// P3: x forward, kinetic phase, x inverse, with the factor tables P1 wrote
+// for this step: complex64 multiplies by each hi + lo pair with one rounding
+// (cmul_split), first by e_x, then by e_yz; complex128 by the FP64 product.
+template <int NX, typename T, int V>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void k_x_kinetic(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<NX, V>::type;
+    using IP = Reversed<FP>;
+    using LN = Lanes<FP, T, true>;
+    constexpr int WG = wg_size<FP, T>();
+    constexpr bool kSplit = std::is_same<T, float>::value;
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
+    // complex64: hi in [0, NX), lo in [NX, 2 NX); complex128: the factor
+    __shared__ cplx<T> ex[kSplit ? 2 * NX : NX];
+    const MemberDev& m = mems[first + blockIdx.y];
+    load_twiddles<NX, WG>(tw, m.tw_x);
+    const cplx<T>* kin = static_cast<const cplx<T>*>(m.kin);
+    constexpr int KE = kSplit ? 2 * NX : NX;   // complex entries of e_x
+    constexpr int KI = (KE + WG - 1) / WG;
+    cplx<T> kr[KI];
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        kr[k] = (KE % WG == 0 || i < KE) ? gld(kin, i) : cplx<T>{T(0), T(0)};
+    }
+    const LN ln;
+    const int64_t ny = m.ny, nz = m.nz;
+    const int64_t plane = ny * nz;
+    const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
+    const bool ok = q < plane;
+    // this pencil's e_yz
+    const int64_t qe = NX + (ok ? q : 0);
+    const cplx<T> yh = gld(kin, kSplit ? 2 * qe : qe);
+    const cplx<T> yl = kSplit ? gld(kin, 2 * qe + 1) : cplx<T>{T(0), T(0)};
+    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
+    cplx<T> v[FP::E];
+    load_slots<FP, FP::first()>(v, psi, q, plane, ok, ln);
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        if (KE % WG == 0 || i < KE) {
+            // complex64 entries alternate hi, lo
+            if constexpr (kSplit)
+                ex[(i & 1) * NX + (i >> 1)] = kr[k];
+            else
+                ex[i] = kr[k];
+        }
+    }
+    __syncthreads();
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+    if constexpr (kSplit) {
+#pragma unroll
+        for (int s = 0; s < FP::E; ++s) {
+            const int e = slot_elem<FP, FP::last()>(ln.t, s);
+            v[s] = cmul_split(cmul_split(v[s], ex[e], ex[NX + e]), yh, yl);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < FP::E; ++s)
+            v[s] = cmul(v[s], cmul(ex[slot_elem<FP, FP::last()>(ln.t, s)], yh));
+    }
+    __syncthreads();
+    pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
+    store_slots<IP, IP::last()>(v, psi, q, plane, ok, ln);
+}
+
+// 1 / x for normal x: hardware reciprocal refined by one Newton step in single
+// precision (within about one unit in the last place); FP64 division otherwise.
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+
+// P7: x forward, Green's function, x inverse, on the half spectrum and the
+// Nyquist plane.  |k|^2 is summed in FP64 from a per-work-group table of k_x^2;
+// the quotient -4 pi G / (|k|^2 N) is taken in the grid precision (its
+// rounding perturbs Phi by one unit in the last place, recomputed every step).
+template <int NX, typename T, int V>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void k_x_green(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<NX, V>::type;
+    using IP = Reversed<FP>;
+    using LN = Lanes<FP, T, true>;
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
+    __shared__ double kx2[NX];
+    const MemberDev& m = mems[first + blockIdx.y];
+    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
+    const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
+    for (int i = int(threadIdx.x); i < NX; i += int(blockDim.x)) {
+        const double kx = cx * signed_mode(i, NX);
+        kx2[i] = kx * kx;
+    }
+    __syncthreads();
+    const LN ln;
+    const int64_t ny = m.ny, h = m.nz / 2;
+    const int64_t main_tiles = (ny * h + LN::PP - 1) / LN::PP;
+    const bool nyq = int64_t(blockIdx.x) >= main_tiles;
+    const int64_t tile = nyq ? blockIdx.x - main_tiles : blockIdx.x;
+    const int64_t plane = nyq ? ny : ny * h;
+    const int64_t q = tile * LN::PP + ln.p;
+    const bool ok = q < plane;
+    const int64_t iy = nyq ? q : q / h;
+    const int64_t iz = nyq ? h : q % h;
+    const double ky = cy * signed_mode(int(iy), int(ny));
+    const double kz = cz * double(iz);
+    const double kyz2 = ky * ky + kz * kz;
+    const T gscale = T(-m.four_pi_G / (double(m.nx) * double(ny) * double(m.nz)));
+    cplx<T>* data = static_cast<cplx<T>*>(nyq ? m.spec_nyq : m.spec);
+    cplx<T> v[FP::E];
+    load_slots<FP, FP::first()>(v, data, q, plane, ok, ln);
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        const T k2 = T(kx2[slot_elem<FP, FP::last()>(ln.t, s)] + kyz2);
+        v[s] = cscale(v[s], k2 > T(0) ? gscale * recip(k2) : T(0));
+    }
+    __syncthreads();
+    pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
+    store_slots<IP, IP::last()>(v, data, q, plane, ok, ln);
+}
+
+
+template <int NX, typename T>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_kinetic_energy(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<NX>::type;
+    using LN = Lanes<FP, T, true>;
+    constexpr int WG = wg_size<FP, T>();
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
+    __shared__ double red[WG];
+    const MemberDev& m = mems[first + blockIdx.y];
+    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
+    __syncthreads();
+    const LN ln;
+    const int64_t ny = m.ny, nz = m.nz, plane = ny * nz;
+    const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
+    const bool ok = q < plane;
+    cplx<T> v[FP::E];
+    load_slots<FP, FP::first()>(v, static_cast<cplx<T>*>(m.scratch), q, plane, ok, ln);
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+    const double cx = kTwoPi / m.lx, cy = kTwoPi / m.ly, cz = kTwoPi / m.lz;
+    const double ky = cy * signed_mode(int(q / nz), int(ny));
+    const double kz = cz * signed_mode(int(q % nz), int(nz));
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        const double kx = cx * signed_mode(slot_elem<FP, FP::last()>(ln.t, s), NX);
+        const double a2 = double(v[s].re) * double(v[s].re) + double(v[s].im) * double(v[s].im);
+        acc += (kx * kx + ky * ky + kz * kz) * a2;
+    }
+    red[threadIdx.x] = ok ? acc : 0.0;
+    __syncthreads();
+    for (int w = WG / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gstr(m.partials, int64_t(blockIdx.x) * kRedFields + 1, red[0]);
+}
+
+
+template <int NX>
+struct XKin {
+    template <typename T, int V>
+    static hipError_t go(const Launch& L, int ny, int nz) {
+        dim3 grid(unsigned(tiles<NX, T, V>(int64_t(ny) * nz)), unsigned(L.count));
+        k_x_kinetic<NX, T, V><<<grid, block<NX, T, V>(), 0, L.stream>>>(L.members, L.first);
+        return hipGetLastError();
+    }
+    template <typename T>
+    static hipError_t pick(const Launch& L, int ny, int nz, int var) {
+        if constexpr (has_variant(NX))
+            if (var == 1) return go<T, 1>(L, ny, nz);
+        return go<T, 0>(L, ny, nz);
+    }
+    static hipError_t run(const Launch& L, int prec, int ny, int nz, int var) {
+        return prec ? pick<double>(L, ny, nz, var) : pick<float>(L, ny, nz, var);
+    }
+};
+
+template <int NX>
+struct XGreen {
+    template <typename T, int V>
+    static hipError_t go(const Launch& L, int ny, int nz) {
+        const int64_t t = tiles<NX, T, V>(int64_t(ny) * (nz / 2)) + tiles<NX, T, V>(ny);
+        dim3 grid(unsigned(t), unsigned(L.count));
+        k_x_green<NX, T, V><<<grid, block<NX, T, V>(), 0, L.stream>>>(L.members, L.first);
+        return hipGetLastError();
+    }
+    template <typename T>
+    static hipError_t pick(const Launch& L, int ny, int nz, int var) {
+        if constexpr (has_variant(NX))
+            if (var == 1) return go<T, 1>(L, ny, nz);
+        return go<T, 0>(L, ny, nz);
+    }
+    static hipError_t run(const Launch& L, int prec, int ny, int nz, int var) {
+        return prec ? pick<double>(L, ny, nz, var) : pick<float>(L, ny, nz, var);
+    }
+};
+
+template <int NX>
+struct XKinE {
+    template <typename T>
+    static hipError_t go(const Launch& L, int ny, int nz) {
+        dim3 grid(unsigned(tiles<NX, T>(int64_t(ny) * nz)), 1u);
+        k_x_kinetic_energy<NX, T><<<grid, block<NX, T>(), 0, L.stream>>>(L.members, L.first);
+        return hipGetLastError();
+    }
+    static hipError_t run(const Launch& L, int prec, int ny, int nz) {
+        return prec ? go<double>(L, ny, nz) : go<float>(L, ny, nz);
+    }
+};
+
+hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz, int variant) {
+    return dispatch_n<XKin>(nx, L, prec, ny, nz, variant);
+}
+hipError_t launch_x_green(const Launch& L, int prec, int nx, int ny, int nz, int variant) {
+    return dispatch_n<XGreen>(nx, L, prec, ny, nz, variant);
+}
+hipError_t launch_x_kinetic_energy(const Launch& L, int prec, int nx, int ny, int nz) {
+    return dispatch_n<XKinE>(nx, L, prec, ny, nz);
+}
+
+}  // namespace wdm

@@ -1,0 +1,208 @@
+// P1 and P5: the passes along the contiguous z axis.
+#include "passes_common.hpp"
+
+namespace wdm {
+
+// ===========================================================================
+// P1: potential from the half spectrum, kick, optional forward z-FFT.
+// ===========================================================================
+template <int NZ, typename T, int OP, int KICK, int V>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void k_z_potential_kick(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<NZ, V>::type;
+    using IP = Reversed<FP>;
+    using LN = Lanes<FP, T, false>;
+    constexpr int PP = LN::PP;
+    constexpr int H = NZ / 2;
+    __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
+    __shared__ cplx<T> tw[tw_entries<T>(NZ)];
+    const MemberDev& m = mems[first + blockIdx.y];
+    const LN ln;
+    const int64_t npen = int64_t(m.nx) * m.ny;
+    const int64_t q = int64_t(blockIdx.x) * PP + ln.p;
+    const bool ok = q < npen;
+    load_twiddles<NZ, wg_size<FP, T>()>(tw, m.tw_z);
+    // psi is loaded together with the spectrum: one memory wait per pass
+    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
+    cplx<T> w[OP == kZPhiOnly ? 1 : FP::E];
+    if constexpr (OP != kZPhiOnly) load_slots<FP, FP::first()>(w, psi, q * NZ, 1, ok, ln);
+    // half spectrum e in [0, H) (H / T per lane) and the Nyquist element e = H,
+    // all loads issued before the LDS writes
+    static_assert(H % FP::T == 0, "half pencil must split evenly over the lanes");
+    constexpr int HE = H / FP::T;
+    const cplx<T>* spec = static_cast<const cplx<T>*>(m.spec) + q * H + ln.t;
+    cplx<T> hs[HE + 1];
+#pragma unroll
+    for (int k = 0; k < HE; ++k) hs[k] = ok ? gld(spec, k * FP::T) : cplx<T>{T(0), T(0)};
+    hs[HE] = (ok && ln.t == 0) ? gld(static_cast<const cplx<T>*>(m.spec_nyq), q)
+                               : cplx<T>{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < HE; ++k) lds[ln(ln.t + k * FP::T)] = hs[k];
+    if (ln.t == 0) lds[ln(H)] = hs[HE];
+    __syncthreads();
+    // Hermitian completion F[e] = conj(F[NZ - e]) for e > NZ/2, in the input
+    // layout of the inverse plan
+    cplx<T> v[FP::E];
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        const int e = slot_elem<IP, IP::first()>(ln.t, s);
+        v[s] = e <= H ? lds[ln(e)] : conj(lds[ln(NZ - e)]);
+    }
+    __syncthreads();
+    pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
+    // output layout of IP == input layout of FP
+    T phi[FP::E];
+    T* gphi = static_cast<T*>(m.phi) + q * NZ;
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        phi[s] = v[s].re;
+        if (ok) gstr(gphi, slot_elem<FP, FP::first()>(ln.t, s), phi[s]);
+    }
+    if constexpr (OP == kZPhiOnly) return;
+    const double dt = gldr(m.dt, 0);
+    const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
+    const double c = -tau / m.eta;
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) v[s] = rotate(w[s], double(phi[s]) * c);
+    if constexpr (OP == kZKickOnly) {
+        store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+        return;
+    }
+    __syncthreads();
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+    store_slots<FP, FP::last()>(v, psi, q * NZ, 1, ok, ln);
+    write_kinetic_table<T>(m, dt, int64_t(gridDim.x) * blockDim.x,
+                           int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+
+// ===========================================================================
+// P5: inverse z-FFT of psi, density, R2C forward z-FFT into the half spectrum.
+// ===========================================================================
+template <int NZ, typename T, int OP, int V>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void k_z_density(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<NZ, V>::type;
+    using IP = Reversed<FP>;
+    using LN = Lanes<FP, T, false>;
+    constexpr int PP = LN::PP;
+    constexpr int H = NZ / 2;
+    __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
+    __shared__ cplx<T> tw[tw_entries<T>(NZ)];
+    const MemberDev& m = mems[first + blockIdx.y];
+    const LN ln;
+    const int64_t npen = int64_t(m.nx) * m.ny;
+    const int64_t q = int64_t(blockIdx.x) * PP + ln.p;
+    const bool ok = q < npen;
+    load_twiddles<NZ, wg_size<FP, T>()>(tw, m.tw_z);
+    cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
+    cplx<T> v[FP::E];
+    // the baryon density is loaded together with psi: one memory wait per pass
+    T* rb = static_cast<T*>(m.rho_b) + q * NZ + ln.t;
+    T rbv[FP::E];
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) rbv[s] = ok ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
+    if constexpr (OP == kDensInvFft) {
+        load_slots<IP, IP::first()>(v, psi, q * NZ, 1, ok, ln);
+        __syncthreads();
+        pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
+        store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+    } else {
+        load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
+        if (ok) gstr(rb, slot_const<FP, FP::first()>(s), T(0));
+    }
+    __syncthreads();
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+    if (!ok) return;
+    cplx<T>* spec = static_cast<cplx<T>*>(m.spec) + q * H;
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        const int e = slot_elem<FP, FP::last()>(ln.t, s);
+        if (e < H)
+            gst(spec, e, v[s]);
+        else if (e == H)
+            gst(static_cast<cplx<T>*>(m.spec_nyq), q, v[s]);
+    }
+}
+
+
+template <int NZ>
+struct ZPotKick {
+    template <typename T, int V>
+    static hipError_t go(const Launch& L, int nx, int ny, ZOp op, KickMode k) {
+        dim3 grid(unsigned(tiles<NZ, T, V>(int64_t(nx) * ny)), unsigned(L.count));
+        const dim3 b = block<NZ, T, V>();
+        if constexpr (V == 0) {
+            if (op == kZPhiOnly) {
+                k_z_potential_kick<NZ, T, kZPhiOnly, kHalfKick, 0>
+                    <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                return hipGetLastError();
+            }
+            if (op == kZKickOnly) {
+                if (k == kHalfKick)
+                    k_z_potential_kick<NZ, T, kZKickOnly, kHalfKick, 0>
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                else
+                    k_z_potential_kick<NZ, T, kZKickOnly, kFullKick, 0>
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                return hipGetLastError();
+            }
+        }
+        if (k == kHalfKick)
+            k_z_potential_kick<NZ, T, kZKickFft, kHalfKick, V>
+                <<<grid, b, 0, L.stream>>>(L.members, L.first);
+        else
+            k_z_potential_kick<NZ, T, kZKickFft, kFullKick, V>
+                <<<grid, b, 0, L.stream>>>(L.members, L.first);
+        return hipGetLastError();
+    }
+    template <typename T>
+    static hipError_t pick(const Launch& L, int nx, int ny, ZOp op, KickMode k, int var) {
+        // only the merged kick + z-FFT variant has a second plan
+        if constexpr (has_variant(NZ))
+            if (var == 1 && op == kZKickFft) return go<T, 1>(L, nx, ny, op, k);
+        return go<T, 0>(L, nx, ny, op, k);
+    }
+    static hipError_t run(const Launch& L, int prec, int nx, int ny, ZOp op, KickMode k, int var) {
+        return prec ? pick<double>(L, nx, ny, op, k, var) : pick<float>(L, nx, ny, op, k, var);
+    }
+};
+
+template <int NZ>
+struct ZDens {
+    template <typename T, int V>
+    static hipError_t go(const Launch& L, int nx, int ny, DensOp op) {
+        dim3 grid(unsigned(tiles<NZ, T, V>(int64_t(nx) * ny)), unsigned(L.count));
+        const dim3 b = block<NZ, T, V>();
+        if (V == 0 && op == kDensDirect)
+            k_z_density<NZ, T, kDensDirect, 0><<<grid, b, 0, L.stream>>>(L.members, L.first);
+        else
+            k_z_density<NZ, T, kDensInvFft, V><<<grid, b, 0, L.stream>>>(L.members, L.first);
+        return hipGetLastError();
+    }
+    template <typename T>
+    static hipError_t pick(const Launch& L, int nx, int ny, DensOp op, int var) {
+        if constexpr (has_variant(NZ))
+            if (var == 1 && op == kDensInvFft) return go<T, 1>(L, nx, ny, op);
+        return go<T, 0>(L, nx, ny, op);
+    }
+    static hipError_t run(const Launch& L, int prec, int nx, int ny, DensOp op, int var) {
+        return prec ? pick<double>(L, nx, ny, op, var) : pick<float>(L, nx, ny, op, var);
+    }
+};
+
+hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, int nz, ZOp op,
+                                   KickMode kick, int variant) {
+    return dispatch_n<ZPotKick>(nz, L, prec, nx, ny, op, kick, variant);
+}
+hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op,
+                            int variant) {
+    return dispatch_n<ZDens>(nz, L, prec, nx, ny, op, variant);
+}
+
+}  // namespace wdm

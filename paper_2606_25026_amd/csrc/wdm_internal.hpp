@@ -84,20 +84,25 @@ enum KickMode : int { kHalfKick = 0, kFullKick = 1 };
 enum ZOp : int { kZKickFft = 0, kZKickOnly = 1, kZPhiOnly = 2 };
 enum DensOp : int { kDensInvFft = 0, kDensDirect = 1 };
 
-// ---- FFT passes (passes.hip); `prec` is 0 for complex64, 1 for complex128 ----
+// ---- FFT passes (passes_z.hip, passes_y.hip, passes_x.hip); `prec` is 0 for complex64, 1 for complex128 ----
 bool axis_supported(int n);
+// True where the axis length has a second FFT plan (the autotuner's choice).
+bool axis_has_variant(int n);
 // P1: half spectrum -> Phi (C2R along z), then kick and optionally z-FFT.
 hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, int nz, ZOp op,
-                                   KickMode kick);
+                                   KickMode kick, int variant = 0);
 // P2 / P4 on psi, P6 / P8 on the half spectrum (+ Nyquist plane).
-hipError_t launch_y_fft_psi(const Launch& L, int prec, int nx, int ny, int nz, bool inverse);
-hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, bool inverse);
+hipError_t launch_y_fft_psi(const Launch& L, int prec, int nx, int ny, int nz, bool inverse,
+                            int variant = 0);
+hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, bool inverse,
+                             int variant = 0);
 // P3: x forward, kinetic phase exp(-i eta |k|^2 dt/2)/N, x inverse.
-hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz);
+hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz, int variant = 0);
 // P5: z inverse of psi (optional), rho = |psi|^2 + rho_b (rho_b cleared), R2C along z.
-hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op);
+hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op,
+                            int variant = 0);
 // P7: x forward, Green's function -4 pi G / |k|^2 / N, x inverse (+ Nyquist plane).
-hipError_t launch_x_green(const Launch& L, int prec, int nx, int ny, int nz);
+hipError_t launch_x_green(const Launch& L, int prec, int nx, int ny, int nz, int variant = 0);
 // Plain 3D transforms between psi-shaped buffers: axis 0 = x, 1 = y, 2 = z.
 // `which` selects the member field: 0 = psi, 1 = scratch.
 hipError_t launch_axis_fft(const Launch& L, int prec, int nx, int ny, int nz, int axis,

@@ -232,7 +232,10 @@ def run(cfg: LearnedConfig, device="cuda", log=print) -> dict:
     t_train = time.perf_counter() - t1
     del xs, ys
     torch.cuda.empty_cache()
-    judged = [judge(cfg, pipe, net, scales, s, device) for s in cfg.heldout_seeds]
+    judged = []
+    for s in cfg.heldout_seeds:
+        judged.append(judge(cfg, pipe, net, scales, s, device))
+        log(f"# judge: seed {s}: {judged[-1]}")
     err_with = float(np.mean([j["err_with_net"] for j in judged]))
     err_without = float(np.mean([j["err_without_net"] for j in judged]))
     t_f, t_c = seconds_per_unit_time(cfg, pipe, net, scales)

@@ -66,6 +66,10 @@ _SIGS = {
     "wdm_fft3d": (C.c_int, [_vp, _i32, _i32]),
     "wdm_set_sort_interval": (C.c_int, [_vp, _i32]),
     "wdm_use_graphs": (C.c_int, [_vp, _i32]),
+    "wdm_autotune": (C.c_int, [_vp, _i32]),
+    "wdm_tuning_entries": (_i32, [_vp]),
+    "wdm_get_tuning": (C.c_int, [_vp, C.POINTER(_i32), _i32]),
+    "wdm_set_tuning": (C.c_int, [_vp, C.POINTER(_i32), _i32]),
     "wdm_profile": (C.c_int, [_vp, _i32]),
     "wdm_profile_read": (C.c_int, [_vp, C.POINTER(wdm_kernel_stat), _i32, C.POINTER(_i32)]),
     "wdm_copy_bandwidth": (C.c_int, [_vp, _vp, C.c_size_t, _i32, _vp, C.POINTER(_f64)]),
@@ -207,6 +211,58 @@ def wdm_set_sort_interval(plan, interval):
 
 def wdm_use_graphs(plan, enable=True):
     _check(load().wdm_use_graphs(plan, 1 if enable else 0))
+
+
+def wdm_autotune(plan, reps=10):
+    _check(load().wdm_autotune(plan, int(reps)))
+
+
+def wdm_tuning_entries(plan):
+    return int(load().wdm_tuning_entries(plan))
+
+
+def wdm_get_tuning(plan):
+    n = wdm_tuning_entries(plan)
+    out = (_i32 * n)()
+    _check(load().wdm_get_tuning(plan, out, n))
+    return [int(v) for v in out]
+
+
+def wdm_set_tuning(plan, table):
+    n = len(table)
+    arr = (_i32 * n)(*[int(v) for v in table])
+    _check(load().wdm_set_tuning(plan, arr, n))
+
+
+def tuning_key(configs) -> str:
+    """Cache key of a plan's tuning table: its distinct grid shapes in the
+    order of its size classes, and the precision."""
+    configs = [configs] if isinstance(configs, wdm_config) else list(configs)
+    shapes = sorted({(c.nx, c.ny, c.nz) for c in configs})
+    return f"{'c128' if configs[0].precision else 'c64'}:" + ";".join(
+        f"{a}x{b}x{c}" for a, b, c in shapes)
+
+
+def autotune(plan, configs, cache=None, reps=10):
+    """Choose the step passes' FFT plans: from the JSON file `cache` when it
+    holds this plan's key, else by wdm_autotune (and store the result there).
+    Overwrites the members' states (set them afterwards).  Returns the table."""
+    import json
+    from pathlib import Path
+
+    key = tuning_key(configs)
+    store = {}
+    if cache is not None and Path(cache).exists():
+        store = json.loads(Path(cache).read_text())
+        if key in store and len(store[key]) == wdm_tuning_entries(plan):
+            wdm_set_tuning(plan, store[key])
+            return list(store[key])
+    wdm_autotune(plan, reps)
+    table = wdm_get_tuning(plan)
+    if cache is not None:
+        store[key] = table
+        Path(cache).write_text(json.dumps(store, indent=1))
+    return table
 
 
 def wdm_profile(plan, enable=True):

@@ -25,8 +25,9 @@ def halo():
     return inputs.coupled_halo(n=256, n_particles=1_000_000, seed=0)
 
 
+@pytest.mark.parametrize("plans", ["default", "second"])
 @pytest.mark.parametrize("sort_interval", [32])
-def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval):
+def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval, plans):
     g = np.load(GOLDEN)
     wl = halo
     # the generator must reproduce the stored initial samples
@@ -34,6 +35,8 @@ def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval):
     steps = int(g["steps"])
     cfg = wdm.make_config(256, n_particles=wl.n_particles, particle_mass=wl.particle_mass)
     plan = wdm.Plan(cfg)
+    if plans == "second":     # every tunable pass on its second FFT plan
+        wdm.wdm_set_tuning(plan.handle, [1] * wdm.wdm_tuning_entries(plan.handle))
     psi = torch.from_numpy(wl.psi.astype(np.complex64)).cuda()
     pos = torch.from_numpy(wl.pos).cuda()
     vel = torch.from_numpy(wl.vel).cuda()
@@ -55,7 +58,7 @@ def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval):
     vv = v.cpu().numpy()[g["parts"]].astype(np.float64)
     perr = float(np.max(np.abs(periodic_diff(pp, g["pos"]))))
     verr = float(np.linalg.norm(vv - g["vel"]) / np.linalg.norm(g["vel"]))
-    print(f"256^3 + 1e6 particles, {steps} steps: psi rel L2 (65536 samples) {err:.3e}, "
+    print(f"[{plans} plans] 256^3 + 1e6 particles, {steps} steps: psi rel L2 (65536 samples) {err:.3e}, "
           f"max |dx| {perr:.2e}, vel rel L2 {verr:.2e}, mass drift {e1['mass'] / e0['mass'] - 1:.2e}")
     assert err < 1e-5
     assert perr < 1e-5
