@@ -106,6 +106,7 @@ def bench_ensemble(args):
             for m in members]
     plan = wdm.Plan(cfgs)
     h = plan.handle
+    tuning = wdm.autotune(h, cfgs, reps=10) if not args.no_tune else wdm.wdm_get_tuning(h)
     keep = []
     for i, m in enumerate(members):
         psi = torch.from_numpy(m.psi.astype(np.complex64)).cuda()
@@ -131,7 +132,8 @@ def bench_ensemble(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
            "data": "synthetic",
            "config": {"workload": "ensemble 16x64^3 + 16x96^3 + 16x128^3, 1e4 particles each",
-                      "members": len(members), "cells": cells, "particles": parts},
+                      "members": len(members), "cells": cells, "particles": parts,
+                      "fft_plan_variants": tuning},
            "step_roofline": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": gbs / HBM_PEAK_GBS}}
     print(json.dumps(out))
@@ -244,6 +246,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel HIP events")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default FFT plan of every pass (no autotuning)")
     ap.add_argument("--workload", choices=["halo", "ensemble", "precision", "learned"],
                     default="halo")
     ap.add_argument("--learned-small", action="store_true")
@@ -271,6 +275,8 @@ def main():
     cfg = wdm.make_config(args.n, n_particles=wl.n_particles, particle_mass=wl.particle_mass)
     plan = wdm.Plan(cfg, device=dev)
     h = plan.handle
+    # choose each step pass's FFT plan by timing (before the state is set)
+    tuning = wdm.autotune(h, cfg, reps=10) if not args.no_tune else wdm.wdm_get_tuning(h)
     psi = torch.from_numpy(wl.psi.astype(np.complex64)).to(dev)
     pos = torch.from_numpy(wl.pos).to(dev) if wl.n_particles else None
     vel = torch.from_numpy(wl.vel).to(dev) if wl.n_particles else None
@@ -366,6 +372,7 @@ def main():
                                "Plummer particles (GRF k0=16*2pi + soliton rc=0.05)",
                    "grid": args.n, "particles": wl.n_particles, "dt": wl.dt,
                    "phase_args": "fp64", "sort_interval": args.sort_interval,
+                   "fft_plan_variants": dict(zip(["P1", "P2/P4", "P3", "P5", "P6/P8", "P7"], tuning)),
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "step_roofline": {"bytes_per_cell_update": step_bytes / n3, "achieved": step_gbs,

@@ -111,11 +111,11 @@ def test_autotune_overwrites_state_and_validates_tables(wdm):
         wdm.wdm_set_tuning(plan.handle, [2] + [0] * 11)      # not 0 / 1
     assert wdm.wdm_get_tuning(plan.handle) == [0] * 12       # unchanged
     ok = [0] * 12
-    ok[6:] = [1] * 6     # classes in ascending shape order: 32^3 second
+    ok[:6] = [1] * 6     # classes in ascending shape order: 32^3 first
     wdm.wdm_set_tuning(plan.handle, ok)
     assert wdm.wdm_get_tuning(plan.handle) == ok
     wdm.wdm_autotune(plan.handle, 2)
-    assert wdm.wdm_get_tuning(plan.handle)[:6] == [0] * 6
+    assert wdm.wdm_get_tuning(plan.handle)[6:] == [0] * 6
     with pytest.raises(wdm.WdmError):
         wdm.wdm_step(plan.handle, 1, 1e-4)                  # states were overwritten
     plan.close()
