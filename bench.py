@@ -184,7 +184,9 @@ def bench_precision(args):
     dt = 0.2 / n ** 2
     outs = {}
     for prec, dt_ in ((0, torch.complex64), (1, torch.complex128)):
-        plan = wdm.Plan(wdm.make_config(n, precision=prec))
+        cfg = wdm.make_config(n, precision=prec)
+        plan = wdm.Plan(cfg)
+        tuning = wdm.autotune(plan.handle, cfg, reps=5) if not args.no_tune else [0] * 6
         x = torch.from_numpy(psi0).to(dt_).cuda()
         wdm.wdm_set_state(plan.handle, 0, x)
         e0 = wdm.wdm_energy(plan.handle, 0)
@@ -201,7 +203,8 @@ def bench_precision(args):
             "ms_per_step": el * 1e3 / args.precision_steps,
             "cell_updates_per_s": n ** 3 * args.precision_steps / el,
             "mass_drift": e1["mass"] / e0["mass"] - 1,
-            "energy_drift": e1["e_total"] / e0["e_total"] - 1}
+            "energy_drift": e1["e_total"] / e0["e_total"] - 1,
+            "fft_plan_variants": tuning}
         plan.close()
         log(f"{n}^3 {'c64' if prec == 0 else 'c128'} done: {res[f'grid{n}_' + ('c64' if prec == 0 else 'c128')]}")
     d = outs[0].to(torch.complex128) - outs[1]
