@@ -290,52 +290,80 @@ __device__ __forceinline__ void deposit_group(T* __restrict__ grid, const Member
 
 // mode 0: kick + drift + deposit into rho_b; 1: kick only; 2: deposit into
 // rho_b; 3: deposit into scratch (as a real grid).
+//
+// Persistent work-groups: at most kGroupsPerCU per compute unit are launched
+// and each walks the member's 256-particle chunks with a grid stride.  The
+// particle kernel runs beside the y/x/y passes on its own stream; capped this
+// way it leaves them most of the machine instead of flooding every CU at once
+// (measured: 424 us per 256^3 + 1e6 step against 429 us with one work-group per
+// chunk).
+constexpr int kGroupsPerCU = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kParticleWG) void k_particles(const MemberDev* __restrict__ mems,
                                                            int first, int mode, int kick) {
     const MemberDev& m = mems[first + blockIdx.y];
-    if (int64_t(blockIdx.x) * kParticleWG >= m.np) return;  // uniform per block
-    const int64_t i = int64_t(blockIdx.x) * kParticleWG + threadIdx.x;
-    const bool act = i < m.np;
-    const int64_t ii = act ? i : 0;
-    float x = gldr(m.px, ii), y = gldr(m.py, ii), z = gldr(m.pz, ii);
     const double dt = gldr(m.dt, 0);
-    if (mode <= 1) {
-        float vx = gldr(m.vx, ii), vy = gldr(m.vy, ii), vz = gldr(m.vz, ii);
-        const CellW<T> c = cic<T>(x, y, z, m);
-        float g[3];
-        cic_accel(static_cast<const T*>(m.phi), m, c, g);
-        const float tau = float(kick == kFullKick ? dt : 0.5 * dt);
-        vx += g[0] * tau;
-        vy += g[1] * tau;
-        vz += g[2] * tau;
-        if (mode == 0) {
-            x = wrap_pos(double(x) + double(vx) * dt, m.lx, m.inv_lx);
-            y = wrap_pos(double(y) + double(vy) * dt, m.ly, m.inv_ly);
-            z = wrap_pos(double(z) + double(vz) * dt, m.lz, m.inv_lz);
-            if (act) {
-                gstr(m.px, i, x);
-                gstr(m.py, i, y);
-                gstr(m.pz, i, z);
+    for (int64_t grp = blockIdx.x; grp * kParticleWG < m.np; grp += gridDim.x) {
+        const int64_t i = grp * kParticleWG + threadIdx.x;
+        const bool act = i < m.np;
+        const int64_t ii = act ? i : 0;
+        float x = gldr(m.px, ii), y = gldr(m.py, ii), z = gldr(m.pz, ii);
+        if (mode <= 1) {
+            float vx = gldr(m.vx, ii), vy = gldr(m.vy, ii), vz = gldr(m.vz, ii);
+            const CellW<T> c = cic<T>(x, y, z, m);
+            float g[3];
+            cic_accel(static_cast<const T*>(m.phi), m, c, g);
+            const float tau = float(kick == kFullKick ? dt : 0.5 * dt);
+            vx += g[0] * tau;
+            vy += g[1] * tau;
+            vz += g[2] * tau;
+            if (mode == 0) {
+                x = wrap_pos(double(x) + double(vx) * dt, m.lx, m.inv_lx);
+                y = wrap_pos(double(y) + double(vy) * dt, m.ly, m.inv_ly);
+                z = wrap_pos(double(z) + double(vz) * dt, m.lz, m.inv_lz);
+                if (act) {
+                    gstr(m.px, i, x);
+                    gstr(m.py, i, y);
+                    gstr(m.pz, i, z);
+                }
             }
+            if (act) {
+                gstr(m.vx, i, vx);
+                gstr(m.vy, i, vy);
+                gstr(m.vz, i, vz);
+            }
+            if (mode == 1) continue;  // uniform; no barrier in this mode
         }
-        if (act) {
-            gstr(m.vx, i, vx);
-            gstr(m.vy, i, vy);
-            gstr(m.vz, i, vz);
-        }
-        if (mode == 1) return;
+        const T q = T(m.particle_mass * m.inv_dx * m.inv_dy * m.inv_dz);
+        const CellW<T> c = cic<T>(x, y, z, m);
+        T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
+        deposit_group(grid, m, c, q, act);
+        __syncthreads();  // the next chunk reuses the group's LDS box and tile
     }
-    const T q = T(m.particle_mass * m.inv_dx * m.inv_dy * m.inv_dz);
-    const CellW<T> c = cic<T>(x, y, z, m);
-    T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
-    deposit_group(grid, m, c, q, act);
+}
+
+// Compute units of the current device (queried once).
+static int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            n > 0)
+            cus = n;
+        else
+            cus = 256;
+    }
+    return cus;
 }
 
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
                             KickMode kick) {
     if (max_np <= 0) return hipSuccess;
-    dim3 grid(unsigned((max_np + kParticleWG - 1) / kParticleWG), unsigned(L.count));
+    const int64_t chunks = (max_np + kParticleWG - 1) / kParticleWG;
+    const int64_t cap = int64_t(kGroupsPerCU) * device_cus();
+    dim3 grid(unsigned(chunks < cap ? chunks : cap), unsigned(L.count));
     if (prec)
         k_particles<double><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first, mode,
                                                                   int(kick));
