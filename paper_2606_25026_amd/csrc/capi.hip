@@ -465,7 +465,7 @@ wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const flo
     HIPCHK(launch_zero(p->stream, m.rho_b, size_t(n) * (p->prec ? 8 : 4)));
     if (c.n_particles > 0) {
         HIPCHK(launch_particle_upload(p->stream, m, pos, vel));
-        HIPCHK(launch_particle_sort(p->stream, m, p->table, p->prec));
+        HIPCHK(launch_particle_sort(L, c.n_particles, c.nx, c.ny, c.nz));
         HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick));
     }
     HIPCHK(potential_from_state(p, L, c));
@@ -557,10 +557,8 @@ hipError_t enqueue_sort(wdm_plan* p, hipStream_t s) {
     for (const auto& c : p->classes) {
         if (c.max_np <= 1) continue;
         e = timed(p, kKSort, [&] {
-            hipError_t r = hipSuccess;
-            for (int d = c.first; d < c.first + c.count && r == hipSuccess; ++d)
-                r = launch_particle_sort(s, p->host[d], p->table, p->prec);
-            return r;
+            return launch_particle_sort(Launch{s, p->table, c.first, c.count}, c.max_np, c.nx,
+                                        c.ny, c.nz);
         });
         if (e != hipSuccess) return e;
     }

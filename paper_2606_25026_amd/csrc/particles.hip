@@ -432,10 +432,20 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     return v;
 }
 
+// Sort kernels work on a size class of members at once: blockIdx.y selects
+// the member in the device table, each member sorts its own np particles with
+// its own histogram (members of a class share the key width), and work-groups
+// beyond a member's range return at once.  Members with at most one particle
+// skip every stage.
+__device__ __forceinline__ int sort_tiles(int64_t np) {
+    return int((np + kSortTile - 1) / kSortTile);
+}
+
 // Sort key: Morton (bit-interleaved) index of the particle's cell, so that
 // particles close in space are close in memory in all three directions and a
 // work-group's force gathers and deposits stay within a compact patch.
-__global__ void k_make_keys(MemberDev m) {
+__global__ void k_make_keys(const MemberDev* __restrict__ mems, int first) {
+    const MemberDev& m = mems[first + blockIdx.y];
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= m.np) return;
     const CellW<float> c = cic<float>(m.px[i], m.py[i], m.pz[i], m);
@@ -456,12 +466,17 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid
     return mask;
 }
 
-// Per-block digit counts.  Keys of one block mostly share their high digits
-// (particles are clustered), so equal digits are first counted across the
-// wavefront and one lane per digit adds the group size.
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
-                                                    int shift, uint32_t* __restrict__ hist,
-                                                    int nblocks) {
+// Per-block digit counts of pass `pass` (keys in key_a for even passes, key_b
+// for odd).  Keys of one block mostly share their high digits (particles are
+// clustered), so equal digits are first counted across the wavefront and one
+// lane per digit adds the group size.
+__global__ __launch_bounds__(256) void k_radix_hist(const MemberDev* __restrict__ mems, int first,
+                                                    int pass) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    const int nb = sort_tiles(m.np);
+    if (m.np <= 1 || int(blockIdx.x) >= nb) return;  // uniform per block
+    const uint32_t* keys = (pass & 1) ? m.key_b : m.key_a;
+    const int shift = 8 * pass;
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -470,23 +485,27 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
     for (int r = 0; r < kSortTile / 256; ++r) {
         const int64_t i = b0 + r * 256 + threadIdx.x;
-        const bool valid = i < n;
+        const bool valid = i < m.np;
         const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
         const unsigned long long mask = match_digit(d, valid);
         if (valid && __popcll(mask & lt) == 0) atomicAdd(&cnt[d], uint32_t(__popcll(mask)));
     }
     __syncthreads();
-    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    m.hist[int64_t(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // Exclusive scan of the digit-major histogram hist[d * nb + b] in two small
 // kernels: each of 256 blocks scans one digit's column over the nb tile blocks
-// (and records the digit total); one block then scans the 256 totals, which
-// k_radix_scatter adds as the digit base.
-__global__ __launch_bounds__(256) void k_scan_digit(uint32_t* __restrict__ hist,
-                                                    uint32_t* __restrict__ totals, int nb) {
+// (and records the digit total after the histogram, at hist + 256 nb); one
+// block then scans the 256 totals, which k_radix_scatter adds as the digit
+// base.
+__global__ __launch_bounds__(256) void k_scan_digit(const MemberDev* __restrict__ mems,
+                                                    int first) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    if (m.np <= 1) return;
+    const int nb = sort_tiles(m.np);
     __shared__ uint32_t s[256];
-    uint32_t* col = hist + int64_t(blockIdx.x) * nb;
+    uint32_t* col = m.hist + int64_t(blockIdx.x) * nb;
     uint32_t carry = 0;
     for (int b0 = 0; b0 < nb; b0 += 256) {
         const int b = b0 + int(threadIdx.x);
@@ -503,10 +522,14 @@ __global__ __launch_bounds__(256) void k_scan_digit(uint32_t* __restrict__ hist,
         carry += s[255];
         __syncthreads();
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) m.hist[int64_t(256) * nb + blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scan_totals(uint32_t* __restrict__ totals) {
+__global__ __launch_bounds__(256) void k_scan_totals(const MemberDev* __restrict__ mems,
+                                                     int first) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    if (m.np <= 1) return;
+    uint32_t* totals = m.hist + int64_t(256) * sort_tiles(m.np);
     __shared__ uint32_t s[256];
     const uint32_t v = totals[threadIdx.x];
     s[threadIdx.x] = v;
@@ -520,25 +543,32 @@ __global__ __launch_bounds__(256) void k_scan_totals(uint32_t* __restrict__ tota
     totals[threadIdx.x] = s[threadIdx.x] - v;
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin,
-                                                       uint32_t* __restrict__ kout,
-                                                       uint32_t* __restrict__ vout, int64_t n,
-                                                       int shift,
-                                                       const uint32_t* __restrict__ hist,
-                                                       const uint32_t* __restrict__ totals,
-                                                       int nblocks) {
+// Stable scatter of pass `pass`: (key_a, idx_a) -> (key_b, idx_b) for even
+// passes, the reverse for odd ones.
+__global__ __launch_bounds__(256) void k_radix_scatter(const MemberDev* __restrict__ mems,
+                                                       int first, int pass) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    const int nb = sort_tiles(m.np);
+    if (m.np <= 1 || int(blockIdx.x) >= nb) return;  // uniform per block
+    const bool odd = (pass & 1) != 0;
+    const uint32_t* kin = odd ? m.key_b : m.key_a;
+    const uint32_t* vin = odd ? m.idx_b : m.idx_a;
+    uint32_t* kout = odd ? m.key_a : m.key_b;
+    uint32_t* vout = odd ? m.idx_a : m.idx_b;
+    const int shift = 8 * pass;
+    const uint32_t* hist = m.hist;
+    const uint32_t* totals = m.hist + int64_t(256) * nb;
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
-    base[tid] = totals[tid] + hist[int64_t(tid) * nblocks + blockIdx.x];
+    base[tid] = totals[tid] + hist[int64_t(tid) * nb + blockIdx.x];
     for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
     for (int r = 0; r < kSortTile / 256; ++r) {
         const int64_t i = b0 + r * 256 + tid;
-        const bool valid = i < n;
+        const bool valid = i < m.np;
         const uint32_t k = valid ? kin[i] : 0u;
         const uint32_t d = (k >> shift) & 255u;
         const unsigned long long mask = match_digit(d, valid);
@@ -558,10 +588,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     }
 }
 
-__global__ void k_gather_sorted(MemberDev m, const uint32_t* __restrict__ idx) {
+// Particles into sorted order through the staging arrays; the permutation
+// is in idx_a after an even number of passes, idx_b after an odd number.
+__global__ void k_gather_sorted(const MemberDev* __restrict__ mems, int first, int passes) {
+    const MemberDev& m = mems[first + blockIdx.y];
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= m.np) return;
-    const uint32_t s = idx[i];
+    if (m.np <= 1 || i >= m.np) return;  // one particle or none: nothing to reorder
+    const uint32_t s = ((passes & 1) ? m.idx_b : m.idx_a)[i];
     m.apx[i] = m.px[s];
     m.apy[i] = m.py[s];
     m.apz[i] = m.pz[s];
@@ -571,9 +604,10 @@ __global__ void k_gather_sorted(MemberDev m, const uint32_t* __restrict__ idx) {
     m.aid[i] = m.id[s];
 }
 
-__global__ void k_copy_back(MemberDev m) {
+__global__ void k_copy_back(const MemberDev* __restrict__ mems, int first) {
+    const MemberDev& m = mems[first + blockIdx.y];
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= m.np) return;
+    if (m.np <= 1 || i >= m.np) return;
     m.px[i] = m.apx[i];
     m.py[i] = m.apy[i];
     m.pz[i] = m.apz[i];
@@ -585,27 +619,23 @@ __global__ void k_copy_back(MemberDev m) {
 
 int sort_blocks(int64_t np) { return int((np + kSortTile - 1) / kSortTile); }
 
-hipError_t launch_particle_sort(hipStream_t s, const MemberDev& m, const MemberDev* /*dev*/,
-                                int /*prec*/) {
-    if (m.np <= 1) return hipSuccess;
-    const unsigned g = unsigned((m.np + 255) / 256);
-    k_make_keys<<<g, 256, 0, s>>>(m);
+hipError_t launch_particle_sort(const Launch& L, int64_t max_np, int nx, int ny, int nz) {
+    if (max_np <= 1) return hipSuccess;
+    const unsigned y = unsigned(L.count);
+    const dim3 g(unsigned((max_np + 255) / 256), y);
+    const dim3 t(unsigned(sort_blocks(max_np)), y);
     int axis_bits = 0;
-    while ((1 << axis_bits) < std::max(m.nx, std::max(m.ny, m.nz))) ++axis_bits;
-    const int bits = 3 * axis_bits;   // Morton key width
-    const int nb = sort_blocks(m.np);
-    uint32_t *ka = m.key_a, *kb = m.key_b, *va = m.idx_a, *vb = m.idx_b;
-    uint32_t* totals = m.hist + int64_t(256) * nb;   // 256 digit bases after the histogram
-    for (int shift = 0; shift < bits; shift += 8) {
-        k_radix_hist<<<nb, 256, 0, s>>>(ka, m.np, shift, m.hist, nb);
-        k_scan_digit<<<256, 256, 0, s>>>(m.hist, totals, nb);
-        k_scan_totals<<<1, 256, 0, s>>>(totals);
-        k_radix_scatter<<<nb, 256, 0, s>>>(ka, va, kb, vb, m.np, shift, m.hist, totals, nb);
-        std::swap(ka, kb);
-        std::swap(va, vb);
+    while ((1 << axis_bits) < std::max(nx, std::max(ny, nz))) ++axis_bits;
+    const int passes = (3 * axis_bits + 7) / 8;   // 8-bit digits of the Morton key
+    k_make_keys<<<g, 256, 0, L.stream>>>(L.members, L.first);
+    for (int pass = 0; pass < passes; ++pass) {
+        k_radix_hist<<<t, 256, 0, L.stream>>>(L.members, L.first, pass);
+        k_scan_digit<<<dim3(256, y), 256, 0, L.stream>>>(L.members, L.first);
+        k_scan_totals<<<dim3(1, y), 256, 0, L.stream>>>(L.members, L.first);
+        k_radix_scatter<<<t, 256, 0, L.stream>>>(L.members, L.first, pass);
     }
-    k_gather_sorted<<<g, 256, 0, s>>>(m, va);
-    k_copy_back<<<g, 256, 0, s>>>(m);
+    k_gather_sorted<<<g, 256, 0, L.stream>>>(L.members, L.first, passes);
+    k_copy_back<<<g, 256, 0, L.stream>>>(L.members, L.first);
     return hipGetLastError();
 }
 

@@ -115,8 +115,8 @@ hipError_t launch_x_kinetic_energy(const Launch& L, int prec, int nx, int ny, in
 // into rho_b; 3: deposit only into scratch (as real grid).
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
                             KickMode kick);
-hipError_t launch_particle_sort(hipStream_t s, const MemberDev& host_copy,
-                                const MemberDev* dev, int prec);
+// Stable radix sort by Morton cell key of every member of a size class.
+hipError_t launch_particle_sort(const Launch& L, int64_t max_np, int nx, int ny, int nz);
 hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos_out,
                                   float* vel_out);
 hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float* pos,
