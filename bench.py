@@ -37,6 +37,19 @@ BYTES_PER_CELL = {
     "z_potential_close_kick": 24,
 }
 BYTES_PER_PARTICLE = {"particles_kick_drift_deposit": 48, "particles_close_kick": 36}
+# tuning-table slot of each grid pass (P1, P2/P4, P3, P5, P6/P8, P7)
+PASS_SLOT = {"z_potential_kick": 0, "z_potential_close_kick": 0, "y_fft_psi_fwd": 1,
+             "y_fft_psi_inv": 1, "x_kinetic": 2, "z_density_r2c": 3, "y_fft_spec_fwd": 4,
+             "y_fft_spec_inv": 4, "x_green": 5}
+
+
+def pass_variant(name, tuning):
+    # the closing kick always runs the default plan
+    if name == "z_potential_close_kick":
+        return 0
+    return int(tuning[PASS_SLOT[name]])
+
+
 # grid passes that run while the particle kernel is in flight on its own stream
 OVERLAPS_PARTICLES = {"y_fft_psi_fwd", "x_kinetic", "y_fft_psi_inv"}
 STEP_BYTES_PER_CELL = 124
@@ -50,8 +63,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, launches_cells: int):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or None."""
+def traffic_from_profiles(kernel: str, variant: int = 0):
+    """HBM bytes per launch of `kernel` with FFT plan `variant` from committed
+    rocprofv3 counter summaries, or None."""
     f = ROOT / "profiles" / "traffic_counters.json"
     if not f.exists():
         return None
@@ -61,7 +75,7 @@ def traffic_from_profiles(kernel: str, launches_cells: int):
         return None
     if d.get("source_hash") != kernel_source_hash():
         return None  # the kernels changed since the counters were taken
-    k = d.get("kernels", {}).get(kernel)
+    k = d.get("kernels", {}).get(kernel, {}).get(str(variant))
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
@@ -251,6 +265,8 @@ def main():
                     help="time without per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default FFT plan of every pass (no autotuning)")
+    ap.add_argument("--plans", choices=["tune", "default", "second"], default="tune",
+                    help="step FFT plans: chosen by timing, or all default / all second plans")
     ap.add_argument("--workload", choices=["halo", "ensemble", "precision", "learned"],
                     default="halo")
     ap.add_argument("--learned-small", action="store_true")
@@ -279,7 +295,13 @@ def main():
     plan = wdm.Plan(cfg, device=dev)
     h = plan.handle
     # choose each step pass's FFT plan by timing (before the state is set)
-    tuning = wdm.autotune(h, cfg, reps=10) if not args.no_tune else wdm.wdm_get_tuning(h)
+    if args.no_tune or args.plans == "default":
+        tuning = wdm.wdm_get_tuning(h)
+    elif args.plans == "second":
+        wdm.wdm_set_tuning(h, [1] * wdm.wdm_tuning_entries(h))
+        tuning = wdm.wdm_get_tuning(h)
+    else:
+        tuning = wdm.autotune(h, cfg, reps=10)
     psi = torch.from_numpy(wl.psi.astype(np.complex64)).to(dev)
     pos = torch.from_numpy(wl.pos).to(dev) if wl.n_particles else None
     vel = torch.from_numpy(wl.vel).to(dev) if wl.n_particles else None
@@ -348,7 +370,8 @@ def main():
         ach = alg / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                    "traffic": traffic_from_profiles(dom["name"], n3),
+                    "traffic": traffic_from_profiles(dom["name"], pass_variant(dom["name"], tuning)),
+                    "fft_plan_variant": pass_variant(dom["name"], tuning),
                     "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6}
     step_bytes = STEP_BYTES_PER_CELL * n3 + STEP_BYTES_PER_PARTICLE * wl.n_particles
     step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
