@@ -187,7 +187,9 @@ wdm_status wdm_profile_read(wdm_plan* plan, wdm_kernel_stat* out, int32_t cap, i
 wdm_status wdm_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps,
                               void* hip_stream, double* ms_per_copy);
 
-/* ---- spectral utilities of the learned-corrector workload -------------- */
+/* ---- spectral utilities of the learned-corrector workload --------------
+ * Not part of the paper's method: they serve the corrector's training-pair
+ * generation (restriction) and its P(k) judge. */
 
 /* Spectral restriction of a fine member's psi to the coarse member's grid
  * (cubic grids, same box, nc < nf): keep the modes with |m_i| < nc/2 on every
@@ -207,6 +209,8 @@ wdm_status wdm_power_spectrum(wdm_plan* plan, int32_t member, int32_t nbins, dou
                               int64_t* counts);
 
 /* ---- learned corrector ----------------------------------------------------
+ * Not part of the paper's method: a network that corrects a 2x-coarser
+ * split-step run toward the fine one every few coarse steps.
  * A three-layer 3x3x3 convolution network on an n^3 periodic grid:
  * 3 -> 16 (ReLU) -> 16 (ReLU) -> 2 channels, circular padding.  Weights and
  * activations are BF16 on the matrix cores with FP32 accumulation; FP32
