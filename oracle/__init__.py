@@ -38,7 +38,8 @@ class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("hbar_over_m", C.c_double), ("four_pi_G", C.c_double),
-                ("n_particles", C.c_int64), ("particle_mass", C.c_double)]
+                ("n_particles", C.c_int64), ("particle_mass", C.c_double),
+                ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double)]
 
 
 _lib = None
@@ -65,7 +66,8 @@ def lib():
         L.orc_kdk.argtypes = [cp, dp, dp, dp, C.c_int64, C.c_double]
         L.orc_energy.argtypes = [cp, dp, dp, dp, dp]
         L.orc_paper_energies.argtypes = [cp, dp, dp, dp]
-        L.orc_dt_auto.argtypes = [cp, dp, C.c_double, C.c_double]
+        L.orc_dt_auto.argtypes = [cp, dp, dp, C.c_double, C.c_double]
+        L.orc_absorb_mask.argtypes = [cp, C.c_double, dp]
         L.orc_dt_auto.restype = C.c_double
         L.orc_power_spectrum.argtypes = [dp, ip, ip, dp, C.POINTER(C.c_int64)]
         L.orc_restrict.argtypes = [dp, ip, dp, ip]
@@ -97,12 +99,12 @@ def get_threads() -> int:
 
 
 def make_config(shape, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0,
-                particle_mass=0.0) -> Config:
+                particle_mass=0.0, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0) -> Config:
     if isinstance(L, (int, float)):
         L = (float(L),) * 3
     nx, ny, nz = shape
     return Config(nx, ny, nz, L[0], L[1], L[2], hbar_over_m, four_pi_G, int(n_particles),
-                  float(particle_mass))
+                  float(particle_mass), float(kappa), float(absorb_alpha), float(absorb_nb))
 
 
 def fft1d(x, sign=-1):
@@ -165,11 +167,11 @@ def kdk(cfg: Config, psi, pos=None, vel=None, nsteps=1, dt=1e-4):
 
 
 ENERGY_FIELDS = ("mass", "e_kin", "e_pot", "e_kin_particles", "e_total", "px", "py", "pz",
-                 "max_abs_phi")
+                 "max_abs_phi", "e_self", "max_rho")
 
 
 def energy(cfg: Config, psi, pos=None, vel=None) -> dict:
-    out = np.zeros(10)
+    out = np.zeros(11)
     lib().orc_energy(C.byref(cfg), _p(_c128(psi).view(np.float64)),
                      _p(_f64(pos)) if pos is not None else None,
                      _p(_f64(vel)) if vel is not None else None, _p(out))
@@ -183,9 +185,17 @@ def paper_energies(cfg: Config, psi, phi) -> dict:
     return dict(zip(("K", "Q", "V", "virial"), out.tolist()))
 
 
-def dt_auto(cfg: Config, phi, zeta=0.9, c_kin=4.0 / (3.0 * np.pi)) -> float:
+def dt_auto(cfg: Config, phi, psi=None, zeta=0.9, c_kin=4.0 / (3.0 * np.pi)) -> float:
     """CFL step of Sec. 3.5.  Parity unpinned beyond its printed formula."""
-    return float(lib().orc_dt_auto(C.byref(cfg), _p(_f64(phi)), zeta, c_kin))
+    ps = _c128(psi).view(np.float64) if psi is not None else None
+    return float(lib().orc_dt_auto(C.byref(cfg), _p(_f64(phi)), _p(ps), zeta, c_kin))
+
+
+def absorb_mask(cfg: Config, dt) -> np.ndarray:
+    """The absorbing boundary factor B of one step (Sec. 3.1, Algorithm 1)."""
+    out = np.zeros((cfg.nx, cfg.ny, cfg.nz))
+    lib().orc_absorb_mask(C.byref(cfg), float(dt), _p(out))
+    return out
 
 
 def power_spectrum(rho, nbins=None):

@@ -32,6 +32,15 @@ typedef struct {
     double four_pi_G;       /* 0 switches gravity off (free Schroedinger) */
     int64_t n_particles;
     double particle_mass;   /* equal-mass particles */
+    /* local self-interaction (Sec. 2.2, 2.4): the kick potential is
+     * Phi + kappa |psi|^2; 0 = non-interacting */
+    double kappa;
+    /* absorbing boundary mask (Sec. 3.1, Algorithm 1): after the second half
+     * kick of every step psi <- psi * B(x), B = exp(-alpha dt sum_a g_a(x_a)),
+     * g_a(x) = 2 - tanh(x / w_a) - tanh((L_a - x) / w_a), w_a = L_a / n_b;
+     * alpha = 0 switches it off */
+    double absorb_alpha;
+    double absorb_nb;
 } orc_config;
 
 /* Number of worker threads (0 = all hardware threads).  Results never depend
@@ -64,10 +73,11 @@ void orc_potential(const orc_config* c, const double* psi, const double* pos, do
 void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
              double dt);
 
-/* Energies of a synchronised state.  out[0..9] =
+/* Energies of a synchronised state.  out[0..10] =
  *   mass = sum |psi|^2 dV, e_kin (spectral, eta^2/2 int |grad psi|^2),
  *   e_pot = 1/2 int rho_tot Phi dV, e_kin_particles = 1/2 sum m v^2,
- *   e_total, momentum of the particles (3), max |Phi|. */
+ *   e_total (including e_self), momentum of the particles (3), max |Phi|,
+ *   e_self = kappa/2 int |psi|^4 dV, max |psi|^2. */
 void orc_energy(const orc_config* c, const double* psi, const double* pos, const double* vel,
                 double* out);
 /* The paper's overall energy terms (Sec. 3.6) exactly as printed:
@@ -77,8 +87,13 @@ void orc_energy(const orc_config* c, const double* psi, const double* pos, const
  *   out[2] V = int rho Phi,   out[3] 2K + 2Q + V.  Wave density only. */
 void orc_paper_energies(const orc_config* c, const double* psi, const double* phi, double* out);
 
-/* dt = zeta * 0.5 * min{c_kin dx_min^2 / eta, 2 pi eta / max|phi|} (Sec. 3.5). */
-double orc_dt_auto(const orc_config* c, const double* phi, double zeta, double c_kin);
+/* dt = zeta * 0.5 * min{c_kin dx_min^2 / eta, 2 pi eta / max|phi|,
+ *                       2 pi eta / (|kappa| max|psi|^2)} (Sec. 3.5); psi may be
+ * NULL when kappa = 0. */
+double orc_dt_auto(const orc_config* c, const double* phi, const double* psi, double zeta,
+                   double c_kin);
+/* The absorbing mask B of one step of size dt, real [nx][ny][nz]. */
+void orc_absorb_mask(const orc_config* c, double dt, double* mask);
 
 /* Shell power spectrum of delta = rho/mean(rho) - 1 (rho real [n]^3, cubic
  * grid): shell b = round(|m|); pk[b] = mean over the shell of |delta_k|^2 / N^2

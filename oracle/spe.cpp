@@ -125,13 +125,40 @@ static void total_potential(const orc_config* c, const cplx* psi, const double* 
     poisson(c, rho.data(), phi);
 }
 
-// (a)/(d): psi <- exp(-i Phi tau / eta) psi.
+// (a)/(d): psi <- exp(-i V tau / eta) psi with V = Phi + kappa |psi|^2 (the
+// local self-interaction of Sec. 2.2 / 2.4 as an extra potential; the kick
+// keeps |psi|, so V taken at its start is exact).
 static void kick(const orc_config* c, cplx* psi, const double* phi, double tau) {
     const int64_t n = cells(c);
     const double s = tau / c->hbar_over_m;
+    const double kappa = c->kappa;
     parallel_for(n, [&](int64_t b, int64_t e) {
-        for (int64_t i = b; i < e; ++i) psi[i] *= std::polar(1.0, -phi[i] * s);
+        for (int64_t i = b; i < e; ++i) {
+            const double v = phi[i] + kappa * std::norm(psi[i]);
+            psi[i] *= std::polar(1.0, -v * s);
+        }
     });
+}
+
+// Absorbing boundary profile of one axis (Sec. 3.1) at node x in [0, L): zero
+// in the interior, 1 at the faces.  The paper's nodes run from -L/2, ours from
+// 0: its x +- L/2 are our x and x - L.
+static double absorb_profile(double x, double L, double nb) {
+    const double w = L / nb;
+    return 2.0 - std::tanh(x / w) + std::tanh((x - L) / w);
+}
+
+// B(x) = exp(-alpha dt sum_a g_a(x_a)) on the nodes.
+static void absorb_mask(const orc_config* c, double dt, double* mask) {
+    Grid g(c);
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k) {
+                const double s = absorb_profile(double(i) * g.dx, g.lx, c->absorb_nb) +
+                                 absorb_profile(double(j) * g.dy, g.ly, c->absorb_nb) +
+                                 absorb_profile(double(k) * g.dz, g.lz, c->absorb_nb);
+                mask[(i * g.ny + j) * g.nz + k] = std::exp(-c->absorb_alpha * dt * s);
+            }
 }
 
 // (b): psi <- F^-1{ exp(-i eta k^2 dt / 2) F{psi} }.
@@ -170,7 +197,11 @@ static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_
                 double dt) {
     const int64_t n = cells(c);
     const bool parts = c->n_particles > 0;
-    std::vector<double> phi(n), acc;
+    std::vector<double> phi(n), acc, mask;
+    if (c->absorb_alpha != 0.0) {
+        mask.resize(size_t(n));
+        absorb_mask(c, dt, mask.data());
+    }
     total_potential(c, psi, pos, phi.data());
     for (int64_t s = 0; s < nsteps; ++s) {
         // (a) first half kick with the current potential
@@ -184,6 +215,9 @@ static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_
         // (d) second half kick with the new potential
         kick(c, psi, phi.data(), 0.5 * dt);
         if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt, acc);
+        // absorbing boundary (Algorithm 1, after step (d))
+        if (!mask.empty())
+            for (int64_t i = 0; i < n; ++i) psi[i] *= mask[size_t(i)];
     }
 }
 
@@ -235,12 +269,16 @@ void orc_energy(const orc_config* c, const double* psi_in, const double* pos, co
                 ek += g.k2(i, j, k) * std::norm(f[(i * g.ny + j) * g.nz + k]);
     const double eta = c->hbar_over_m;
     ek *= 0.5 * eta * eta * g.dv / double(n);
-    double ep = 0.0, maxphi = 0.0;
+    double ep = 0.0, maxphi = 0.0, rho4 = 0.0, maxrho = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         ep += rho[i] * phi[i];
         maxphi = std::max(maxphi, std::fabs(phi[i]));
+        const double d = std::norm(psi[i]);
+        rho4 += d * d;
+        maxrho = std::max(maxrho, d);
     }
     ep *= 0.5 * g.dv;
+    const double es = 0.5 * c->kappa * rho4 * g.dv;
     double kp = 0.0, mom[3] = {0.0, 0.0, 0.0};
     for (int64_t p = 0; p < c->n_particles; ++p)
         for (int a = 0; a < 3; ++a) {
@@ -253,10 +291,11 @@ void orc_energy(const orc_config* c, const double* psi_in, const double* pos, co
     out[1] = ek;
     out[2] = ep;
     out[3] = kp;
-    out[4] = ek + ep + kp;
+    out[4] = ek + ep + kp + es;
     for (int a = 0; a < 3; ++a) out[5 + a] = mom[a] * c->particle_mass;
     out[8] = maxphi;
-    out[9] = 0.0;
+    out[9] = es;
+    out[10] = maxrho;
 }
 
 void orc_paper_energies(const orc_config* c, const double* psi_in, const double* phi, double* out) {
@@ -291,7 +330,8 @@ void orc_paper_energies(const orc_config* c, const double* psi_in, const double*
     out[3] = 2.0 * out[0] + 2.0 * out[1] + out[2];
 }
 
-double orc_dt_auto(const orc_config* c, const double* phi, double zeta, double c_kin) {
+double orc_dt_auto(const orc_config* c, const double* phi, const double* psi_in, double zeta,
+                   double c_kin) {
     Grid g(c);
     double m = 0.0;
     for (int64_t i = 0; i < g.n(); ++i) m = std::max(m, std::fabs(phi[i]));
@@ -299,7 +339,15 @@ double orc_dt_auto(const orc_config* c, const double* phi, double zeta, double c
     const double eta = c->hbar_over_m;
     double t = c_kin * h * h / eta;
     if (m > 0.0) t = std::min(t, kTwoPi * eta / m);
+    if (c->kappa != 0.0 && psi_in) {
+        const cplx* psi = reinterpret_cast<const cplx*>(psi_in);
+        double r = 0.0;
+        for (int64_t i = 0; i < g.n(); ++i) r = std::max(r, std::norm(psi[i]));
+        if (r > 0.0) t = std::min(t, kTwoPi * eta / (std::fabs(c->kappa) * r));
+    }
     return zeta * 0.5 * t;
 }
+
+void orc_absorb_mask(const orc_config* c, double dt, double* mask) { absorb_mask(c, dt, mask); }
 
 }  // extern "C"
