@@ -65,6 +65,17 @@ typedef struct {
     double particle_mass;      /* equal-mass particles */
     int32_t precision;         /* wdm_precision; all members of a plan share it */
     uint32_t flags;            /* reserved, must be 0 */
+    /* Local self-interaction (Sec. 2.2, 2.4): the kick potential becomes
+     * Phi + kappa |psi|^2 (kappa > 0 repulsive, < 0 attractive; 0 = none), the
+     * energy gains kappa/2 int |psi|^4 and the CFL step a third term. */
+    double kappa;
+    /* Absorbing boundary (Sec. 3.1, Algorithm 1): after the second half kick
+     * of every step psi <- psi * B, B = exp(-absorb_alpha dt sum_a g_a(x_a)),
+     * g_a(x) = 2 - tanh(x / w_a) - tanh((L_a - x) / w_a), w_a = L_a /
+     * absorb_nb, nodes x in [0, L).  absorb_alpha = 0 switches it off (the
+     * paper's defaults are absorb_alpha = 10, absorb_nb = 50); absorb_nb > 0. */
+    double absorb_alpha;
+    double absorb_nb;
 } wdm_config;
 
 /* Diagnostics of a synchronised state (Sec. 3.6 energy bookkeeping). */
@@ -73,12 +84,14 @@ typedef struct {
     double e_kin;              /* eta^2/2 int |grad psi|^2, spectral */
     double e_pot;              /* 1/2 int (|psi|^2 + rho_b) Phi dV */
     double e_kin_particles;    /* 1/2 sum m v^2 */
-    double e_total;            /* e_kin + e_pot + e_kin_particles */
+    double e_total;            /* e_kin + e_pot + e_kin_particles + e_self */
     double momentum[3];        /* particle momentum sum m v */
     double max_abs_phi;        /* max |Phi| over the grid */
     double t;                  /* simulated time */
     double dt;                 /* time step last used (or selected) */
     double dt_auto;            /* CFL step of Sec. 3.5 from the last wdm_set_state */
+    double e_self;             /* kappa/2 int |psi|^4 dV (included in e_total) */
+    double max_rho;            /* max |psi|^2 over the grid */
 } wdm_energy_t;
 
 typedef struct {

@@ -71,7 +71,7 @@ struct Carver {
 };
 
 struct MemberLayout {
-    size_t psi, phi, rho_b, spec, nyq, kin, dt, results;
+    size_t psi, phi, rho_b, spec, nyq, kin, absorb, dt, results;
     size_t p[7], a[7], key_a, key_b, idx_a, idx_b, hist;
 };
 
@@ -122,6 +122,14 @@ bool valid_config(const wdm_config& c, std::string& why) {
         why = "flags must be 0";
         return false;
     }
+    if (!std::isfinite(c.kappa) || !std::isfinite(c.absorb_alpha) || c.absorb_alpha < 0) {
+        why = "kappa must be finite and absorb_alpha finite and >= 0";
+        return false;
+    }
+    if (c.absorb_alpha > 0 && !(c.absorb_nb > 0 && std::isfinite(c.absorb_nb))) {
+        why = "absorb_nb must be positive when the absorbing boundary is on";
+        return false;
+    }
     return true;
 }
 
@@ -157,6 +165,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         m.spec = c.take(int64_t(g.nx) * g.ny * (g.nz / 2) * cs);
         m.nyq = c.take(int64_t(g.nx) * g.ny * cs);
         m.kin = c.take((int64_t(g.nx) + int64_t(g.ny) * g.nz) * 16);
+        m.absorb = c.take((int64_t(g.nx) + g.ny + g.nz) * sizeof(double));
         m.dt = c.take(4 * sizeof(double));
         m.results = c.take(kRedFields * sizeof(double));
         const int64_t np = std::max<int64_t>(g.n_particles, 0);
@@ -189,6 +198,8 @@ struct SizeClass {
     int nx, ny, nz;
     int64_t max_np;
     int var[kTuneSlots] = {0, 0, 0, 0, 0, 0};   // plan variant per tunable pass
+    bool absorb = false;    // some member has an absorbing boundary
+    bool extended = false;  // some member has a self-interaction or absorbing boundary
 };
 
 struct Rec {
@@ -348,6 +359,7 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.spec_nyq = ws + ml.nyq;
         m.scratch = ws + L.scratch;
         m.kin = ws + ml.kin;
+        m.absorb = reinterpret_cast<double*>(ws + ml.absorb);
         m.tw_x = ws + L.tw.at(c.nx);
         m.tw_y = ws + L.tw.at(c.ny);
         m.tw_z = ws + L.tw.at(c.nz);
@@ -359,6 +371,9 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.lz = c.lz;
         m.eta = c.hbar_over_m;
         m.four_pi_G = c.four_pi_G;
+        m.kappa = c.kappa;
+        m.absorb_alpha = c.absorb_alpha;
+        m.absorb_nb = c.absorb_nb;
         m.inv_dx = double(c.nx) / c.lx;
         m.inv_dy = double(c.ny) / c.ly;
         m.inv_dz = double(c.nz) / c.lz;
@@ -388,6 +403,8 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
             p->classes.push_back({d, 0, c.nx, c.ny, c.nz, 0});
         p->classes.back().count++;
         p->classes.back().max_np = std::max<int64_t>(p->classes.back().max_np, c.n_particles);
+        if (c.absorb_alpha != 0.0) p->classes.back().absorb = true;
+        if (c.absorb_alpha != 0.0 || c.kappa != 0.0) p->classes.back().extended = true;
     }
     p->table = reinterpret_cast<MemberDev*>(ws + L.table);
 
@@ -427,6 +444,10 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
             launch_zero(p->stream, m.results, kRedFields * sizeof(double)) != hipSuccess)
             return cleanup(WDM_EDEVICE, "plan initialisation failed");
     }
+    // absorbing factors of dt = 0 (all ones) until the first step sets dt
+    for (const auto& c : p->classes)
+        if (launch_absorb_tables(Launch{p->stream, p->table, c.first, c.count}) != hipSuccess)
+            return cleanup(WDM_EDEVICE, "plan initialisation failed");
     if (hipStreamSynchronize(p->stream) != hipSuccess)
         return cleanup(WDM_EDEVICE, "plan initialisation failed");
     *out = p;
@@ -471,6 +492,7 @@ wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const flo
     HIPCHK(potential_from_state(p, L, c));
     HIPCHK(launch_reduce_grid(L, p->prec, n, 0));
     HIPCHK(launch_reduce_finish(L, 7, kRedBlocks, true));
+    HIPCHK(launch_reduce_finish(L, 8, kRedBlocks, true));
     HIPCHK(launch_dt_auto(L, 0.9, 4.0 / (3.0 * kPi)));
     HIPCHK(launch_set_dt(L, t0, 3));
     p->has_state[member] = true;
@@ -504,7 +526,7 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
         const bool fork = parts && aux != nullptr;
         if (!chk(timed(p, kKZPot, [&] {
                 return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km,
-                                               c.var[kTzPot]);
+                                               c.var[kTzPot], c.extended);
             })))
             return e;
         if (fork) {
@@ -570,7 +592,8 @@ hipError_t enqueue_close(wdm_plan* p, hipStream_t s, int64_t n) {
     for (const auto& c : p->classes) {
         const Launch L{s, p->table, c.first, c.count};
         e = timed(p, kKClose, [&] {
-            return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZKickOnly, kHalfKick);
+            return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZKickOnly, kHalfKick, 0,
+                                           c.extended);
         });
         if (e == hipSuccess && c.max_np > 0)
             e = timed(p, kKCloseParticles, [&] {
@@ -644,6 +667,7 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
     for (const auto& c : p->classes) {
         const Launch L{s, p->table, c.first, c.count};
         HIPCHK(dt != 0.0 ? launch_set_dt(L, dt, 0) : launch_set_dt(L, 0.0, 1));
+        if (c.absorb) HIPCHK(launch_absorb_tables(L));
     }
     for (int64_t i = 0; i < n; ++i) {
         if (resort_due(p)) HIPCHK(enqueue_sort(p, s));
@@ -847,10 +871,12 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     const MemberDev& m = p->host[p->dev_index[member]];
     const int64_t n = cells_of(c);
     const int prec = p->prec;
-    // mass and max |Phi|
+    // mass, max |Phi|, max |psi|^2 and sum |psi|^4
     HIPCHK(launch_reduce_grid(L, prec, n, 0));
     HIPCHK(launch_reduce_finish(L, 0, kRedBlocks, false));
     HIPCHK(launch_reduce_finish(L, 7, kRedBlocks, true));
+    HIPCHK(launch_reduce_finish(L, 8, kRedBlocks, true));
+    HIPCHK(launch_reduce_finish(L, 9, kRedBlocks, false));
     // potential energy with the deposited baryons
     HIPCHK(launch_zero(p->stream, m.scratch, size_t(n) * (prec ? 8 : 4)));
     if (c.n_particles > 0) HIPCHK(launch_particles(L, prec, c.n_particles, 3, kHalfKick));
@@ -881,8 +907,10 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
         out->e_kin_particles = 0.5 * c.particle_mass * res[3];
         for (int a = 0; a < 3; ++a) out->momentum[a] = c.particle_mass * res[4 + a];
     }
-    out->e_total = out->e_kin + out->e_pot + out->e_kin_particles;
+    out->e_self = 0.5 * c.kappa * res[9] * dv;
+    out->e_total = out->e_kin + out->e_pot + out->e_kin_particles + out->e_self;
     out->max_abs_phi = res[7];
+    out->max_rho = res[8];
     out->t = dts[3];
     out->dt = dts[0] != 0.0 ? dts[0] : dts[1];
     out->dt_auto = dts[1];

@@ -3,10 +3,47 @@
 
 namespace wdm {
 
+// Kick with the local self-interaction and the absorbing boundary (Sec. 2.2,
+// 3.1): the potential is V = Phi + kappa |psi|^2, taken from psi before the
+// kick (the kick keeps |psi|).  With MASK the absorbing factor
+// B = b_x b_y b_z closes the step; in a merged kick (FULL) it falls between
+// the closing half kick of one step and the opening one of the next, whose
+// self-interaction then sees |B psi|^2:
+//   phase = -dt/eta (Phi + kappa |psi|^2 (1 + B^2) / 2),  psi <- B e^{i phase} psi.
+// `c` is -tau / eta of the kick as launched.
+template <class FP, typename T, bool MASK, bool FULL, class LN>
+__device__ __forceinline__ void kick_general(cplx<T>* v, const cplx<T>* w, const T* phi,
+                                             const MemberDev& m, int64_t q, bool ok, double c,
+                                             const LN& ln) {
+    const double kappa = m.kappa;
+    const bool mask = MASK && m.absorb_alpha != 0.0;
+    const double* bz = m.absorb + m.nx + m.ny;
+    double bxy = 1.0;
+    if (mask && ok) {
+        const int64_t i = q / m.ny, j = q - i * m.ny;
+        bxy = gldr(m.absorb, i) * gldr(m.absorb, m.nx + j);
+    }
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        const double re = double(w[s].re), im = double(w[s].im);
+        const double r2 = re * re + im * im;
+        const double b = mask ? bxy * gldr(bz, slot_elem<FP, FP::first()>(ln.t, s)) : 1.0;
+        const double pot = double(phi[s]) + kappa * r2 * (FULL ? 0.5 * (1.0 + b * b) : 1.0);
+        cplx<T> r = rotate(w[s], pot * c);
+        if (mask) {
+            r.re *= T(b);
+            r.im *= T(b);
+        }
+        v[s] = r;
+    }
+}
+
 // ===========================================================================
 // P1: potential from the half spectrum, kick, optional forward z-FFT.
 // ===========================================================================
-template <int NZ, typename T, int OP, int KICK, int V>
+// GEN selects the kick with self-interaction and absorbing boundary (kept out
+// of the plain kernel, whose register budget it would otherwise raise).
+template <int NZ, typename T, int OP, int KICK, int V, bool GEN>
 __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void k_z_potential_kick(
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NZ, V>::type;
@@ -62,8 +99,15 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     const double dt = gldr(m.dt, 0);
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
     const double c = -tau / m.eta;
+    if constexpr (GEN) {
+        // the closing kick and the merged kick end a step: the absorbing
+        // boundary follows them; the opening kick has none before it
+        kick_general<FP, T, OP == kZKickOnly || KICK == kFullKick, KICK == kFullKick>(
+            v, w, phi, m, q, ok, c, ln);
+    } else {
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s) v[s] = rotate(w[s], double(phi[s]) * c);
+        for (int s = 0; s < FP::E; ++s) v[s] = rotate(w[s], double(phi[s]) * c);
+    }
     if constexpr (OP == kZKickOnly) {
         store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
         return;
@@ -133,43 +177,48 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
 
 template <int NZ>
 struct ZPotKick {
-    template <typename T, int V>
+    template <typename T, int V, bool GEN>
     static hipError_t go(const Launch& L, int nx, int ny, ZOp op, KickMode k) {
         dim3 grid(unsigned(tiles<NZ, T, V>(int64_t(nx) * ny)), unsigned(L.count));
         const dim3 b = block<NZ, T, V>();
         if constexpr (V == 0) {
             if (op == kZPhiOnly) {
-                k_z_potential_kick<NZ, T, kZPhiOnly, kHalfKick, 0>
+                k_z_potential_kick<NZ, T, kZPhiOnly, kHalfKick, 0, false>
                     <<<grid, b, 0, L.stream>>>(L.members, L.first);
                 return hipGetLastError();
             }
             if (op == kZKickOnly) {
                 if (k == kHalfKick)
-                    k_z_potential_kick<NZ, T, kZKickOnly, kHalfKick, 0>
+                    k_z_potential_kick<NZ, T, kZKickOnly, kHalfKick, 0, GEN>
                         <<<grid, b, 0, L.stream>>>(L.members, L.first);
                 else
-                    k_z_potential_kick<NZ, T, kZKickOnly, kFullKick, 0>
+                    k_z_potential_kick<NZ, T, kZKickOnly, kFullKick, 0, GEN>
                         <<<grid, b, 0, L.stream>>>(L.members, L.first);
                 return hipGetLastError();
             }
         }
         if (k == kHalfKick)
-            k_z_potential_kick<NZ, T, kZKickFft, kHalfKick, V>
+            k_z_potential_kick<NZ, T, kZKickFft, kHalfKick, V, GEN>
                 <<<grid, b, 0, L.stream>>>(L.members, L.first);
         else
-            k_z_potential_kick<NZ, T, kZKickFft, kFullKick, V>
+            k_z_potential_kick<NZ, T, kZKickFft, kFullKick, V, GEN>
                 <<<grid, b, 0, L.stream>>>(L.members, L.first);
         return hipGetLastError();
     }
     template <typename T>
-    static hipError_t pick(const Launch& L, int nx, int ny, ZOp op, KickMode k, int var) {
+    static hipError_t pick(const Launch& L, int nx, int ny, ZOp op, KickMode k, int var,
+                           bool gen) {
+        // the extended kick runs on the default plan only
+        if (gen && op != kZPhiOnly) return go<T, 0, true>(L, nx, ny, op, k);
         // only the merged kick + z-FFT variant has a second plan
         if constexpr (has_variant(NZ))
-            if (var == 1 && op == kZKickFft) return go<T, 1>(L, nx, ny, op, k);
-        return go<T, 0>(L, nx, ny, op, k);
+            if (var == 1 && op == kZKickFft) return go<T, 1, false>(L, nx, ny, op, k);
+        return go<T, 0, false>(L, nx, ny, op, k);
     }
-    static hipError_t run(const Launch& L, int prec, int nx, int ny, ZOp op, KickMode k, int var) {
-        return prec ? pick<double>(L, nx, ny, op, k, var) : pick<float>(L, nx, ny, op, k, var);
+    static hipError_t run(const Launch& L, int prec, int nx, int ny, ZOp op, KickMode k, int var,
+                          bool gen) {
+        return prec ? pick<double>(L, nx, ny, op, k, var, gen)
+                    : pick<float>(L, nx, ny, op, k, var, gen);
     }
 };
 
@@ -197,8 +246,8 @@ struct ZDens {
 };
 
 hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, int nz, ZOp op,
-                                   KickMode kick, int variant) {
-    return dispatch_n<ZPotKick>(nz, L, prec, nx, ny, op, kick, variant);
+                                   KickMode kick, int variant, bool extended) {
+    return dispatch_n<ZPotKick>(nz, L, prec, nx, ny, op, kick, variant, extended);
 }
 hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op,
                             int variant) {

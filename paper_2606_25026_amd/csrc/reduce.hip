@@ -35,7 +35,8 @@ __device__ __forceinline__ double block_max(double v, double* red) {
     return r;
 }
 
-// what 0: sum |psi|^2 -> field 0, max |Phi| -> field 7
+// what 0: sum |psi|^2 -> field 0, max |Phi| -> field 7, max |psi|^2 -> field 8,
+//         sum |psi|^4 -> field 9
 // what 1: sum (|psi|^2 + scratch) Phi -> field 2 (scratch holds CIC rho_b)
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __restrict__ mems,
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __
     const cplx<T>* psi = static_cast<const cplx<T>*>(m.psi);
     const T* phi = static_cast<const T*>(m.phi);
     const T* rb = static_cast<const T*>(m.scratch);
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int64_t i = b + threadIdx.x; i < e; i += kRedThreads) {
         const cplx<T> v = gld(psi, i);
         const double re = double(v.re), im = double(v.im);
@@ -56,6 +57,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __
         if (what == 0) {
             s0 += rho;
             s1 = fmax(s1, fabs(double(gldr(phi, i))));
+            s2 = fmax(s2, rho);
+            s3 += rho * rho;
         } else {
             s0 += (rho + double(gldr(rb, i))) * double(gldr(phi, i));
         }
@@ -63,9 +66,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __
     const double t0 = block_sum<T>(s0, red);
     if (what == 0) {
         const double t1 = block_max(s1, red);
+        const double t2 = block_max(s2, red);
+        const double t3 = block_sum<T>(s3, red);
         if (threadIdx.x == 0) {
             m.partials[int64_t(blockIdx.x) * kRedFields + 0] = t0;
             m.partials[int64_t(blockIdx.x) * kRedFields + 7] = t1;
+            m.partials[int64_t(blockIdx.x) * kRedFields + 8] = t2;
+            m.partials[int64_t(blockIdx.x) * kRedFields + 9] = t3;
         }
     } else if (threadIdx.x == 0) {
         m.partials[int64_t(blockIdx.x) * kRedFields + 2] = t0;
@@ -129,9 +136,10 @@ hipError_t launch_reduce_finish(const Launch& L, int field, int nblocks, bool is
     return hipGetLastError();
 }
 
-// dt = zeta * 0.5 * min{c_kin dx_min^2 / eta, 2 pi eta / max|Phi|}; needs
-// results[7] = max |Phi|.  Stored as dt_auto and, unless a per-member dt was
-// set, as the dt in use.
+// dt = zeta * 0.5 * min{c_kin dx_min^2 / eta, 2 pi eta / max|Phi|,
+// 2 pi eta / (|kappa| max|psi|^2)} (Sec. 3.5; the last term only with a
+// self-interaction); needs results[7] = max |Phi| and results[8] = max |psi|^2.
+// Stored as dt_auto; wdm_step(dt = 0) uses it unless a per-member dt was set.
 __global__ void k_dt_auto(const MemberDev* __restrict__ mems, int first, double zeta,
                           double c_kin) {
     const MemberDev& m = mems[first + blockIdx.x];
@@ -139,6 +147,8 @@ __global__ void k_dt_auto(const MemberDev* __restrict__ mems, int first, double 
     double t = c_kin * dx * dx / m.eta;
     const double mp = m.results[7];
     if (mp > 0.0) t = fmin(t, kTwoPi * m.eta / mp);
+    const double mr = m.results[8];
+    if (m.kappa != 0.0 && mr > 0.0) t = fmin(t, kTwoPi * m.eta / (fabs(m.kappa) * mr));
     m.dt[1] = zeta * 0.5 * t;
 }
 
@@ -163,6 +173,34 @@ __global__ void k_set_dt(const MemberDev* __restrict__ mems, int first, double d
 
 hipError_t launch_set_dt(const Launch& L, double dt, int mode) {
     k_set_dt<<<unsigned(L.count), 1, 0, L.stream>>>(L.members, L.first, dt, mode);
+    return hipGetLastError();
+}
+
+// b_a[i] = exp(-alpha dt g_a(i L_a / n_a)) with the face profile of Sec. 3.1,
+// g(x) = 2 - tanh(x / w) + tanh((x - L) / w), w = L / n_b, on nodes x in
+// [0, L) (the paper centres the box: its x + L/2 is our x).  One work-group
+// per member; all ones where alpha dt is 0.
+__global__ __launch_bounds__(256) void k_absorb_tables(const MemberDev* __restrict__ mems,
+                                                       int first) {
+    const MemberDev& m = mems[first + blockIdx.x];
+    const double adt = m.absorb_alpha * m.dt[0];
+    const int nxy = m.nx + m.ny, n = nxy + m.nz;
+    for (int i = int(threadIdx.x); i < n; i += 256) {
+        double b = 1.0;
+        if (adt != 0.0) {
+            const int k = i < m.nx ? i : (i < nxy ? i - m.nx : i - nxy);
+            const int len = i < m.nx ? m.nx : (i < nxy ? m.ny : m.nz);
+            const double L = i < m.nx ? m.lx : (i < nxy ? m.ly : m.lz);
+            const double w = L / m.absorb_nb;
+            const double x = double(k) * (L / double(len));
+            b = exp(-adt * (2.0 - tanh(x / w) + tanh((x - L) / w)));
+        }
+        gstr(m.absorb, i, b);
+    }
+}
+
+hipError_t launch_absorb_tables(const Launch& L) {
+    k_absorb_tables<<<unsigned(L.count), 256, 0, L.stream>>>(L.members, L.first);
     return hipGetLastError();
 }
 

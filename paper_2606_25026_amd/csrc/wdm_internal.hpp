@@ -44,6 +44,9 @@ struct MemberDev {
     // [0, nx) e_x(k_x); [nx, nx + ny nz) e_yz(k_y, k_z) / N at q = iy nz + iz.
     // 16 bytes per entry: (hi, lo) complex64 pair, or one complex128.
     void* kin;
+    // absorbing-boundary factors of the step's dt, b_a = exp(-alpha dt g_a) at
+    // the nodes: [0, nx) x, [nx, nx + ny) y, [nx + ny, nx + ny + nz) z (FP64)
+    double* absorb;
     const void* tw_x;  // W_nx^m, m in [0, nx) (complex, plan precision)
     const void* tw_y;
     const void* tw_z;
@@ -51,6 +54,8 @@ struct MemberDev {
     double lx, ly, lz;
     double eta;        // hbar / m
     double four_pi_G;
+    double kappa;                  // local self-interaction (0 = none)
+    double absorb_alpha, absorb_nb;  // absorbing boundary (alpha = 0: none)
     double inv_dx, inv_dy, inv_dz;   // n / L per axis
     double inv_lx, inv_ly, inv_lz;   // 1 / L per axis
     // time-step slots (device doubles): [0] dt in use, [1] dt_auto, [2] dt set by user,
@@ -69,7 +74,7 @@ struct MemberDev {
     double* results;   // [kRedFields]
 };
 
-constexpr int kRedFields = 8;
+constexpr int kRedFields = 10;
 constexpr int kRedBlocks = 1024;
 
 // Launch context shared by all launchers.
@@ -89,8 +94,11 @@ bool axis_supported(int n);
 // True where the axis length has a second FFT plan (the autotuner's choice).
 bool axis_has_variant(int n);
 // P1: half spectrum -> Phi (C2R along z), then kick and optionally z-FFT.
+// `extended` selects the kick with the local self-interaction and the
+// absorbing boundary (needed when a member of the class has either; it runs
+// the default FFT plan whatever `variant` says).
 hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, int nz, ZOp op,
-                                   KickMode kick, int variant = 0);
+                                   KickMode kick, int variant = 0, bool extended = false);
 // P2 / P4 on psi, P6 / P8 on the half spectrum (+ Nyquist plane).
 hipError_t launch_y_fft_psi(const Launch& L, int prec, int nx, int ny, int nz, bool inverse,
                             int variant = 0);
@@ -124,12 +132,15 @@ hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float
 
 // ---- reductions and small kernels (reduce.hip) ----
 // fields of `results`: 0 mass, 1 e_kin, 2 sum rho Phi, 3 sum v^2, 4..6 sum v,
-// 7 max |Phi|
+// 7 max |Phi|, 8 max |psi|^2, 9 sum |psi|^4
 hipError_t launch_reduce_grid(const Launch& L, int prec, int64_t ncells, int what);
 hipError_t launch_reduce_finish(const Launch& L, int field, int nblocks, bool is_max);
 hipError_t launch_reduce_particles(const Launch& L, int64_t max_np);
 hipError_t launch_dt_auto(const Launch& L, double zeta, double c_kin);
 hipError_t launch_set_dt(const Launch& L, double dt, int mode);
+// Absorbing-boundary factor tables of every member of the class from dt[0]
+// (all ones where absorb_alpha is 0).
+hipError_t launch_absorb_tables(const Launch& L);
 hipError_t launch_advance_time(const Launch& L, int64_t nsteps);
 hipError_t launch_zero(hipStream_t s, void* p, size_t bytes);
 hipError_t launch_copy_complex(hipStream_t s, void* dst, const void* src, int64_t n,

@@ -29,14 +29,16 @@ class wdm_config(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("hbar_over_m", C.c_double), ("four_pi_G", C.c_double),
                 ("n_particles", C.c_int64), ("particle_mass", C.c_double),
-                ("precision", C.c_int32), ("flags", C.c_uint32)]
+                ("precision", C.c_int32), ("flags", C.c_uint32),
+                ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double)]
 
 
 class wdm_energy_t(C.Structure):
     _fields_ = [("mass", C.c_double), ("e_kin", C.c_double), ("e_pot", C.c_double),
                 ("e_kin_particles", C.c_double), ("e_total", C.c_double),
                 ("momentum", C.c_double * 3), ("max_abs_phi", C.c_double), ("t", C.c_double),
-                ("dt", C.c_double), ("dt_auto", C.c_double)]
+                ("dt", C.c_double), ("dt_auto", C.c_double), ("e_self", C.c_double),
+                ("max_rho", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "momentum"}
@@ -138,11 +140,12 @@ def _cfg_array(configs):
 
 
 def make_config(n, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0, particle_mass=0.0,
-                precision=WDM_C64) -> wdm_config:
+                precision=WDM_C64, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0) -> wdm_config:
     nx, ny, nz = (n, n, n) if isinstance(n, int) else n
     lx, ly, lz = (L, L, L) if isinstance(L, (int, float)) else L
     return wdm_config(nx, ny, nz, lx, ly, lz, hbar_over_m, four_pi_G, int(n_particles),
-                      float(particle_mass), precision, 0)
+                      float(particle_mass), precision, 0, float(kappa), float(absorb_alpha),
+                      float(absorb_nb))
 
 
 # ---- entry points --------------------------------------------------------

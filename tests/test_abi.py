@@ -54,6 +54,12 @@ def test_workspace_bytes_and_validation(wdm):
     mixed = [wdm.make_config(64), wdm.make_config(64, precision=wdm.WDM_C128)]
     assert wdm.wdm_workspace_bytes(mixed) == 0
     assert "precision" in wdm.wdm_last_error()
+    for extra, why in ((dict(absorb_alpha=-1.0), "absorb_alpha"),
+                       (dict(absorb_alpha=10.0, absorb_nb=0.0), "absorb_nb"),
+                       (dict(kappa=float("nan")), "kappa")):
+        assert wdm.wdm_workspace_bytes(wdm.make_config(64, **extra)) == 0, extra
+        assert why in wdm.wdm_last_error()
+    assert wdm.wdm_workspace_bytes(wdm.make_config(64, kappa=-2.0, absorb_alpha=10.0)) > 0
     ens = [wdm.make_config(n) for n in (64,) * 3 + (96,) * 3 + (128,) * 3]
     assert wdm.wdm_workspace_bytes(ens) > sum(
         wdm.wdm_workspace_bytes(wdm.make_config(n)) for n in (64, 96, 128))

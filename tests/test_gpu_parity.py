@@ -40,13 +40,13 @@ class Run:
     """A single-member plan fed from numpy arrays."""
 
     def __init__(self, wdm, psi, L=1.0, pos=None, vel=None, mp=0.0, four_pi_G=1.0, eta=1.0,
-                 prec=0):
+                 prec=0, **extra):
         self.wdm = wdm
         self.prec = prec
         self.shape = psi.shape
         npart = 0 if pos is None else pos.shape[0]
         self.cfg = wdm.make_config(psi.shape, L=L, hbar_over_m=eta, four_pi_G=four_pi_G,
-                                   n_particles=npart, particle_mass=mp, precision=prec)
+                                   n_particles=npart, particle_mass=mp, precision=prec, **extra)
         self.plan = wdm.Plan(self.cfg)
         self.psi = torch.from_numpy(psi).to(cdt(prec)).cuda()
         self.pos = torch.from_numpy(np.ascontiguousarray(pos, np.float32)).cuda() if npart else None
@@ -55,6 +55,12 @@ class Run:
 
     def step(self, n, dt):
         self.wdm.wdm_step(self.plan.handle, n, dt)
+
+    def psi_tensor(self):
+        """The current field as a device tensor of the plan's precision."""
+        out = torch.empty(self.shape, dtype=cdt(self.prec), device="cuda")
+        self.wdm.wdm_get_psi(self.plan.handle, 0, out)
+        return out
 
     def get_psi(self):
         out = torch.empty(self.shape, dtype=cdt(self.prec), device="cuda")
