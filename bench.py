@@ -271,6 +271,12 @@ def main():
                     default="halo")
     ap.add_argument("--learned-small", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=2000)
+    ap.add_argument("--kappa", type=float, default=0.0,
+                    help="halo workload: local self-interaction strength (0 = none)")
+    ap.add_argument("--absorb-alpha", type=float, default=0.0,
+                    help="halo workload: absorbing boundary strength (0 = periodic box)")
+    ap.add_argument("--absorb-nb", type=float, default=50.0,
+                    help="halo workload: absorbing layer width parameter N_b")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -291,7 +297,9 @@ def main():
     dev = torch.device("cuda:0")
     wl = inputs.coupled_halo(n=args.n, n_particles=args.particles, seed=0)
     n3 = args.n ** 3
-    cfg = wdm.make_config(args.n, n_particles=wl.n_particles, particle_mass=wl.particle_mass)
+    extended = dict(kappa=args.kappa, absorb_alpha=args.absorb_alpha, absorb_nb=args.absorb_nb)
+    cfg = wdm.make_config(args.n, n_particles=wl.n_particles, particle_mass=wl.particle_mass,
+                          **extended)
     plan = wdm.Plan(cfg, device=dev)
     h = plan.handle
     # choose each step pass's FFT plan by timing (before the state is set)
@@ -411,6 +419,10 @@ def main():
         "mass_drift": e1["mass"] / e0["mass"] - 1.0,
         "cpu_baseline": cpu,
     }
+    if args.kappa != 0.0 or args.absorb_alpha != 0.0:
+        out["config"]["workload"] += (f", self-interaction kappa={args.kappa:g}, absorbing "
+                                      f"boundary alpha={args.absorb_alpha:g} N_b={args.absorb_nb:g}")
+        out["config"].update(extended)
     print(json.dumps(out))
     plan.close()
 

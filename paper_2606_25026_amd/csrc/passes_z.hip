@@ -3,6 +3,33 @@
 
 namespace wdm {
 
+// Absorbing factors of one pencil for the extended kick: b_x b_y of the pencil
+// (returned) and the z factors staged in LDS, all loads issued with the
+// pass's other loads.  Ones when the member has no absorbing boundary.
+template <int NZ, int WG>
+__device__ __forceinline__ double load_absorb(double* bz, const MemberDev& m, int64_t q, bool ok) {
+    constexpr int R = (NZ + WG - 1) / WG;
+    if (m.absorb_alpha == 0.0) return 1.0;
+    const double* tz = m.absorb + m.nx + m.ny;
+    double r[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        r[k] = (NZ % WG == 0 || i < NZ) ? gldr(tz, i) : 1.0;
+    }
+    double bxy = 1.0;
+    if (ok) {
+        const int64_t i = q / m.ny, j = q - i * m.ny;
+        bxy = gldr(m.absorb, i) * gldr(m.absorb, m.nx + j);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = int(threadIdx.x) + k * WG;
+        if (NZ % WG == 0 || i < NZ) bz[i] = r[k];
+    }
+    return bxy;
+}
+
 // Kick with the local self-interaction and the absorbing boundary (Sec. 2.2,
 // 3.1): the potential is V = Phi + kappa |psi|^2, taken from psi before the
 // kick (the kick keeps |psi|).  With MASK the absorbing factor
@@ -10,24 +37,19 @@ namespace wdm {
 // the closing half kick of one step and the opening one of the next, whose
 // self-interaction then sees |B psi|^2:
 //   phase = -dt/eta (Phi + kappa |psi|^2 (1 + B^2) / 2),  psi <- B e^{i phase} psi.
-// `c` is -tau / eta of the kick as launched.
+// `c` is -tau / eta of the kick as launched; `bxy` and `bz` come from
+// load_absorb.
 template <class FP, typename T, bool MASK, bool FULL, class LN>
 __device__ __forceinline__ void kick_general(cplx<T>* v, const cplx<T>* w, const T* phi,
-                                             const MemberDev& m, int64_t q, bool ok, double c,
-                                             const LN& ln) {
+                                             const MemberDev& m, double bxy, const double* bz,
+                                             double c, const LN& ln) {
     const double kappa = m.kappa;
     const bool mask = MASK && m.absorb_alpha != 0.0;
-    const double* bz = m.absorb + m.nx + m.ny;
-    double bxy = 1.0;
-    if (mask && ok) {
-        const int64_t i = q / m.ny, j = q - i * m.ny;
-        bxy = gldr(m.absorb, i) * gldr(m.absorb, m.nx + j);
-    }
 #pragma unroll
     for (int s = 0; s < FP::E; ++s) {
         const double re = double(w[s].re), im = double(w[s].im);
         const double r2 = re * re + im * im;
-        const double b = mask ? bxy * gldr(bz, slot_elem<FP, FP::first()>(ln.t, s)) : 1.0;
+        const double b = mask ? bxy * bz[slot_elem<FP, FP::first()>(ln.t, s)] : 1.0;
         const double pot = double(phi[s]) + kappa * r2 * (FULL ? 0.5 * (1.0 + b * b) : 1.0);
         cplx<T> r = rotate(w[s], pot * c);
         if (mask) {
@@ -51,14 +73,20 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     using LN = Lanes<FP, T, false>;
     constexpr int PP = LN::PP;
     constexpr int H = NZ / 2;
+    // the closing kick and the merged kick end a step: the absorbing boundary
+    // follows them; the opening kick has none before it
+    constexpr bool MASK = GEN && (OP == kZKickOnly || KICK == kFullKick);
     __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(NZ)];
+    __shared__ double bz[MASK ? NZ : 1];
     const MemberDev& m = mems[first + blockIdx.y];
     const LN ln;
     const int64_t npen = int64_t(m.nx) * m.ny;
     const int64_t q = int64_t(blockIdx.x) * PP + ln.p;
     const bool ok = q < npen;
     load_twiddles<NZ, wg_size<FP, T>()>(tw, m.tw_z);
+    double bxy = 1.0;
+    if constexpr (MASK) bxy = load_absorb<NZ, wg_size<FP, T>()>(bz, m, q, ok);
     // psi is loaded together with the spectrum: one memory wait per pass
     cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
     cplx<T> w[OP == kZPhiOnly ? 1 : FP::E];
@@ -100,10 +128,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
     const double c = -tau / m.eta;
     if constexpr (GEN) {
-        // the closing kick and the merged kick end a step: the absorbing
-        // boundary follows them; the opening kick has none before it
-        kick_general<FP, T, OP == kZKickOnly || KICK == kFullKick, KICK == kFullKick>(
-            v, w, phi, m, q, ok, c, ln);
+        kick_general<FP, T, MASK, KICK == kFullKick>(v, w, phi, m, bxy, bz, c, ln);
     } else {
 #pragma unroll
         for (int s = 0; s < FP::E; ++s) v[s] = rotate(w[s], double(phi[s]) * c);
