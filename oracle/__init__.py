@@ -39,7 +39,8 @@ class Config(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("hbar_over_m", C.c_double), ("four_pi_G", C.c_double),
                 ("n_particles", C.c_int64), ("particle_mass", C.c_double),
-                ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double)]
+                ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double),
+                ("baryon_mode", C.c_int32), ("nbody_substeps", C.c_int32)]
 
 
 _lib = None
@@ -98,13 +99,18 @@ def get_threads() -> int:
     return lib().orc_get_threads()
 
 
+BARYON_DYNAMIC, BARYON_STATIC = 0, 1
+
+
 def make_config(shape, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0,
-                particle_mass=0.0, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0) -> Config:
+                particle_mass=0.0, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0,
+                baryon_mode=BARYON_DYNAMIC, nbody_substeps=1) -> Config:
     if isinstance(L, (int, float)):
         L = (float(L),) * 3
     nx, ny, nz = shape
     return Config(nx, ny, nz, L[0], L[1], L[2], hbar_over_m, four_pi_G, int(n_particles),
-                  float(particle_mass), float(kappa), float(absorb_alpha), float(absorb_nb))
+                  float(particle_mass), float(kappa), float(absorb_alpha), float(absorb_nb),
+                  int(baryon_mode), int(nbody_substeps))
 
 
 def fft1d(x, sign=-1):

@@ -41,6 +41,13 @@ typedef struct {
      * alpha = 0 switches it off */
     double absorb_alpha;
     double absorb_nb;
+    /* baryon treatment (Sec. 3.2.2): 0 dynamic particles, 1 static particles
+     * (deposited from their fixed positions, never kicked or moved) */
+    int32_t baryon_mode;
+    /* particle leapfrog sub-steps per wave step (0 or 1: one).  The S
+     * sub-steps of h = dt / S run in the potential of the step's start; the
+     * last half kick takes the step's new potential */
+    int32_t nbody_substeps;
 } orc_config;
 
 /* Number of worker threads (0 = all hardware threads).  Results never depend
@@ -69,7 +76,9 @@ void orc_potential(const orc_config* c, const double* psi, const double* pos, do
 
 /* Advance psi (complex [nx][ny][nz]) and particles (pos, vel [Np][3], may be
  * NULL when n_particles == 0) by nsteps unmerged KDK steps of size dt (dt may
- * be negative).  The starting potential is rebuilt from the state. */
+ * be negative).  The starting potential is rebuilt from the state.  Particles
+ * take nbody_substeps leapfrog sub-steps per step; static particles
+ * (baryon_mode 1) are left untouched. */
 void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
              double dt);
 

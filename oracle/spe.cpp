@@ -193,10 +193,27 @@ static void particle_drift(const orc_config* c, double* pos, const double* vel, 
         }
 }
 
+// Particle part of one wave step with S leapfrog sub-steps of h = dt / S
+// (Sec. 3.2.2: the N-body component advances in several sub-steps per wave
+// step).  The grid potential is that of the step's start for every sub-step;
+// the closing half kick, after the step's Poisson solve, is done by the caller.
+static void particle_substeps(const orc_config* c, const double* phi, double* pos, double* vel,
+                              double dt, std::vector<double>& acc) {
+    const int S = c->nbody_substeps > 1 ? c->nbody_substeps : 1;
+    const double h = dt / S;
+    for (int k = 0; k < S; ++k) {
+        particle_kick(c, phi, pos, vel, 0.5 * h, acc);
+        particle_drift(c, pos, vel, h);
+        if (k + 1 < S) particle_kick(c, phi, pos, vel, 0.5 * h, acc);
+    }
+}
+
 static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_t nsteps,
                 double dt) {
     const int64_t n = cells(c);
-    const bool parts = c->n_particles > 0;
+    // static baryons (Sec. 3.2.2) only source the potential
+    const bool parts = c->n_particles > 0 && c->baryon_mode == 0;
+    const int S = c->nbody_substeps > 1 ? c->nbody_substeps : 1;
     std::vector<double> phi(n), acc, mask;
     if (c->absorb_alpha != 0.0) {
         mask.resize(size_t(n));
@@ -206,15 +223,16 @@ static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_
     for (int64_t s = 0; s < nsteps; ++s) {
         // (a) first half kick with the current potential
         kick(c, psi, phi.data(), 0.5 * dt);
-        if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt, acc);
-        // (b) full drift: kinetic phase in Fourier space; particles move
+        // particles: first half kick and drift (one sub-step), or all but the
+        // last half kick of S sub-steps in the potential of the step's start
+        if (parts) particle_substeps(c, phi.data(), pos, vel, dt, acc);
+        // (b) full drift: kinetic phase in Fourier space
         drift(c, psi, dt);
-        if (parts) particle_drift(c, pos, vel, dt);
         // (c) potential of the wave density plus the deposited baryons
         total_potential(c, psi, pos, phi.data());
         // (d) second half kick with the new potential
         kick(c, psi, phi.data(), 0.5 * dt);
-        if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt, acc);
+        if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt / S, acc);
         // absorbing boundary (Algorithm 1, after step (d))
         if (!mask.empty())
             for (int64_t i = 0; i < n; ++i) psi[i] *= mask[size_t(i)];
