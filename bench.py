@@ -277,6 +277,10 @@ def main():
                     help="halo workload: absorbing boundary strength (0 = periodic box)")
     ap.add_argument("--absorb-nb", type=float, default=50.0,
                     help="halo workload: absorbing layer width parameter N_b")
+    ap.add_argument("--baryons", choices=["dynamic", "static"], default="dynamic",
+                    help="halo workload: particles move (dynamic) or only source the potential")
+    ap.add_argument("--substeps", type=int, default=1,
+                    help="halo workload: particle leapfrog sub-steps per wave step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -297,7 +301,9 @@ def main():
     dev = torch.device("cuda:0")
     wl = inputs.coupled_halo(n=args.n, n_particles=args.particles, seed=0)
     n3 = args.n ** 3
-    extended = dict(kappa=args.kappa, absorb_alpha=args.absorb_alpha, absorb_nb=args.absorb_nb)
+    extended = dict(kappa=args.kappa, absorb_alpha=args.absorb_alpha, absorb_nb=args.absorb_nb,
+                    baryon_mode=1 if args.baryons == "static" else 0,
+                    nbody_substeps=args.substeps)
     cfg = wdm.make_config(args.n, n_particles=wl.n_particles, particle_mass=wl.particle_mass,
                           **extended)
     plan = wdm.Plan(cfg, device=dev)
@@ -389,6 +395,8 @@ def main():
         print("# timing the FP64 CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl)
 
+    base_workload = (f"coupled halo {args.n}^3 complex64 + {wl.n_particles} CIC "
+                     "Plummer particles (GRF k0=16*2pi + soliton rc=0.05)")
     out = {
         "metric": "grid cell-updates/s (KDK) at 256^3 c64 + % HBM roofline",
         "value": value,
@@ -402,8 +410,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": f"coupled halo {args.n}^3 complex64 + {wl.n_particles} CIC "
-                               "Plummer particles (GRF k0=16*2pi + soliton rc=0.05)",
+        "config": {"workload": base_workload,
                    "grid": args.n, "particles": wl.n_particles, "dt": wl.dt,
                    "phase_args": "fp64", "sort_interval": args.sort_interval,
                    "fft_plan_variants": dict(zip(["P1", "P2/P4", "P3", "P5", "P6/P8", "P7"], tuning)),
@@ -422,6 +429,10 @@ def main():
     if args.kappa != 0.0 or args.absorb_alpha != 0.0:
         out["config"]["workload"] += (f", self-interaction kappa={args.kappa:g}, absorbing "
                                       f"boundary alpha={args.absorb_alpha:g} N_b={args.absorb_nb:g}")
+    if args.baryons != "dynamic" or args.substeps > 1:
+        out["config"]["workload"] += (f", {args.baryons} baryons, {args.substeps} particle "
+                                      "sub-steps per step")
+    if out["config"]["workload"] != base_workload:
         out["config"].update(extended)
     print(json.dumps(out))
     plan.close()

@@ -56,6 +56,8 @@ typedef enum {
 typedef enum { WDM_C64 = 0, WDM_C128 = 1 } wdm_precision;
 
 /* One periodic box (an ensemble has several). */
+enum { WDM_BARYON_DYNAMIC = 0, WDM_BARYON_STATIC = 1 };
+
 typedef struct {
     int32_t nx, ny, nz;        /* each in {16,32,64,96,128,192,256,384,512} */
     double lx, ly, lz;         /* box lengths; dx = lx / nx */
@@ -76,6 +78,16 @@ typedef struct {
      * paper's defaults are absorb_alpha = 10, absorb_nb = 50); absorb_nb > 0. */
     double absorb_alpha;
     double absorb_nb;
+    /* Baryon treatment (Sec. 3.2.2): WDM_BARYON_DYNAMIC particles are kicked
+     * and drift with the wave; WDM_BARYON_STATIC particles are deposited once
+     * from the positions given to wdm_set_state and never move (their
+     * velocities are kept as given). */
+    int32_t baryon_mode;
+    /* Particle leapfrog sub-steps per wave step (Sec. 3.2.2), 0 or 1 = one,
+     * at most 1024.  The S sub-steps of h = dt / S run in the potential of the
+     * step's start; the closing half kick takes the step's new potential, and
+     * the baryons are deposited once, after the last sub-step. */
+    int32_t nbody_substeps;
 } wdm_config;
 
 /* Diagnostics of a synchronised state (Sec. 3.6 energy bookkeeping). */

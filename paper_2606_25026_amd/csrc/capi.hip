@@ -130,6 +130,14 @@ bool valid_config(const wdm_config& c, std::string& why) {
         why = "absorb_nb must be positive when the absorbing boundary is on";
         return false;
     }
+    if (c.baryon_mode != WDM_BARYON_DYNAMIC && c.baryon_mode != WDM_BARYON_STATIC) {
+        why = "baryon_mode must be WDM_BARYON_DYNAMIC or WDM_BARYON_STATIC";
+        return false;
+    }
+    if (c.nbody_substeps < 0 || c.nbody_substeps > 1024) {
+        why = "nbody_substeps must be in [0, 1024]";
+        return false;
+    }
     return true;
 }
 
@@ -200,6 +208,7 @@ struct SizeClass {
     int var[kTuneSlots] = {0, 0, 0, 0, 0, 0};   // plan variant per tunable pass
     bool absorb = false;    // some member has an absorbing boundary
     bool extended = false;  // some member has a self-interaction or absorbing boundary
+    int64_t moving_np = 0;  // most particles of a member whose particles move
 };
 
 struct Rec {
@@ -374,6 +383,8 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.kappa = c.kappa;
         m.absorb_alpha = c.absorb_alpha;
         m.absorb_nb = c.absorb_nb;
+        m.substeps = std::max(1, c.nbody_substeps);
+        m.static_baryons = c.baryon_mode == WDM_BARYON_STATIC ? 1 : 0;
         m.inv_dx = double(c.nx) / c.lx;
         m.inv_dy = double(c.ny) / c.ly;
         m.inv_dz = double(c.nz) / c.lz;
@@ -405,6 +416,9 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         p->classes.back().max_np = std::max<int64_t>(p->classes.back().max_np, c.n_particles);
         if (c.absorb_alpha != 0.0) p->classes.back().absorb = true;
         if (c.absorb_alpha != 0.0 || c.kappa != 0.0) p->classes.back().extended = true;
+        if (c.baryon_mode == WDM_BARYON_DYNAMIC)
+            p->classes.back().moving_np =
+                std::max<int64_t>(p->classes.back().moving_np, c.n_particles);
     }
     p->table = reinterpret_cast<MemberDev*>(ws + L.table);
 
@@ -522,7 +536,7 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
     };
     for (const auto& c : p->classes) {
         const Launch L{s, p->table, c.first, c.count};
-        const bool parts = c.max_np > 0;
+        const bool parts = c.moving_np > 0;
         const bool fork = parts && aux != nullptr;
         if (!chk(timed(p, kKZPot, [&] {
                 return launch_z_potential_kick(L, prec, c.nx, c.ny, c.nz, kZKickFft, km,
@@ -534,11 +548,12 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             if (!chk(hipEventRecord(p->ev_fork, s))) return e;
             if (!chk(hipStreamWaitEvent(aux, p->ev_fork, 0))) return e;
             if (!chk(timed_on(p, aux, kKParticles,
-                              [&] { return launch_particles(LA, prec, c.max_np, 0, km); })))
+                              [&] { return launch_particles(LA, prec, c.moving_np, 0, km); })))
                 return e;
             if (!chk(hipEventRecord(p->ev_join, aux))) return e;
         } else if (parts) {
-            if (!chk(timed(p, kKParticles, [&] { return launch_particles(L, prec, c.max_np, 0, km); })))
+            if (!chk(timed(p, kKParticles,
+                           [&] { return launch_particles(L, prec, c.moving_np, 0, km); })))
                 return e;
         }
         if (!chk(timed(p, kKYPsiF, [&] {
@@ -577,7 +592,7 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
 hipError_t enqueue_sort(wdm_plan* p, hipStream_t s) {
     hipError_t e = hipSuccess;
     for (const auto& c : p->classes) {
-        if (c.max_np <= 1) continue;
+        if (c.moving_np <= 1) continue;   // static particles keep their order
         e = timed(p, kKSort, [&] {
             return launch_particle_sort(Launch{s, p->table, c.first, c.count}, c.max_np, c.nx,
                                         c.ny, c.nz);
@@ -595,9 +610,9 @@ hipError_t enqueue_close(wdm_plan* p, hipStream_t s, int64_t n) {
             return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZKickOnly, kHalfKick, 0,
                                            c.extended);
         });
-        if (e == hipSuccess && c.max_np > 0)
+        if (e == hipSuccess && c.moving_np > 0)
             e = timed(p, kKCloseParticles, [&] {
-                return launch_particles(L, p->prec, c.max_np, 1, kHalfKick);
+                return launch_particles(L, p->prec, c.moving_np, 1, kHalfKick);
             });
         if (e == hipSuccess) e = launch_advance_time(L, n);
         if (e != hipSuccess) return e;

@@ -299,11 +299,18 @@ __device__ __forceinline__ void deposit_group(T* __restrict__ grid, const Member
 // chunk).
 constexpr int kGroupsPerCU = 4;
 
+// With S = m.substeps leapfrog sub-steps of h = dt / S (Sec. 3.2.2), mode 0
+// runs the opening (or merged) kick, then S drifts with a full kick of h in
+// the same potential between them; the closing half kick of h/2 is mode 1
+// after the step's Poisson solve.  Static baryons skip modes 0 and 1.
 template <typename T>
 __global__ __launch_bounds__(kParticleWG) void k_particles(const MemberDev* __restrict__ mems,
                                                            int first, int mode, int kick) {
     const MemberDev& m = mems[first + blockIdx.y];
+    if (mode <= 1 && m.static_baryons) return;   // uniform over the work-group
     const double dt = gldr(m.dt, 0);
+    const int S = m.substeps;
+    const double h = dt / S;
     for (int64_t grp = blockIdx.x; grp * kParticleWG < m.np; grp += gridDim.x) {
         const int64_t i = grp * kParticleWG + threadIdx.x;
         const bool act = i < m.np;
@@ -311,17 +318,22 @@ __global__ __launch_bounds__(kParticleWG) void k_particles(const MemberDev* __re
         float x = gldr(m.px, ii), y = gldr(m.py, ii), z = gldr(m.pz, ii);
         if (mode <= 1) {
             float vx = gldr(m.vx, ii), vy = gldr(m.vy, ii), vz = gldr(m.vz, ii);
-            const CellW<T> c = cic<T>(x, y, z, m);
-            float g[3];
-            cic_accel(static_cast<const T*>(m.phi), m, c, g);
-            const float tau = float(kick == kFullKick ? dt : 0.5 * dt);
-            vx += g[0] * tau;
-            vy += g[1] * tau;
-            vz += g[2] * tau;
+            float tau = float(kick == kFullKick ? h : 0.5 * h);
+            for (int sub = 0;; ++sub) {
+                const CellW<T> c = cic<T>(x, y, z, m);
+                float g[3];
+                cic_accel(static_cast<const T*>(m.phi), m, c, g);
+                vx += g[0] * tau;
+                vy += g[1] * tau;
+                vz += g[2] * tau;
+                if (mode == 1) break;
+                x = wrap_pos(double(x) + double(vx) * h, m.lx, m.inv_lx);
+                y = wrap_pos(double(y) + double(vy) * h, m.ly, m.inv_ly);
+                z = wrap_pos(double(z) + double(vz) * h, m.lz, m.inv_lz);
+                if (sub + 1 == S) break;
+                tau = float(h);   // the two half kicks between sub-steps
+            }
             if (mode == 0) {
-                x = wrap_pos(double(x) + double(vx) * dt, m.lx, m.inv_lx);
-                y = wrap_pos(double(y) + double(vy) * dt, m.ly, m.inv_ly);
-                z = wrap_pos(double(z) + double(vz) * dt, m.lz, m.inv_lz);
                 if (act) {
                     gstr(m.px, i, x);
                     gstr(m.py, i, y);

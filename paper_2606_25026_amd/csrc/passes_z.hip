@@ -180,10 +180,12 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
         load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
         __syncthreads();
     }
+    // the accumulator is cleared for the next deposit; a static deposit stays
+    const bool clear = ok && !m.static_baryons;
 #pragma unroll
     for (int s = 0; s < FP::E; ++s) {
         v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
-        if (ok) gstr(rb, slot_const<FP, FP::first()>(s), T(0));
+        if (clear) gstr(rb, slot_const<FP, FP::first()>(s), T(0));
     }
     __syncthreads();
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);

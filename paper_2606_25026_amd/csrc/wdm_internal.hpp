@@ -36,7 +36,8 @@ struct MemberDev {
     // grids (C order [nx][ny][nz], z contiguous)
     void* psi;        // complex, n cells
     void* phi;        // real potential, n cells
-    void* rho_b;      // real baryon density accumulator, n cells (zero between steps)
+    void* rho_b;      // real baryon density accumulator, n cells (zero between steps,
+                      // except with static baryons, whose deposit it keeps)
     void* spec;       // complex half spectrum [nx][ny][nz/2] (kz = 0 .. nz/2-1)
     void* spec_nyq;   // complex Nyquist plane [nx][ny] (kz = nz/2)
     void* scratch;    // complex, n cells (diagnostics only)
@@ -50,7 +51,10 @@ struct MemberDev {
     const void* tw_x;  // W_nx^m, m in [0, nx) (complex, plan precision)
     const void* tw_y;
     const void* tw_z;
-    int32_t nx, ny, nz, pad0;
+    int32_t nx, ny, nz;
+    int32_t substeps;        // particle leapfrog sub-steps per step (>= 1)
+    int32_t static_baryons;  // 1: particles never move and rho_b is kept between steps
+    int32_t pad0;
     double lx, ly, lz;
     double eta;        // hbar / m
     double four_pi_G;

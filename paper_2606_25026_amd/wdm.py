@@ -14,6 +14,7 @@ from pathlib import Path
 LIB_PATH = Path(__file__).resolve().parent / "libwdm.so"
 
 WDM_C64, WDM_C128 = 0, 1
+WDM_BARYON_DYNAMIC, WDM_BARYON_STATIC = 0, 1
 STATUS = {0: "WDM_OK", 1: "WDM_EINVAL", 2: "WDM_ENOMEM", 3: "WDM_EDEVICE", 4: "WDM_ESTATE",
           5: "WDM_EUNSTABLE", 6: "WDM_EUNSUPPORTED"}
 
@@ -30,7 +31,8 @@ class wdm_config(C.Structure):
                 ("hbar_over_m", C.c_double), ("four_pi_G", C.c_double),
                 ("n_particles", C.c_int64), ("particle_mass", C.c_double),
                 ("precision", C.c_int32), ("flags", C.c_uint32),
-                ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double)]
+                ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double),
+                ("baryon_mode", C.c_int32), ("nbody_substeps", C.c_int32)]
 
 
 class wdm_energy_t(C.Structure):
@@ -140,12 +142,13 @@ def _cfg_array(configs):
 
 
 def make_config(n, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0, particle_mass=0.0,
-                precision=WDM_C64, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0) -> wdm_config:
+                precision=WDM_C64, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0,
+                baryon_mode=0, nbody_substeps=1) -> wdm_config:
     nx, ny, nz = (n, n, n) if isinstance(n, int) else n
     lx, ly, lz = (L, L, L) if isinstance(L, (int, float)) else L
     return wdm_config(nx, ny, nz, lx, ly, lz, hbar_over_m, four_pi_G, int(n_particles),
                       float(particle_mass), precision, 0, float(kappa), float(absorb_alpha),
-                      float(absorb_nb))
+                      float(absorb_nb), int(baryon_mode), int(nbody_substeps))
 
 
 # ---- entry points --------------------------------------------------------

@@ -60,6 +60,14 @@ def test_workspace_bytes_and_validation(wdm):
         assert wdm.wdm_workspace_bytes(wdm.make_config(64, **extra)) == 0, extra
         assert why in wdm.wdm_last_error()
     assert wdm.wdm_workspace_bytes(wdm.make_config(64, kappa=-2.0, absorb_alpha=10.0)) > 0
+    for extra, why in ((dict(baryon_mode=2), "baryon_mode"),
+                       (dict(nbody_substeps=-1), "nbody_substeps"),
+                       (dict(nbody_substeps=1025), "nbody_substeps")):
+        assert wdm.wdm_workspace_bytes(wdm.make_config(64, **extra)) == 0, extra
+        assert why in wdm.wdm_last_error()
+    assert wdm.wdm_workspace_bytes(
+        wdm.make_config(64, n_particles=10, baryon_mode=wdm.WDM_BARYON_STATIC,
+                        nbody_substeps=1024)) > 0
     ens = [wdm.make_config(n) for n in (64,) * 3 + (96,) * 3 + (128,) * 3]
     assert wdm.wdm_workspace_bytes(ens) > sum(
         wdm.wdm_workspace_bytes(wdm.make_config(n)) for n in (64, 96, 128))
