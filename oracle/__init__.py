@@ -69,6 +69,8 @@ def lib():
         L.orc_paper_energies.argtypes = [cp, dp, dp, dp]
         L.orc_dt_auto.argtypes = [cp, dp, dp, C.c_double, C.c_double]
         L.orc_absorb_mask.argtypes = [cp, C.c_double, dp]
+        L.orc_mass_fraction_radii.argtypes = [cp, dp, C.POINTER(C.c_int32), dp, ip, dp]
+        L.orc_mass_fraction_radii.restype = ip
         L.orc_dt_auto.restype = C.c_double
         L.orc_power_spectrum.argtypes = [dp, ip, ip, dp, C.POINTER(C.c_int64)]
         L.orc_restrict.argtypes = [dp, ip, dp, ip]
@@ -185,10 +187,27 @@ def energy(cfg: Config, psi, pos=None, vel=None) -> dict:
 
 
 def paper_energies(cfg: Config, psi, phi) -> dict:
-    out = np.zeros(4)
+    """The paper's K, Q, V, 2K + 2Q + V and the wave momentum (Sec. 3.6)."""
+    out = np.zeros(7)
     lib().orc_paper_energies(C.byref(cfg), _p(_c128(psi).view(np.float64)), _p(_f64(phi)),
                              _p(out))
-    return dict(zip(("K", "Q", "V", "virial"), out.tolist()))
+    return dict(zip(("K", "Q", "V", "virial", "Px", "Py", "Pz"), out.tolist()))
+
+
+MASS_FRACTIONS = tuple(0.1 * f for f in range(1, 10))
+
+
+def mass_fraction_radii(cfg: Config, psi, centre=None, fractions=MASS_FRACTIONS) -> np.ndarray:
+    """Radii enclosing the given fractions of the wave mass (App. A.1.2)."""
+    if centre is None:
+        centre = (cfg.nx // 2, cfg.ny // 2, cfg.nz // 2)
+    cen = (C.c_int32 * 3)(*centre)
+    fr = np.ascontiguousarray(fractions, dtype=np.float64)
+    out = np.zeros(len(fr))
+    if lib().orc_mass_fraction_radii(C.byref(cfg), _p(_c128(psi).view(np.float64)), cen,
+                                     _p(fr), len(fr), _p(out)) != 0:
+        raise ValueError("mass-fraction radii need cubic cells")
+    return out
 
 
 def dt_auto(cfg: Config, phi, psi=None, zeta=0.9, c_kin=4.0 / (3.0 * np.pi)) -> float:

@@ -90,11 +90,19 @@ void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t
 void orc_energy(const orc_config* c, const double* psi, const double* pos, const double* vel,
                 double* out);
 /* The paper's overall energy terms (Sec. 3.6) exactly as printed:
- *   out[0] K = 1/2 int |rho v|^2 / rho (rho v = Im(psi* grad psi), central diff.,
- *              cells with rho <= 1e-30 skipped),
+ *   out[0] K = 1/2 int |rho v|^2 / rho (rho v = eta Im(psi* grad psi), central
+ *              differences, cells with rho <= 1e-30 skipped),
  *   out[1] Q = int |grad sqrt(rho)|^2 (central differences),
- *   out[2] V = int rho Phi,   out[3] 2K + 2Q + V.  Wave density only. */
+ *   out[2] V = int rho Phi,   out[3] 2K + 2Q + V,
+ *   out[4..6] wave momentum int rho v.  Wave density only. */
 void orc_paper_energies(const orc_config* c, const double* psi, const double* phi, double* out);
+
+/* Mass-fraction radii (App. A.1.2) of the wave mass around the node
+ * centre[3]: radii[f] = smallest minimum-image node distance whose enclosed
+ * mass reaches fractions[f] of the total.  Needs cubic cells (returns -1
+ * otherwise, 0 on success). */
+int orc_mass_fraction_radii(const orc_config* c, const double* psi, const int32_t* centre,
+                            const double* fractions, int nf, double* radii);
 
 /* dt = zeta * 0.5 * min{c_kin dx_min^2 / eta, 2 pi eta / max|phi|,
  *                       2 pi eta / (|kappa| max|psi|^2)} (Sec. 3.5); psi may be

@@ -320,7 +320,8 @@ void orc_paper_energies(const orc_config* c, const double* psi_in, const double*
     Grid g(c);
     const cplx* psi = reinterpret_cast<const cplx*>(psi_in);
     const double h[3] = {g.dx, g.dy, g.dz};
-    double K = 0.0, Q = 0.0, V = 0.0;
+    const double eta = c->hbar_over_m;
+    double K = 0.0, Q = 0.0, V = 0.0, P[3] = {0.0, 0.0, 0.0};
     for (int64_t i = 0; i < g.nx; ++i)
         for (int64_t j = 0; j < g.ny; ++j)
             for (int64_t k = 0; k < g.nz; ++k) {
@@ -331,9 +332,11 @@ void orc_paper_energies(const orc_config* c, const double* psi_in, const double*
                                     {g.at(i, j, k + 1), g.at(i, j, k - 1)}};
                 double j2 = 0.0, q2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
+                    // momentum density rho v = eta Im(psi* grad psi)
                     const cplx dpsi = (psi[nb[a][0]] - psi[nb[a][1]]) / (2.0 * h[a]);
-                    const double ja = (std::conj(psi[o]) * dpsi).imag();
+                    const double ja = eta * (std::conj(psi[o]) * dpsi).imag();
                     j2 += ja * ja;
+                    P[a] += ja;
                     const double ds = (std::sqrt(std::norm(psi[nb[a][0]])) -
                                        std::sqrt(std::norm(psi[nb[a][1]]))) / (2.0 * h[a]);
                     q2 += ds * ds;
@@ -346,6 +349,47 @@ void orc_paper_energies(const orc_config* c, const double* psi_in, const double*
     out[1] = Q * g.dv;
     out[2] = V * g.dv;
     out[3] = 2.0 * out[0] + 2.0 * out[1] + out[2];
+    for (int a = 0; a < 3; ++a) out[4 + a] = P[a] * g.dv;
+}
+
+// Radii enclosing the fractions f of the wave mass around the node `centre`
+// (App. A.1.2, spherical symmetry assumed).  Distances are minimum-image node
+// distances r = dx sqrt(s), s = di^2 + dj^2 + dk^2 an integer (cubic cells);
+// r_f is the smallest node distance whose enclosed mass (all nodes at that
+// distance or closer) reaches f times the total.
+int orc_mass_fraction_radii(const orc_config* c, const double* psi_in, const int32_t* centre,
+                            const double* fractions, int nf, double* radii) {
+    Grid g(c);
+    if (!(g.dx == g.dy && g.dy == g.dz)) return -1;
+    const cplx* psi = reinterpret_cast<const cplx*>(psi_in);
+    const int64_t smax = (g.nx / 2) * (g.nx / 2) + (g.ny / 2) * (g.ny / 2) + (g.nz / 2) * (g.nz / 2);
+    std::vector<double> shell(size_t(smax + 1), 0.0);
+    auto offset = [](int64_t i, int64_t ci, int64_t n) {
+        int64_t d = ((i - ci) % n + n) % n;   // in [0, n)
+        return d >= n / 2 ? n - d : d;        // minimum image |offset|
+    };
+    double total = 0.0;
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k) {
+                const int64_t di = offset(i, centre[0], g.nx), dj = offset(j, centre[1], g.ny),
+                              dk = offset(k, centre[2], g.nz);
+                const double m = std::norm(psi[g.at(i, j, k)]);
+                shell[size_t(di * di + dj * dj + dk * dk)] += m;
+                total += m;
+            }
+    for (int f = 0; f < nf; ++f) {
+        double cum = 0.0;
+        radii[f] = -1.0;
+        for (int64_t s = 0; s <= smax; ++s) {
+            cum += shell[size_t(s)];
+            if (shell[size_t(s)] > 0.0 && cum >= fractions[f] * total) {
+                radii[f] = g.dx * std::sqrt(double(s));
+                break;
+            }
+        }
+    }
+    return 0;
 }
 
 double orc_dt_auto(const orc_config* c, const double* phi, const double* psi_in, double zeta,
