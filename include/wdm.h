@@ -106,6 +106,22 @@ typedef struct {
     double max_rho;            /* max |psi|^2 over the grid */
 } wdm_energy_t;
 
+/* The paper's diagnostics of a synchronised state (Sec. 3.6, App. A.1),
+ * wave density only, second-order central differences on the periodic nodes. */
+typedef struct {
+    double K;                  /* 1/2 int |rho v|^2 / rho dV, rho v = eta Im(psi* grad psi)
+                                  (cells with |psi|^2 <= 1e-30 skipped) */
+    double Q;                  /* int |grad sqrt(rho)|^2 dV (as printed, without eta^2/2) */
+    double V;                  /* int rho Phi dV (as printed, without 1/2) */
+    double virial;             /* 2K + 2Q + V */
+    double momentum[3];        /* wave momentum int rho v dV */
+    double mass;               /* int |psi|^2 dV */
+    double radii[9];           /* radii enclosing 10%, 20%, ..., 90% of the wave mass around
+                                  the centre node: the smallest minimum-image node distance
+                                  whose enclosed mass (nodes at that distance included)
+                                  reaches the fraction; NaN unless the cells are cubic */
+} wdm_diagnostics_t;
+
 typedef struct {
     char name[40];             /* pass name, e.g. "x_kinetic" */
     int64_t launches;          /* launches recorded */
@@ -158,6 +174,15 @@ wdm_status wdm_potential(wdm_plan* plan, int32_t member, void* phi_out);
 
 /* FP64 diagnostics (host out).  Synchronises the plan's stream. */
 wdm_status wdm_energy(wdm_plan* plan, int32_t member, wdm_energy_t* out);
+
+/* The paper's halo diagnostics (host out): K, Q, V, 2K + 2Q + V, the wave
+ * momentum and mass, and the mass-fraction radii around the node centre[3]
+ * (NULL = (nx/2, ny/2, nz/2), the box centre; each index in [0, n)).  V uses
+ * the potential of the synchronised state.  Uses the plan's shared scratch;
+ * synchronises the plan's stream.  FP64 sums; K, Q, V and the momentum are
+ * deterministic, the radial histogram uses FP64 atomics (last bits only). */
+wdm_status wdm_diagnostics(wdm_plan* plan, int32_t member, const int32_t* centre,
+                           wdm_diagnostics_t* out);
 
 /* Particle positions and velocities in their original order (dev out,
  * float [n_particles][3]; either pointer may be NULL). */

@@ -935,6 +935,54 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     return WDM_OK;
 }
 
+wdm_status wdm_diagnostics(wdm_plan* p, int32_t member, const int32_t* centre,
+                           wdm_diagnostics_t* out) {
+    if (wdm_status s = check_member(p, member)) return s;
+    if (!out) return fail(WDM_EINVAL, "out is null");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const wdm_config& c = p->cfg[member];
+    int cen[3] = {c.nx / 2, c.ny / 2, c.nz / 2};
+    if (centre) {
+        const int len[3] = {c.nx, c.ny, c.nz};
+        for (int a = 0; a < 3; ++a) {
+            if (centre[a] < 0 || centre[a] >= len[a])
+                return fail(WDM_EINVAL, "centre node out of range");
+            cen[a] = centre[a];
+        }
+    }
+    const Launch L = one(p, member);
+    const MemberDev& m = p->host[p->dev_index[member]];
+    const int64_t n = cells_of(c);
+    HIPCHK(launch_diag_energies(L, p->prec, kRedBlocks));
+    for (int f = 0; f < 7; ++f) HIPCHK(launch_reduce_finish(L, f, kRedBlocks, false));
+    const double dx = c.lx / c.nx;
+    const bool cubic = dx == c.ly / c.ny && dx == c.lz / c.nz;
+    double radii[9];
+    // the histogram and the radii live in the plan's scratch (>= n doubles)
+    const int64_t nbins = int64_t(c.nx / 2) * (c.nx / 2) + int64_t(c.ny / 2) * (c.ny / 2) +
+                          int64_t(c.nz / 2) * (c.nz / 2) + 1;
+    double* hist = static_cast<double*>(m.scratch);
+    if (cubic) {
+        if (nbins + 9 > n) return fail(WDM_EINVAL, "grid too small for the radial histogram");
+        HIPCHK(launch_mass_radii(L, p->prec, n, cen, dx, hist, nbins, hist + nbins));
+    }
+    double res[kRedFields];
+    HIPCHK(hipMemcpyAsync(res, m.results, sizeof(res), hipMemcpyDeviceToHost, p->stream));
+    if (cubic)
+        HIPCHK(hipMemcpyAsync(radii, hist + nbins, sizeof(radii), hipMemcpyDeviceToHost,
+                              p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    const double dv = dx * (c.ly / c.ny) * (c.lz / c.nz);
+    out->K = res[0] * dv;
+    out->Q = res[1] * dv;
+    out->V = res[2] * dv;
+    out->virial = 2.0 * out->K + 2.0 * out->Q + out->V;
+    for (int a = 0; a < 3; ++a) out->momentum[a] = res[3 + a] * dv;
+    out->mass = res[6] * dv;
+    for (int f = 0; f < 9; ++f) out->radii[f] = cubic ? radii[f] : std::nan("");
+    return WDM_OK;
+}
+
 wdm_status wdm_particles(wdm_plan* p, int32_t member, float* pos_out, float* vel_out) {
     if (wdm_status s = check_member(p, member)) return s;
     if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");

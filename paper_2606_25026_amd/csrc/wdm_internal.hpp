@@ -134,6 +134,15 @@ hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos_
 hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float* pos,
                                   const float* vel);
 
+// ---- diagnostics (diag.hip) ----
+// Partials of K, Q, V, Px, Py, Pz, sum |psi|^2 (per 1/dV) into fields 0..6
+// over `nblocks` work-groups; finish each with launch_reduce_finish.
+hipError_t launch_diag_energies(const Launch& L, int prec, int nblocks);
+// Mass-fraction radii (10%, ..., 90%) around the node `centre` into out[0..8]
+// via a radial histogram hist[0..nbins) of squared node distances.
+hipError_t launch_mass_radii(const Launch& L, int prec, int64_t ncells, const int centre[3],
+                             double dx, double* hist, int64_t nbins, double* out);
+
 // ---- reductions and small kernels (reduce.hip) ----
 // fields of `results`: 0 mass, 1 e_kin, 2 sum rho Phi, 3 sum v^2, 4..6 sum v,
 // 7 max |Phi|, 8 max |psi|^2, 9 sum |psi|^4

@@ -48,6 +48,17 @@ class wdm_energy_t(C.Structure):
         return d
 
 
+class wdm_diagnostics_t(C.Structure):
+    _fields_ = [("K", C.c_double), ("Q", C.c_double), ("V", C.c_double), ("virial", C.c_double),
+                ("momentum", C.c_double * 3), ("mass", C.c_double), ("radii", C.c_double * 9)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("momentum", "radii")}
+        d["momentum"] = list(self.momentum)
+        d["radii"] = list(self.radii)
+        return d
+
+
 class wdm_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -66,6 +77,7 @@ _SIGS = {
     "wdm_density": (C.c_int, [_vp, _i32, _vp, _i32]),
     "wdm_potential": (C.c_int, [_vp, _i32, _vp]),
     "wdm_energy": (C.c_int, [_vp, _i32, C.POINTER(wdm_energy_t)]),
+    "wdm_diagnostics": (C.c_int, [_vp, _i32, C.POINTER(C.c_int32), C.POINTER(wdm_diagnostics_t)]),
     "wdm_particles": (C.c_int, [_vp, _i32, _vp, _vp]),
     "wdm_fft3d": (C.c_int, [_vp, _i32, _i32]),
     "wdm_set_sort_interval": (C.c_int, [_vp, _i32]),
@@ -201,6 +213,13 @@ def wdm_energy(plan, member=0) -> dict:
     e = wdm_energy_t()
     _check(load().wdm_energy(plan, member, C.byref(e)))
     return e.as_dict()
+
+
+def wdm_diagnostics(plan, member=0, centre=None) -> dict:
+    d = wdm_diagnostics_t()
+    cen = (C.c_int32 * 3)(*centre) if centre is not None else None
+    _check(load().wdm_diagnostics(plan, member, cen, C.byref(d)))
+    return d.as_dict()
 
 
 def wdm_particles(plan, member, pos_out=None, vel_out=None):
