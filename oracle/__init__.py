@@ -40,7 +40,8 @@ class Config(C.Structure):
                 ("hbar_over_m", C.c_double), ("four_pi_G", C.c_double),
                 ("n_particles", C.c_int64), ("particle_mass", C.c_double),
                 ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double),
-                ("baryon_mode", C.c_int32), ("nbody_substeps", C.c_int32)]
+                ("baryon_mode", C.c_int32), ("nbody_substeps", C.c_int32),
+                ("boundary", C.c_int32)]
 
 
 _lib = None
@@ -71,6 +72,11 @@ def lib():
         L.orc_absorb_mask.argtypes = [cp, C.c_double, dp]
         L.orc_mass_fraction_radii.argtypes = [cp, dp, C.POINTER(C.c_int32), dp, ip, dp]
         L.orc_mass_fraction_radii.restype = ip
+        L.orc_kdk_ext.argtypes = [cp, dp, dp, dp, C.c_int64, C.c_double, dp]
+        L.orc_poisson_direct.argtypes = [cp, dp, dp]
+        L.orc_cube_self_integral.restype = C.c_double
+        L.orc_tidal_correct.argtypes = [cp, dp, dp]
+        L.orc_energy_ext.argtypes = [cp, dp, dp, dp, dp, dp]
         L.orc_dt_auto.restype = C.c_double
         L.orc_power_spectrum.argtypes = [dp, ip, ip, dp, C.POINTER(C.c_int64)]
         L.orc_restrict.argtypes = [dp, ip, dp, ip]
@@ -102,17 +108,19 @@ def get_threads() -> int:
 
 
 BARYON_DYNAMIC, BARYON_STATIC = 0, 1
+BOUNDARY_PERIODIC, BOUNDARY_VACUUM = 0, 1
 
 
 def make_config(shape, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0,
                 particle_mass=0.0, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0,
-                baryon_mode=BARYON_DYNAMIC, nbody_substeps=1) -> Config:
+                baryon_mode=BARYON_DYNAMIC, nbody_substeps=1,
+                boundary=BOUNDARY_PERIODIC) -> Config:
     if isinstance(L, (int, float)):
         L = (float(L),) * 3
     nx, ny, nz = shape
     return Config(nx, ny, nz, L[0], L[1], L[2], hbar_over_m, four_pi_G, int(n_particles),
                   float(particle_mass), float(kappa), float(absorb_alpha), float(absorb_nb),
-                  int(baryon_mode), int(nbody_substeps))
+                  int(baryon_mode), int(nbody_substeps), int(boundary))
 
 
 def fft1d(x, sign=-1):
@@ -165,24 +173,49 @@ def potential(cfg: Config, psi, pos=None):
     return phi
 
 
-def kdk(cfg: Config, psi, pos=None, vel=None, nsteps=1, dt=1e-4):
-    """Run ``nsteps`` unmerged KDK steps; returns new (psi, pos, vel) arrays."""
+def kdk(cfg: Config, psi, pos=None, vel=None, nsteps=1, dt=1e-4, phi_ext=None):
+    """Run ``nsteps`` unmerged KDK steps; returns new (psi, pos, vel) arrays.
+    ``phi_ext``: external potential already passed through tidal_correct."""
     a = _c128(psi).copy()
     p = _f64(pos).copy() if pos is not None else None
     v = _f64(vel).copy() if vel is not None else None
-    lib().orc_kdk(C.byref(cfg), _p(a.view(np.float64)), _p(p), _p(v), int(nsteps), float(dt))
+    ext = _f64(phi_ext) if phi_ext is not None else None
+    lib().orc_kdk_ext(C.byref(cfg), _p(a.view(np.float64)), _p(p), _p(v), int(nsteps),
+                      float(dt), _p(ext) if ext is not None else None)
     return a, p, v
 
 
+def poisson_direct(cfg: Config, rho):
+    """Isolated potential by direct summation (small grids only)."""
+    r = _f64(rho)
+    phi = np.empty_like(r)
+    lib().orc_poisson_direct(C.byref(cfg), _p(r), _p(phi))
+    return phi
+
+
+def cube_self_integral() -> float:
+    return float(lib().orc_cube_self_integral())
+
+
+def tidal_correct(cfg: Config, phi_ext):
+    """External potential with its mean acceleration removed (Sec. 4.3)."""
+    a = _f64(phi_ext)
+    out = np.empty_like(a)
+    lib().orc_tidal_correct(C.byref(cfg), _p(a), _p(out))
+    return out
+
+
 ENERGY_FIELDS = ("mass", "e_kin", "e_pot", "e_kin_particles", "e_total", "px", "py", "pz",
-                 "max_abs_phi", "e_self", "max_rho")
+                 "max_abs_phi", "e_self", "max_rho", "e_ext")
 
 
-def energy(cfg: Config, psi, pos=None, vel=None) -> dict:
-    out = np.zeros(11)
-    lib().orc_energy(C.byref(cfg), _p(_c128(psi).view(np.float64)),
-                     _p(_f64(pos)) if pos is not None else None,
-                     _p(_f64(vel)) if vel is not None else None, _p(out))
+def energy(cfg: Config, psi, pos=None, vel=None, phi_ext=None) -> dict:
+    out = np.zeros(12)
+    ext = _f64(phi_ext) if phi_ext is not None else None
+    lib().orc_energy_ext(C.byref(cfg), _p(_c128(psi).view(np.float64)),
+                         _p(_f64(pos)) if pos is not None else None,
+                         _p(_f64(vel)) if vel is not None else None,
+                         _p(ext) if ext is not None else None, _p(out))
     return dict(zip(ENERGY_FIELDS, out.tolist()))
 
 

@@ -48,6 +48,9 @@ typedef struct {
      * sub-steps of h = dt / S run in the potential of the step's start; the
      * last half kick takes the step's new potential */
     int32_t nbody_substeps;
+    /* gravity boundary: 0 periodic (Fourier solve, mean removed), 1 vacuum
+     * (isolated solve by zero-padded convolution; cubic cells) */
+    int32_t boundary;
 } orc_config;
 
 /* Number of worker threads (0 = all hardware threads).  Results never depend
@@ -82,6 +85,20 @@ void orc_potential(const orc_config* c, const double* psi, const double* pos, do
 void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
              double dt);
 
+/* orc_kdk with an external potential phi_ext (real [nx][ny][nz], already
+ * corrected by orc_tidal_correct; NULL = none) added to the self-gravity felt
+ * by the wave and the particles. */
+void orc_kdk_ext(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
+                 double dt, const double* phi_ext);
+
+/* Isolated Poisson solve by direct summation over all node pairs with the
+ * same sampled Green's function (O(N^6): small grids only). */
+void orc_poisson_direct(const orc_config* c, const double* rho, double* phi);
+/* Integral of 1/|u| over the unit cube centred at the origin. */
+double orc_cube_self_integral(void);
+/* External (tidal) potential with its mean acceleration removed (Sec. 4.3). */
+void orc_tidal_correct(const orc_config* c, const double* phi_in, double* phi_out);
+
 /* Energies of a synchronised state.  out[0..10] =
  *   mass = sum |psi|^2 dV, e_kin (spectral, eta^2/2 int |grad psi|^2),
  *   e_pot = 1/2 int rho_tot Phi dV, e_kin_particles = 1/2 sum m v^2,
@@ -89,6 +106,10 @@ void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t
  *   e_self = kappa/2 int |psi|^4 dV, max |psi|^2. */
 void orc_energy(const orc_config* c, const double* psi, const double* pos, const double* vel,
                 double* out);
+/* orc_energy with an external potential: out[11] = int rho_tot phi_ext dV
+ * (in e_total; max |Phi| is of the potential felt, self plus external). */
+void orc_energy_ext(const orc_config* c, const double* psi, const double* pos, const double* vel,
+                    const double* phi_ext, double* out);
 /* The paper's overall energy terms (Sec. 3.6) exactly as printed:
  *   out[0] K = 1/2 int |rho v|^2 / rho (rho v = eta Im(psi* grad psi), central
  *              differences, cells with rho <= 1e-30 skipped),

@@ -34,8 +34,88 @@ struct Grid {
     }
 };
 
-// (c) Phi = F^-1{ -(4 pi G) / k^2 F{rho} }, mean removed by zeroing k = 0.
+// Integral of 1/|u| over the unit cube centred on u = 0.  Split into the six
+// pyramids on which one coordinate is largest; in each, u = x (1, s, t) gives
+// 6 * int_0^(1/2) x dx * int int_[-1,1]^2 (1 + s^2 + t^2)^(-1/2) ds dt
+// = (3/4) * 4 * J, J = int int_[0,1]^2 (1 + s^2 + t^2)^(-1/2), the smooth J
+// taken by 24-point Gauss-Legendre in each variable (nodes by Newton on P_24).
+static double cube_self_integral() {
+    const int m = 24;
+    double xs[m], ws[m];
+    for (int i = 0; i < m; ++i) {
+        double x = std::cos(kPi * (i + 0.75) / (m + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= m; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = m * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        xs[i] = 0.5 * (x + 1.0);              // mapped to [0, 1]
+        ws[i] = 1.0 / ((1.0 - x * x) * dp * dp);  // 2/((1-x^2)P'^2), halved
+    }
+    double J = 0.0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            J += ws[i] * ws[j] / std::sqrt(1.0 + xs[i] * xs[i] + xs[j] * xs[j]);
+    return 3.0 * J;
+}
+
+// Sampled free-space Green's function of the isolated solve (Sec. 3.2.1,
+// vacuum boundary): g(r) = -G dV / |r| between nodes, and for the node itself
+// -G times the integral of 1/|x| over its own cell (cubic cells, h^2 times the
+// unit-cube integral), G = four_pi_G / (4 pi).
+static double green_iso(const orc_config* c, const Grid& g, int64_t di, int64_t dj, int64_t dk,
+                        double self) {
+    const double G = c->four_pi_G / (4.0 * kPi);
+    if (di == 0 && dj == 0 && dk == 0) return -G * g.dx * g.dx * self;
+    const double x = di * g.dx, y = dj * g.dy, z = dk * g.dz;
+    return -G * g.dv / std::sqrt(x * x + y * y + z * z);
+}
+
+// Isolated Poisson solve: the linear convolution Phi = g * rho over the box,
+// as a circular convolution on the zero-padded (2 nx, 2 ny, 2 nz) grid (the
+// O(N^3 log N) stand-in for the O(N^4) method the paper cites).
+static void poisson_isolated(const orc_config* c, const double* rho, double* phi) {
+    Grid g(c);
+    const int64_t px = 2 * g.nx, py = 2 * g.ny, pz = 2 * g.nz, pn = px * py * pz;
+    const double self = cube_self_integral();
+    std::vector<cplx> fr(size_t(pn), cplx(0.0, 0.0));
+    std::vector<cplx> fg(static_cast<size_t>(pn));
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k)
+                fr[size_t((i * py + j) * pz + k)] = cplx(rho[(i * g.ny + j) * g.nz + k], 0.0);
+    for (int64_t i = 0; i < px; ++i)
+        for (int64_t j = 0; j < py; ++j)
+            for (int64_t k = 0; k < pz; ++k) {
+                // offsets of the padded circulant: i and i - 2n are the same node
+                const int64_t di = i <= g.nx ? i : i - px, dj = j <= g.ny ? j : j - py,
+                              dk = k <= g.nz ? k : k - pz;
+                fg[size_t((i * py + j) * pz + k)] = cplx(green_iso(c, g, di, dj, dk, self), 0.0);
+            }
+    fft3d(fr.data(), int(px), int(py), int(pz), -1);
+    fft3d(fg.data(), int(px), int(py), int(pz), -1);
+    for (int64_t q = 0; q < pn; ++q) fr[size_t(q)] *= fg[size_t(q)];
+    fft3d(fr.data(), int(px), int(py), int(pz), +1);
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k)
+                phi[(i * g.ny + j) * g.nz + k] = fr[size_t((i * py + j) * pz + k)].real();
+}
+
+// (c) Phi = F^-1{ -(4 pi G) / k^2 F{rho} }, mean removed by zeroing k = 0;
+// with the vacuum boundary the isolated solve above.
 static void poisson(const orc_config* c, const double* rho, double* phi) {
+    if (c->boundary == 1) {
+        poisson_isolated(c, rho, phi);
+        return;
+    }
     Grid g(c);
     std::vector<cplx> f(g.n());
     for (int64_t i = 0; i < g.n(); ++i) f[i] = cplx(rho[i], 0.0);
@@ -208,8 +288,15 @@ static void particle_substeps(const orc_config* c, const double* phi, double* po
     }
 }
 
+// Potential felt by the wave and the particles: self-gravity plus the
+// (already corrected) external potential, if any.
+static void add_external(const orc_config* c, const double* phi_ext, double* phi) {
+    if (!phi_ext) return;
+    for (int64_t i = 0; i < cells(c); ++i) phi[i] += phi_ext[i];
+}
+
 static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_t nsteps,
-                double dt) {
+                double dt, const double* phi_ext) {
     const int64_t n = cells(c);
     // static baryons (Sec. 3.2.2) only source the potential
     const bool parts = c->n_particles > 0 && c->baryon_mode == 0;
@@ -220,6 +307,7 @@ static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_
         absorb_mask(c, dt, mask.data());
     }
     total_potential(c, psi, pos, phi.data());
+    add_external(c, phi_ext, phi.data());
     for (int64_t s = 0; s < nsteps; ++s) {
         // (a) first half kick with the current potential
         kick(c, psi, phi.data(), 0.5 * dt);
@@ -230,6 +318,7 @@ static void kdk(const orc_config* c, cplx* psi, double* pos, double* vel, int64_
         drift(c, psi, dt);
         // (c) potential of the wave density plus the deposited baryons
         total_potential(c, psi, pos, phi.data());
+        add_external(c, phi_ext, phi.data());
         // (d) second half kick with the new potential
         kick(c, psi, phi.data(), 0.5 * dt);
         if (parts) particle_kick(c, phi.data(), pos, vel, 0.5 * dt / S, acc);
@@ -261,11 +350,67 @@ void orc_potential(const orc_config* c, const double* psi, const double* pos, do
 
 void orc_kdk(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
              double dt) {
-    kdk(c, reinterpret_cast<cplx*>(psi), pos, vel, nsteps, dt);
+    kdk(c, reinterpret_cast<cplx*>(psi), pos, vel, nsteps, dt, nullptr);
 }
 
-void orc_energy(const orc_config* c, const double* psi_in, const double* pos, const double* vel,
-                double* out) {
+void orc_kdk_ext(const orc_config* c, double* psi, double* pos, double* vel, int64_t nsteps,
+                 double dt, const double* phi_ext) {
+    kdk(c, reinterpret_cast<cplx*>(psi), pos, vel, nsteps, dt, phi_ext);
+}
+
+void orc_poisson_direct(const orc_config* c, const double* rho, double* phi) {
+    Grid g(c);
+    const double self = cube_self_integral();
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k) {
+                double sum = 0.0;
+                for (int64_t a = 0; a < g.nx; ++a)
+                    for (int64_t b = 0; b < g.ny; ++b)
+                        for (int64_t d = 0; d < g.nz; ++d)
+                            sum += green_iso(c, g, i - a, j - b, k - d, self) *
+                                   rho[(a * g.ny + b) * g.nz + d];
+                phi[(i * g.ny + j) * g.nz + k] = sum;
+            }
+}
+
+double orc_cube_self_integral(void) { return cube_self_integral(); }
+
+// Tidal potential with its mean acceleration removed (Sec. 4.3): the mean
+// gradient along each axis over the nodes symmetric about the centre node
+// (1 .. n-1; node 0 has no mirror in a periodic box of even n), averaged over
+// the other two axes, is subtracted as a linear ramp through the box centre.
+void orc_tidal_correct(const orc_config* c, const double* in, double* out) {
+    Grid g(c);
+    const int64_t n[3] = {g.nx, g.ny, g.nz};
+    const double h[3] = {g.dx, g.dy, g.dz}, L[3] = {g.lx, g.ly, g.lz};
+    double grad[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k) {
+                const int64_t idx[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                    if (idx[a] != n[a] - 1) continue;
+                    int64_t lo[3] = {i, j, k};
+                    lo[a] = 1;
+                    const double d = in[(i * g.ny + j) * g.nz + k] -
+                                     in[(lo[0] * g.ny + lo[1]) * g.nz + lo[2]];
+                    grad[a] += d / (double(n[a] - 2) * h[a]);
+                }
+            }
+    for (int a = 0; a < 3; ++a) grad[a] /= double(g.n() / n[a]);
+    for (int64_t i = 0; i < g.nx; ++i)
+        for (int64_t j = 0; j < g.ny; ++j)
+            for (int64_t k = 0; k < g.nz; ++k) {
+                const double x[3] = {i * h[0] - 0.5 * L[0], j * h[1] - 0.5 * L[1],
+                                     k * h[2] - 0.5 * L[2]};
+                const int64_t o = (i * g.ny + j) * g.nz + k;
+                out[o] = in[o] - grad[0] * x[0] - grad[1] * x[1] - grad[2] * x[2];
+            }
+}
+
+void orc_energy_ext(const orc_config* c, const double* psi_in, const double* pos,
+                    const double* vel, const double* phi_ext, double* out) {
     Grid g(c);
     const cplx* psi = reinterpret_cast<const cplx*>(psi_in);
     const int64_t n = g.n();
@@ -287,10 +432,14 @@ void orc_energy(const orc_config* c, const double* psi_in, const double* pos, co
                 ek += g.k2(i, j, k) * std::norm(f[(i * g.ny + j) * g.nz + k]);
     const double eta = c->hbar_over_m;
     ek *= 0.5 * eta * eta * g.dv / double(n);
-    double ep = 0.0, maxphi = 0.0, rho4 = 0.0, maxrho = 0.0;
+    // an external potential enters once (not halved) and is part of the
+    // potential the wave feels
+    double ep = 0.0, maxphi = 0.0, rho4 = 0.0, maxrho = 0.0, ex = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         ep += rho[i] * phi[i];
-        maxphi = std::max(maxphi, std::fabs(phi[i]));
+        const double pe = phi_ext ? phi_ext[i] : 0.0;
+        ex += rho[i] * pe;
+        maxphi = std::max(maxphi, std::fabs(phi[i] + pe));
         const double d = std::norm(psi[i]);
         rho4 += d * d;
         maxrho = std::max(maxrho, d);
@@ -309,11 +458,18 @@ void orc_energy(const orc_config* c, const double* psi_in, const double* pos, co
     out[1] = ek;
     out[2] = ep;
     out[3] = kp;
-    out[4] = ek + ep + kp + es;
+    ex *= g.dv;
+    out[4] = ek + ep + kp + es + ex;
     for (int a = 0; a < 3; ++a) out[5 + a] = mom[a] * c->particle_mass;
     out[8] = maxphi;
     out[9] = es;
     out[10] = maxrho;
+    out[11] = ex;
+}
+
+void orc_energy(const orc_config* c, const double* psi_in, const double* pos, const double* vel,
+                double* out) {
+    orc_energy_ext(c, psi_in, pos, vel, nullptr, out);
 }
 
 void orc_paper_energies(const orc_config* c, const double* psi_in, const double* phi, double* out) {

@@ -1,0 +1,186 @@
+"""CPU pins of the oracle's vacuum-boundary Poisson solve (Sec. 3.2.1) and of the
+external (tidal) potential with its mean acceleration removed (Sec. 4.3).
+
+Isolated solve: the zero-padded FFT convolution equals the direct sum over node
+pairs with the same Green's function; its potential of a Gaussian converges to
+the closed form -G M erf(r / (sqrt(2) sigma)) / r as dx^2; it commutes with
+translations inside the box; the self term is the unit-cube integral of 1/r,
+6 ln((1 + sqrt 3) / sqrt 2) - pi / 2.  Steps with it keep the norm, reverse in
+time and conserve energy to O(dt^2).
+
+External potential: a harmonic trap holds its Gaussian ground state still
+(with the phase of its energy, 3 omega / 2) to O(dt^2), and test particles in
+it oscillate as x0 cos(omega t); a linear potential becomes a constant (a
+global phase only); adding a ramp to any potential changes the corrected one by
+a constant; a trap symmetric about the centre node is left as it is; the total
+energy with a static external potential is conserved to O(dt^2).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+from paper_2606_25026_amd import inputs
+
+
+def coords(n, L=1.0):
+    x = np.arange(n) * (L / n)
+    return np.meshgrid(x, x, x, indexing="ij")
+
+
+# -------------------------------------------------------------- isolated
+def test_cube_self_integral_closed_form(orc):
+    exact = 6 * math.log((1 + math.sqrt(3)) / math.sqrt(2)) - math.pi / 2
+    assert orc.cube_self_integral() == pytest.approx(exact, rel=1e-14)
+    # midpoint rule on a fine lattice of the centred cube (no node at 0)
+    m = 200
+    u = (np.arange(m) + 0.5) / m - 0.5
+    X, Y = np.meshgrid(u, u, indexing="ij")
+    mid = sum(np.sum(1 / np.sqrt(X * X + Y * Y + z * z)) for z in u) / m ** 3
+    assert mid == pytest.approx(exact, rel=1e-5)
+
+
+@pytest.mark.parametrize("shape,L", [((8, 8, 8), 1.0), ((8, 12, 6), (1.0, 1.5, 0.75))])
+def test_isolated_solve_equals_direct_sum(orc, shape, L):
+    rng = np.random.default_rng(sum(shape))
+    rho = rng.random(shape)
+    cfg = orc.make_config(shape, L=L, boundary=orc.BOUNDARY_VACUUM, four_pi_G=3.0)
+    a, b = orc.poisson(cfg, rho), orc.poisson_direct(cfg, rho)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
+
+
+def test_isolated_gaussian_converges_to_closed_form(orc):
+    sig, G4 = 0.06, 2.0
+    errs = []
+    for n in (32, 64, 128):
+        X, Y, Z = coords(n)
+        r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2)
+        rho = np.exp(-r ** 2 / (2 * sig ** 2))
+        mass = rho.sum() / n ** 3
+        G = G4 / (4 * math.pi)
+        rr = np.where(r > 0, r, 1.0)
+        exact = np.where(r > 0, -G * mass * erf(r / (math.sqrt(2) * sig)) / rr,
+                         -G * mass * math.sqrt(2 / math.pi) / sig)
+        cfg = orc.make_config((n,) * 3, boundary=orc.BOUNDARY_VACUUM, four_pi_G=G4)
+        phi = orc.poisson(cfg, rho)
+        errs.append(np.max(np.abs(phi - exact)) / np.max(np.abs(exact)))
+    assert errs[-1] < 1e-3
+    for a, b in zip(errs, errs[1:]):
+        assert 3.5 < a / b < 4.5, errs
+
+
+def test_isolated_solve_commutes_with_translation(orc):
+    n = 24
+    rng = np.random.default_rng(5)
+    rho = np.zeros((n,) * 3)
+    rho[4:12, 5:14, 3:10] = rng.random((8, 9, 7))
+    cfg = orc.make_config((n,) * 3, boundary=orc.BOUNDARY_VACUUM)
+    a = orc.poisson(cfg, rho)
+    b = orc.poisson(cfg, np.roll(rho, (6, 3, 9), axis=(0, 1, 2)))
+    assert np.max(np.abs(np.roll(a, (6, 3, 9), axis=(0, 1, 2))[6:, 3:, 9:] - b[6:, 3:, 9:])) \
+        < 1e-13 * np.max(np.abs(a))
+    # and differs from the periodic solve
+    per = orc.poisson(orc.make_config((n,) * 3), rho)
+    assert np.max(np.abs((a - a.mean()) - per)) > 0.05 * np.max(np.abs(per))
+
+
+def test_isolated_steps_unitary_reversible_second_order(orc):
+    wl = inputs.coupled_halo(n=32, n_particles=500, seed=6, steps=0)
+    pos, vel = wl.pos.astype(np.float64), wl.vel.astype(np.float64)
+    cfg = orc.make_config((32,) * 3, n_particles=500, particle_mass=wl.particle_mass,
+                          boundary=orc.BOUNDARY_VACUUM, four_pi_G=10.0)
+    psi, p, v = orc.kdk(cfg, wl.psi, pos, vel, nsteps=30, dt=wl.dt)
+    assert np.linalg.norm(psi) / np.linalg.norm(wl.psi) == pytest.approx(1.0, abs=1e-12)
+    back, pb, vb = orc.kdk(cfg, psi, p, v, nsteps=30, dt=-wl.dt)
+    assert np.linalg.norm(back - wl.psi) / np.linalg.norm(wl.psi) < 1e-10
+    assert np.max(np.abs(pb - pos)) < 1e-10
+    e0 = orc.energy(cfg, wl.psi, pos, vel)["e_total"]
+    T, drifts = 0.004, []
+    for k in (20, 40, 80):
+        ps, pp, vv = orc.kdk(cfg, wl.psi, pos, vel, nsteps=k, dt=T / k)
+        drifts.append(orc.energy(cfg, ps, pp, vv)["e_total"] - e0)
+    # the PM coupling adds a dt-independent part (not an integration error);
+    # differences isolate the O(dt^2) one
+    d1, d2 = drifts[0] - drifts[1], drifts[1] - drifts[2]
+    assert 3.6 < d1 / d2 < 4.4, drifts
+
+
+# -------------------------------------------------------------- external
+def trap(n, w):
+    X, Y, Z = coords(n)
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2
+    return r2, 0.5 * w * w * r2
+
+
+def test_trap_ground_state_is_stationary(orc):
+    n, w, T = 64, 400.0, 0.01
+    r2, ext = trap(n, w)
+    cfg = orc.make_config((n,) * 3, four_pi_G=0.0)
+    corr = orc.tidal_correct(cfg, ext)
+    assert np.array_equal(corr, ext)          # symmetric about the centre node
+    psi0 = np.exp(-w * r2 / 2).astype(complex)
+    errs = []
+    for k in (50, 100, 200):
+        psi, _, _ = orc.kdk(cfg, psi0, nsteps=k, dt=T / k, phi_ext=corr)
+        exact = psi0 * np.exp(-1j * 1.5 * w * T)
+        errs.append(np.linalg.norm(psi - exact) / np.linalg.norm(psi0))
+    assert errs[-1] < 2e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 3.8 < a / b < 4.2, errs
+
+
+def test_test_particles_oscillate_in_the_trap(orc):
+    n, w = 32, 30.0
+    _, ext = trap(n, w)
+    cfg = orc.make_config((n,) * 3, four_pi_G=0.0, n_particles=3, particle_mass=1.0)
+    pos = np.array([[0.6, 0.5, 0.5], [0.5, 0.41, 0.5], [0.5, 0.5, 0.53]])
+    vel = np.zeros((3, 3))
+    psi = np.zeros((n,) * 3, complex)
+    psi[0, 0, 0] = 1e-30
+    T = 0.5 * math.pi / w
+    errs = []
+    for k in (25, 50, 100):
+        _, p, _ = orc.kdk(cfg, psi, pos, vel, nsteps=k, dt=T / k, phi_ext=ext)
+        errs.append(np.max(np.abs(p - (0.5 + (pos - 0.5) * math.cos(w * T)))))
+    assert errs[-1] < 1e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 3.8 < a / b < 4.2, errs
+
+
+def test_linear_potential_is_removed(orc):
+    n = 32
+    X, Y, Z = coords(n)
+    lin = 3.0 * X - 2.0 * Y + 0.5 * Z + 7.0
+    cfg = orc.make_config((n,) * 3)
+    corr = orc.tidal_correct(cfg, lin)
+    assert np.max(np.abs(corr - corr[n // 2, n // 2, n // 2])) < 1e-13
+    assert corr[n // 2, n // 2, n // 2] == pytest.approx(3.0 * 0.5 - 2.0 * 0.5 + 0.25 + 7.0)
+    # ramps change the corrected potential by a constant only
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((n,) * 3)
+    d = orc.tidal_correct(cfg, f + lin) - orc.tidal_correct(cfg, f)
+    assert np.max(np.abs(d - d.flat[0])) < 1e-12
+    # a constant potential is a global phase
+    wl = inputs.plane_wave_box(n, seed=2)
+    a, _, _ = orc.kdk(cfg, wl.psi, nsteps=10, dt=wl.dt, phi_ext=corr)
+    b, _, _ = orc.kdk(cfg, wl.psi, nsteps=10, dt=wl.dt)
+    c0 = corr[0, 0, 0]
+    assert np.max(np.abs(a - b * np.exp(-1j * c0 * 10 * wl.dt))) < 1e-12
+
+
+def test_energy_with_static_external_potential(orc):
+    wl = inputs.coupled_halo(n=32, n_particles=0, seed=8, steps=0)
+    _, ext = trap(32, 40.0)
+    cfg = orc.make_config((32,) * 3, four_pi_G=5.0)
+    corr = orc.tidal_correct(cfg, ext)
+    e0 = orc.energy(cfg, wl.psi, phi_ext=corr)
+    assert e0["e_ext"] > 0
+    T, drifts = 0.004, []
+    for k in (20, 40, 80):
+        psi, _, _ = orc.kdk(cfg, wl.psi, nsteps=k, dt=T / k, phi_ext=corr)
+        e = orc.energy(cfg, psi, phi_ext=corr)
+        drifts.append(e["e_total"] - e0["e_total"])
+    assert abs(e["e_ext"] - e0["e_ext"]) > 100 * abs(drifts[-1])
+    for a, b in zip(drifts, drifts[1:]):
+        assert 3.8 < a / b < 4.2, drifts
