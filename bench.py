@@ -281,6 +281,11 @@ def main():
                     help="halo workload: particles move (dynamic) or only source the potential")
     ap.add_argument("--substeps", type=int, default=1,
                     help="halo workload: particle leapfrog sub-steps per wave step")
+    ap.add_argument("--boundary", choices=["periodic", "vacuum"], default="periodic",
+                    help="halo workload: gravity boundary (vacuum = zero-padded isolated solve)")
+    ap.add_argument("--tidal", type=float, default=0.0,
+                    help="halo workload: strength of an external tidal potential "
+                         "T (x^2 + y^2 - 2 z^2) / 2 about the box centre (0 = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -303,7 +308,9 @@ def main():
     n3 = args.n ** 3
     extended = dict(kappa=args.kappa, absorb_alpha=args.absorb_alpha, absorb_nb=args.absorb_nb,
                     baryon_mode=1 if args.baryons == "static" else 0,
-                    nbody_substeps=args.substeps)
+                    nbody_substeps=args.substeps,
+                    boundary=1 if args.boundary == "vacuum" else 0,
+                    external_potential=1 if args.tidal != 0.0 else 0)
     cfg = wdm.make_config(args.n, n_particles=wl.n_particles, particle_mass=wl.particle_mass,
                           **extended)
     plan = wdm.Plan(cfg, device=dev)
@@ -316,6 +323,12 @@ def main():
         tuning = wdm.wdm_get_tuning(h)
     else:
         tuning = wdm.autotune(h, cfg, reps=10)
+    if args.tidal != 0.0:
+        x = (torch.arange(args.n, dtype=torch.float32, device=dev) + 0.5 - 0.5) / args.n - 0.5
+        X, Y, Z = torch.meshgrid(x, x, x, indexing="ij")
+        ext = (0.5 * args.tidal * (X * X + Y * Y - 2 * Z * Z)).contiguous()
+        wdm.wdm_set_external_potential(h, 0, ext)
+        del X, Y, Z, ext
     psi = torch.from_numpy(wl.psi.astype(np.complex64)).to(dev)
     pos = torch.from_numpy(wl.pos).to(dev) if wl.n_particles else None
     vel = torch.from_numpy(wl.vel).to(dev) if wl.n_particles else None
@@ -432,6 +445,11 @@ def main():
     if args.baryons != "dynamic" or args.substeps > 1:
         out["config"]["workload"] += (f", {args.baryons} baryons, {args.substeps} particle "
                                       "sub-steps per step")
+    if args.boundary != "periodic":
+        out["config"]["workload"] += ", vacuum gravity boundary (zero-padded isolated solve)"
+    if args.tidal != 0.0:
+        out["config"]["workload"] += f", external tidal potential T={args.tidal:g}"
+
     if out["config"]["workload"] != base_workload:
         out["config"].update(extended)
     print(json.dumps(out))

@@ -57,6 +57,7 @@ typedef enum { WDM_C64 = 0, WDM_C128 = 1 } wdm_precision;
 
 /* One periodic box (an ensemble has several). */
 enum { WDM_BARYON_DYNAMIC = 0, WDM_BARYON_STATIC = 1 };
+enum { WDM_BOUNDARY_PERIODIC = 0, WDM_BOUNDARY_VACUUM = 1 };
 
 typedef struct {
     int32_t nx, ny, nz;        /* each in {16,32,64,96,128,192,256,384,512} */
@@ -88,6 +89,17 @@ typedef struct {
      * step's start; the closing half kick takes the step's new potential, and
      * the baryons are deposited once, after the last sub-step. */
     int32_t nbody_substeps;
+    /* Gravity boundary (Sec. 3.2.1): WDM_BOUNDARY_PERIODIC, the Fourier solve
+     * with the mean removed; WDM_BOUNDARY_VACUUM, the isolated solve as a
+     * convolution with the free-space Green's function -G dV / r on the
+     * zero-padded (2 nx, 2 ny, 2 nz) grid (G = four_pi_G / (4 pi); the node's
+     * own cell contributes -G h^2 C, C = 6 ln((1 + sqrt 3) / sqrt 2) - pi / 2,
+     * the integral of 1/r over the unit cube).  Vacuum needs cubic cells and
+     * n <= 256 per axis; the wave's own propagation stays periodic. */
+    int32_t boundary;
+    /* 1 reserves a per-member external (tidal) potential, set with
+     * wdm_set_external_potential; 0 none. */
+    int32_t external_potential;
 } wdm_config;
 
 /* Diagnostics of a synchronised state (Sec. 3.6 energy bookkeeping). */
@@ -104,6 +116,9 @@ typedef struct {
     double dt_auto;            /* CFL step of Sec. 3.5 from the last wdm_set_state */
     double e_self;             /* kappa/2 int |psi|^4 dV (included in e_total) */
     double max_rho;            /* max |psi|^2 over the grid */
+    double e_ext;              /* int rho_tot Phi_ext dV of an external potential (in e_total;
+                                  e_pot is then the self-gravity part, max_abs_phi and the
+                                  CFL step are of the potential felt, self plus external) */
 } wdm_energy_t;
 
 /* The paper's diagnostics of a synchronised state (Sec. 3.6, App. A.1),
@@ -174,6 +189,17 @@ wdm_status wdm_potential(wdm_plan* plan, int32_t member, void* phi_out);
 
 /* FP64 diagnostics (host out).  Synchronises the plan's stream. */
 wdm_status wdm_energy(wdm_plan* plan, int32_t member, wdm_energy_t* out);
+
+/* External (tidal) potential of a member created with external_potential =
+ * 1 (Sec. 4.3): phi_ext (dev, real [nx][ny][nz] of the plan precision; NULL
+ * = zero) is copied, and its mean acceleration removed: along each axis the
+ * gradient averaged over the nodes symmetric about the centre node (1 .. n-1,
+ * the other two axes over all nodes), (phi[n-1] - phi[1]) / ((n - 2) h), is
+ * subtracted as a ramp through the box centre.  The corrected potential is
+ * added to the self-gravity felt by the wave and the particles from the next
+ * step on (set it before wdm_set_state for dt_auto to include it).  For a
+ * time-dependent field, set it again between wdm_step calls. */
+wdm_status wdm_set_external_potential(wdm_plan* plan, int32_t member, const void* phi_ext);
 
 /* The paper's halo diagnostics (host out): K, Q, V, 2K + 2Q + V, the wave
  * momentum and mass, and the mass-fraction radii around the node centre[3]

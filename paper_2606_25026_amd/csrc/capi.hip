@@ -72,26 +72,28 @@ struct Carver {
 
 struct MemberLayout {
     size_t psi, phi, rho_b, spec, nyq, kin, absorb, dt, results;
+    size_t pad = 0, green = 0, ext = 0;   // vacuum boundary, external potential
     size_t p[7], a[7], key_a, key_b, idx_a, idx_b, hist;
 };
 
 struct Layout {
     std::vector<MemberLayout> m;
     std::map<int, size_t> tw;     // axis length -> twiddle table offset
-    size_t scratch = 0, partials = 0, table = 0, pk = 0, total = 0;
+    size_t scratch = 0, partials = 0, table = 0, iso_table = 0, pk = 0, total = 0;
     int64_t partial_rows = 0;
 };
 
 enum Kind : int {
     kKZPot = 0, kKParticles, kKYPsiF, kKXKin, kKYPsiI, kKZDens, kKYSpecF, kKXGreen, kKYSpecI,
-    kKClose, kKCloseParticles, kKSort, kKinds
+    kKClose, kKCloseParticles, kKSort, kKVacuum, kKPhiR2C, kKinds
 };
 const char* kKindNames[kKinds] = {"z_potential_kick", "particles_kick_drift_deposit",
                                   "y_fft_psi_fwd",    "x_kinetic",
                                   "y_fft_psi_inv",    "z_density_r2c",
                                   "y_fft_spec_fwd",   "x_green",
                                   "y_fft_spec_inv",   "z_potential_close_kick",
-                                  "particles_close_kick", "particle_sort"};
+                                  "particles_close_kick", "particle_sort",
+                                  "vacuum_poisson",   "z_phi_r2c"};
 
 bool valid_config(const wdm_config& c, std::string& why) {
     if (!axis_supported(c.nx) || !axis_supported(c.ny) || !axis_supported(c.nz)) {
@@ -138,6 +140,25 @@ bool valid_config(const wdm_config& c, std::string& why) {
         why = "nbody_substeps must be in [0, 1024]";
         return false;
     }
+    if (c.boundary != WDM_BOUNDARY_PERIODIC && c.boundary != WDM_BOUNDARY_VACUUM) {
+        why = "boundary must be WDM_BOUNDARY_PERIODIC or WDM_BOUNDARY_VACUUM";
+        return false;
+    }
+    if (c.boundary == WDM_BOUNDARY_VACUUM) {
+        const double h = c.lx / c.nx;
+        if (h != c.ly / c.ny || h != c.lz / c.nz) {
+            why = "the vacuum boundary needs cubic cells";
+            return false;
+        }
+        if (!axis_supported(2 * c.nx) || !axis_supported(2 * c.ny) || !axis_supported(2 * c.nz)) {
+            why = "the vacuum boundary needs axis lengths <= 256 (padded to 2n)";
+            return false;
+        }
+    }
+    if (c.external_potential != 0 && c.external_potential != 1) {
+        why = "external_potential must be 0 or 1";
+        return false;
+    }
     return true;
 }
 
@@ -174,6 +195,11 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         m.nyq = c.take(int64_t(g.nx) * g.ny * cs);
         m.kin = c.take((int64_t(g.nx) + int64_t(g.ny) * g.nz) * 16);
         m.absorb = c.take((int64_t(g.nx) + g.ny + g.nz) * sizeof(double));
+        if (g.boundary == WDM_BOUNDARY_VACUUM) {
+            m.pad = c.take(8 * cells * cs);
+            m.green = c.take(8 * cells * rs);
+        }
+        if (g.external_potential) m.ext = c.take(cells * rs);
         m.dt = c.take(4 * sizeof(double));
         m.results = c.take(kRedFields * sizeof(double));
         const int64_t np = std::max<int64_t>(g.n_particles, 0);
@@ -186,6 +212,9 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         m.hist = c.take(int64_t(256) * (std::max(1, sort_blocks(np)) + 1) * 4);
         for (int len : {g.nx, g.ny, g.nz})
             if (!L.tw.count(len)) L.tw[len] = 0;
+        if (g.boundary == WDM_BOUNDARY_VACUUM)
+            for (int len : {2 * g.nx, 2 * g.ny, 2 * g.nz})
+                if (!L.tw.count(len)) L.tw[len] = 0;
     }
     // complex64: hi and lo float tables; complex128: one double table
     for (auto& kv : L.tw) kv.second = c.take(size_t(kv.first) * cs * (prec ? 1 : 2));
@@ -193,6 +222,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
     L.partial_rows = std::max<int64_t>(kRedBlocks, (maxplane + 7) / 8);
     L.partials = c.take(L.partial_rows * kRedFields * sizeof(double));
     L.table = c.take(n * sizeof(MemberDev));
+    L.iso_table = c.take(n * sizeof(MemberDev));
     L.pk = c.take(shells_partial_doubles() * sizeof(double));
     L.total = (c.off + kAlign - 1) / kAlign * kAlign;
     return true;
@@ -209,6 +239,7 @@ struct SizeClass {
     bool absorb = false;    // some member has an absorbing boundary
     bool extended = false;  // some member has a self-interaction or absorbing boundary
     int64_t moving_np = 0;  // most particles of a member whose particles move
+    bool vacuum = false;    // isolated Poisson solve (the class's members share the boundary)
 };
 
 struct Rec {
@@ -227,6 +258,8 @@ struct wdm_plan {
     std::vector<SizeClass> classes;
     std::vector<bool> has_state;        // user order
     MemberDev* table = nullptr;
+    MemberDev* iso_table = nullptr;     // padded-grid descriptors of vacuum members
+    std::vector<MemberDev> iso_host;
     Layout layout;
     uint8_t* ws = nullptr;
     int sort_interval = 32;
@@ -291,15 +324,76 @@ Launch one(wdm_plan* p, int32_t member) {
     return Launch{p->stream, p->table, p->dev_index[member], 1};
 }
 
+// Vacuum-boundary Poisson solve of a class (or one member): the density,
+// computed by P5 (`op`: from psi after its inverse z transform, or from psi in
+// real space) into Phi, is convolved with the free-space Green's function on
+// the zero-padded grid, and the potential is handed to the next P1 as the half
+// spectrum along z, as the periodic solve does.
+hipError_t enqueue_vacuum_poisson(wdm_plan* p, hipStream_t s, int first, int count, int nx,
+                                  int ny, int nz, DensOp op) {
+    const int prec = p->prec;
+    const Launch L{s, p->table, first, count};
+    const Launch LP{s, p->iso_table, first, count};
+    const int64_t cells = int64_t(nx) * ny * nz;
+    hipError_t e = timed_on(p, s, kKZDens,
+                            [&] { return launch_z_density(L, prec, nx, ny, nz, op); });
+    if (e != hipSuccess) return e;
+    e = timed_on(p, s, kKVacuum, [&] {
+        hipError_t r = launch_pad_density(L, prec, cells);
+        for (int axis = 2; axis >= 0 && r == hipSuccess; --axis)
+            r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, axis, false, 0);
+        if (r == hipSuccess) r = launch_mul_green(L, prec, cells);
+        for (int axis = 0; axis < 3 && r == hipSuccess; ++axis)
+            r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, axis, true, 0);
+        if (r == hipSuccess) r = launch_unpad(L, prec, cells);
+        return r;
+    });
+    if (e != hipSuccess) return e;
+    return timed_on(p, s, kKPhiR2C,
+                    [&] { return launch_z_density(L, prec, nx, ny, nz, kPhiR2C); });
+}
+
+// Transform of the padded Green's function of every vacuum class (once per plan).
+hipError_t compute_green(wdm_plan* p) {
+    hipError_t e = hipSuccess;
+    for (const auto& c : p->classes) {
+        if (!c.vacuum) continue;
+        const Launch L{p->stream, p->table, c.first, c.count};
+        const Launch LP{p->stream, p->iso_table, c.first, c.count};
+        const int64_t cells = int64_t(c.nx) * c.ny * c.nz;
+        if ((e = launch_green_fill(L, p->prec, cells)) != hipSuccess) return e;
+        for (int axis = 2; axis >= 0; --axis)
+            if ((e = launch_axis_fft(LP, p->prec, 2 * c.nx, 2 * c.ny, 2 * c.nz, axis, false, 0)) !=
+                hipSuccess)
+                return e;
+        if ((e = launch_green_extract(L, p->prec, cells)) != hipSuccess) return e;
+    }
+    return e;
+}
+
+// A member's extended kick (self-interaction, absorbing boundary, external
+// potential) as its class launches it.
+bool member_extended(const wdm_config& c) {
+    return c.kappa != 0.0 || c.absorb_alpha != 0.0 || c.external_potential != 0;
+}
+
 // Poisson solve of the density already deposited in rho_b plus |psi|^2
 // (psi in real space), ending with Phi written and psi untouched.
 hipError_t potential_from_state(wdm_plan* p, const Launch& L, const wdm_config& c) {
     hipError_t e;
-    if ((e = launch_z_density(L, p->prec, c.nx, c.ny, c.nz, kDensDirect)) != hipSuccess) return e;
-    if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, false)) != hipSuccess) return e;
-    if ((e = launch_x_green(L, p->prec, c.nx, c.ny, c.nz)) != hipSuccess) return e;
-    if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, true)) != hipSuccess) return e;
-    return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZPhiOnly, kHalfKick);
+    if (c.boundary == WDM_BOUNDARY_VACUUM) {
+        e = enqueue_vacuum_poisson(p, L.stream, L.first, L.count, c.nx, c.ny, c.nz,
+                                   kDensDirectToPhi);
+        if (e != hipSuccess) return e;
+    } else {
+        if ((e = launch_z_density(L, p->prec, c.nx, c.ny, c.nz, kDensDirect)) != hipSuccess)
+            return e;
+        if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, false)) != hipSuccess) return e;
+        if ((e = launch_x_green(L, p->prec, c.nx, c.ny, c.nz)) != hipSuccess) return e;
+        if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, true)) != hipSuccess) return e;
+    }
+    return launch_z_potential_kick(L, p->prec, c.nx, c.ny, c.nz, kZPhiOnly, kHalfKick, 0,
+                                   member_extended(c));
 }
 
 }  // namespace
@@ -350,10 +444,12 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const auto& A = members[a];
         const auto& B = members[b];
-        return std::make_tuple(A.nx, A.ny, A.nz) < std::make_tuple(B.nx, B.ny, B.nz);
+        return std::make_tuple(A.boundary, A.nx, A.ny, A.nz) <
+               std::make_tuple(B.boundary, B.nx, B.ny, B.nz);
     });
     p->dev_index.assign(n_members, 0);
     p->host.resize(n_members);
+    p->iso_host.resize(n_members);
     for (int d = 0; d < n_members; ++d) {
         const int u = order[d];
         p->dev_index[u] = d;
@@ -369,6 +465,9 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.scratch = ws + L.scratch;
         m.kin = ws + ml.kin;
         m.absorb = reinterpret_cast<double*>(ws + ml.absorb);
+        m.pad = c.boundary == WDM_BOUNDARY_VACUUM ? ws + ml.pad : nullptr;
+        m.green = c.boundary == WDM_BOUNDARY_VACUUM ? ws + ml.green : nullptr;
+        m.ext = c.external_potential ? ws + ml.ext : nullptr;
         m.tw_x = ws + L.tw.at(c.nx);
         m.tw_y = ws + L.tw.at(c.ny);
         m.tw_z = ws + L.tw.at(c.nz);
@@ -410,17 +509,38 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.partials = reinterpret_cast<double*>(ws + L.partials);
         m.results = reinterpret_cast<double*>(ws + ml.results);
         if (p->classes.empty() || p->classes.back().nx != c.nx || p->classes.back().ny != c.ny ||
-            p->classes.back().nz != c.nz)
+            p->classes.back().nz != c.nz ||
+            p->classes.back().vacuum != (c.boundary == WDM_BOUNDARY_VACUUM)) {
             p->classes.push_back({d, 0, c.nx, c.ny, c.nz, 0});
+            p->classes.back().vacuum = c.boundary == WDM_BOUNDARY_VACUUM;
+        }
         p->classes.back().count++;
         p->classes.back().max_np = std::max<int64_t>(p->classes.back().max_np, c.n_particles);
         if (c.absorb_alpha != 0.0) p->classes.back().absorb = true;
-        if (c.absorb_alpha != 0.0 || c.kappa != 0.0) p->classes.back().extended = true;
+        if (c.absorb_alpha != 0.0 || c.kappa != 0.0 || c.external_potential)
+            p->classes.back().extended = true;
         if (c.baryon_mode == WDM_BARYON_DYNAMIC)
             p->classes.back().moving_np =
                 std::max<int64_t>(p->classes.back().moving_np, c.n_particles);
     }
     p->table = reinterpret_cast<MemberDev*>(ws + L.table);
+    p->iso_table = reinterpret_cast<MemberDev*>(ws + L.iso_table);
+    // the padded grid of a vacuum member as a member of its own, for the plain
+    // axis transforms: doubled lengths, its twiddles, the padded buffer as psi
+    for (int d = 0; d < n_members; ++d) {
+        const MemberDev& m = p->host[d];
+        MemberDev& iso = p->iso_host[d];
+        iso = m;
+        if (!m.pad) continue;
+        iso.nx = 2 * m.nx;
+        iso.ny = 2 * m.ny;
+        iso.nz = 2 * m.nz;
+        iso.psi = m.pad;
+        iso.scratch = m.pad;
+        iso.tw_x = ws + L.tw.at(iso.nx);
+        iso.tw_y = ws + L.tw.at(iso.ny);
+        iso.tw_z = ws + L.tw.at(iso.nz);
+    }
 
     auto cleanup = [&](wdm_status st, const std::string& msg) {
         delete p;
@@ -447,6 +567,8 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
             return cleanup(WDM_EDEVICE, "twiddle upload failed");
     }
     if (hipMemcpy(p->table, p->host.data(), sizeof(MemberDev) * n_members,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->iso_table, p->iso_host.data(), sizeof(MemberDev) * n_members,
                   hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(WDM_EDEVICE, "member table upload failed");
     // clear accumulators and slots that must start at zero
@@ -462,6 +584,15 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
     for (const auto& c : p->classes)
         if (launch_absorb_tables(Launch{p->stream, p->table, c.first, c.count}) != hipSuccess)
             return cleanup(WDM_EDEVICE, "plan initialisation failed");
+    // no external potential until one is set
+    for (int d = 0; d < n_members; ++d) {
+        const MemberDev& m = p->host[d];
+        if (m.ext && launch_zero(p->stream, m.ext, size_t(int64_t(m.nx) * m.ny * m.nz) *
+                                                       (p->prec ? 8 : 4)) != hipSuccess)
+            return cleanup(WDM_EDEVICE, "plan initialisation failed");
+    }
+    if (compute_green(p) != hipSuccess)
+        return cleanup(WDM_EDEVICE, "Green's function of the vacuum boundary failed");
     if (hipStreamSynchronize(p->stream) != hipSuccess)
         return cleanup(WDM_EDEVICE, "plan initialisation failed");
     *out = p;
@@ -569,6 +700,12 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             })))
             return e;
         if (fork && !chk(hipStreamWaitEvent(s, p->ev_join, 0))) return e;
+        if (c.vacuum) {
+            if (!chk(enqueue_vacuum_poisson(p, s, c.first, c.count, c.nx, c.ny, c.nz,
+                                            kDensInvToPhi)))
+                return e;
+            continue;
+        }
         if (!chk(timed(p, kKZDens, [&] {
                 return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft, c.var[kTzDens]);
             })))
@@ -897,6 +1034,11 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     if (c.n_particles > 0) HIPCHK(launch_particles(L, prec, c.n_particles, 3, kHalfKick));
     HIPCHK(launch_reduce_grid(L, prec, n, 1));
     HIPCHK(launch_reduce_finish(L, 2, kRedBlocks, false));
+    // the stored Phi carries the external potential; its energy enters once
+    if (m.ext) {
+        HIPCHK(launch_reduce_grid(L, prec, n, 2));
+        HIPCHK(launch_reduce_finish(L, 10, kRedBlocks, false));
+    }
     // spectral kinetic energy: F_z, F_y into scratch, F_x fused with the sum
     HIPCHK(hipMemcpyAsync(m.scratch, m.psi, size_t(n) * (prec ? 16 : 8), hipMemcpyDeviceToDevice,
                           p->stream));
@@ -917,13 +1059,15 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     std::memset(out, 0, sizeof(*out));
     out->mass = res[0] * dv;
     out->e_kin = 0.5 * eta * eta * res[1] * dv / double(n);
-    out->e_pot = 0.5 * res[2] * dv;
+    const double s_ext = m.ext ? res[10] : 0.0;
+    out->e_pot = 0.5 * (res[2] - s_ext) * dv;
+    out->e_ext = s_ext * dv;
     if (c.n_particles > 0) {
         out->e_kin_particles = 0.5 * c.particle_mass * res[3];
         for (int a = 0; a < 3; ++a) out->momentum[a] = c.particle_mass * res[4 + a];
     }
     out->e_self = 0.5 * c.kappa * res[9] * dv;
-    out->e_total = out->e_kin + out->e_pot + out->e_kin_particles + out->e_self;
+    out->e_total = out->e_kin + out->e_pot + out->e_kin_particles + out->e_self + out->e_ext;
     out->max_abs_phi = res[7];
     out->max_rho = res[8];
     out->t = dts[3];
@@ -932,6 +1076,22 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     const bool finite = std::isfinite(out->mass) && std::isfinite(out->e_total) &&
                         std::isfinite(out->max_abs_phi);
     if (!finite) return fail(WDM_EUNSTABLE, "non-finite state");
+    return WDM_OK;
+}
+
+wdm_status wdm_set_external_potential(wdm_plan* p, int32_t member, const void* phi_ext) {
+    if (wdm_status s = check_member(p, member)) return s;
+    const wdm_config& c = p->cfg[member];
+    if (!c.external_potential)
+        return fail(WDM_EINVAL, "member was created without external_potential");
+    const MemberDev& m = p->host[p->dev_index[member]];
+    const int64_t n = cells_of(c);
+    const size_t bytes = size_t(n) * (p->prec ? 8 : 4);
+    if (phi_ext)
+        HIPCHK(hipMemcpyAsync(m.ext, phi_ext, bytes, hipMemcpyDeviceToDevice, p->stream));
+    else
+        HIPCHK(launch_zero(p->stream, m.ext, bytes));
+    HIPCHK(launch_tidal_correct(one(p, member), p->prec, n));
     return WDM_OK;
 }
 

@@ -119,10 +119,20 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     T phi[FP::E];
     T* gphi = static_cast<T*>(m.phi) + q * NZ;
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s) {
-        phi[s] = v[s].re;
-        if (ok) gstr(gphi, slot_elem<FP, FP::first()>(ln.t, s), phi[s]);
+    for (int s = 0; s < FP::E; ++s) phi[s] = v[s].re;
+    if constexpr (GEN) {
+        // an external potential joins the self-gravity felt by the wave and,
+        // through the stored Phi, by the particles; loaded here rather than
+        // with the other loads, so only runs that have one pay the wait
+        if (m.ext != nullptr && ok) {
+            const T* ge = static_cast<const T*>(m.ext) + q * NZ;
+#pragma unroll
+            for (int s = 0; s < FP::E; ++s) phi[s] += gldr(ge, slot_elem<FP, FP::first()>(ln.t, s));
+        }
     }
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s)
+        if (ok) gstr(gphi, slot_elem<FP, FP::first()>(ln.t, s), phi[s]);
     if constexpr (OP == kZPhiOnly) return;
     const double dt = gldr(m.dt, 0);
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
@@ -156,6 +166,9 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     using LN = Lanes<FP, T, false>;
     constexpr int PP = LN::PP;
     constexpr int H = NZ / 2;
+    constexpr bool INV = OP == kDensInvFft || OP == kDensInvToPhi;
+    constexpr bool TO_PHI = OP == kDensInvToPhi || OP == kDensDirectToPhi;
+    constexpr bool FROM_PHI = OP == kPhiR2C;
     __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     const MemberDev& m = mems[first + blockIdx.y];
@@ -165,27 +178,43 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     const bool ok = q < npen;
     load_twiddles<NZ, wg_size<FP, T>()>(tw, m.tw_z);
     cplx<T>* psi = static_cast<cplx<T>*>(m.psi);
+    T* ph = static_cast<T*>(m.phi) + q * NZ + ln.t;
     cplx<T> v[FP::E];
     // the baryon density is loaded together with psi: one memory wait per pass
     T* rb = static_cast<T*>(m.rho_b) + q * NZ + ln.t;
     T rbv[FP::E];
+    if constexpr (FROM_PHI) {
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s) rbv[s] = ok ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
-    if constexpr (OP == kDensInvFft) {
-        load_slots<IP, IP::first()>(v, psi, q * NZ, 1, ok, ln);
+        for (int s = 0; s < FP::E; ++s)
+            v[s] = cplx<T>{ok ? gldr(ph, slot_const<FP, FP::first()>(s)) : T(0), T(0)};
         __syncthreads();
-        pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
-        store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
     } else {
-        load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
-        __syncthreads();
-    }
-    // the accumulator is cleared for the next deposit; a static deposit stays
-    const bool clear = ok && !m.static_baryons;
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s) {
-        v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
-        if (clear) gstr(rb, slot_const<FP, FP::first()>(s), T(0));
+        for (int s = 0; s < FP::E; ++s)
+            rbv[s] = ok ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
+        if constexpr (INV) {
+            load_slots<IP, IP::first()>(v, psi, q * NZ, 1, ok, ln);
+            __syncthreads();
+            pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
+            store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+        } else {
+            load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+            __syncthreads();
+        }
+        // the accumulator is cleared for the next deposit; a static deposit stays
+        const bool clear = ok && !m.static_baryons;
+#pragma unroll
+        for (int s = 0; s < FP::E; ++s) {
+            v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
+            if (clear) gstr(rb, slot_const<FP, FP::first()>(s), T(0));
+        }
+        if constexpr (TO_PHI) {
+            if (ok) {
+#pragma unroll
+                for (int s = 0; s < FP::E; ++s) gstr(ph, slot_const<FP, FP::first()>(s), v[s].re);
+            }
+            return;
+        }
     }
     __syncthreads();
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
@@ -210,7 +239,7 @@ struct ZPotKick {
         const dim3 b = block<NZ, T, V>();
         if constexpr (V == 0) {
             if (op == kZPhiOnly) {
-                k_z_potential_kick<NZ, T, kZPhiOnly, kHalfKick, 0, false>
+                k_z_potential_kick<NZ, T, kZPhiOnly, kHalfKick, 0, GEN>
                     <<<grid, b, 0, L.stream>>>(L.members, L.first);
                 return hipGetLastError();
             }
@@ -236,7 +265,7 @@ struct ZPotKick {
     static hipError_t pick(const Launch& L, int nx, int ny, ZOp op, KickMode k, int var,
                            bool gen) {
         // the extended kick runs on the default plan only
-        if (gen && op != kZPhiOnly) return go<T, 0, true>(L, nx, ny, op, k);
+        if (gen) return go<T, 0, true>(L, nx, ny, op, k);
         // only the merged kick + z-FFT variant has a second plan
         if constexpr (has_variant(NZ))
             if (var == 1 && op == kZKickFft) return go<T, 1, false>(L, nx, ny, op, k);
@@ -255,10 +284,27 @@ struct ZDens {
     static hipError_t go(const Launch& L, int nx, int ny, DensOp op) {
         dim3 grid(unsigned(tiles<NZ, T, V>(int64_t(nx) * ny)), unsigned(L.count));
         const dim3 b = block<NZ, T, V>();
-        if (V == 0 && op == kDensDirect)
-            k_z_density<NZ, T, kDensDirect, 0><<<grid, b, 0, L.stream>>>(L.members, L.first);
-        else
-            k_z_density<NZ, T, kDensInvFft, V><<<grid, b, 0, L.stream>>>(L.members, L.first);
+        if constexpr (V == 0) {
+            switch (op) {
+                case kDensDirect:
+                    k_z_density<NZ, T, kDensDirect, 0><<<grid, b, 0, L.stream>>>(L.members, L.first);
+                    return hipGetLastError();
+                case kDensInvToPhi:
+                    k_z_density<NZ, T, kDensInvToPhi, 0>
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                    return hipGetLastError();
+                case kDensDirectToPhi:
+                    k_z_density<NZ, T, kDensDirectToPhi, 0>
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                    return hipGetLastError();
+                case kPhiR2C:
+                    k_z_density<NZ, T, kPhiR2C, 0><<<grid, b, 0, L.stream>>>(L.members, L.first);
+                    return hipGetLastError();
+                default:
+                    break;
+            }
+        }
+        k_z_density<NZ, T, kDensInvFft, V><<<grid, b, 0, L.stream>>>(L.members, L.first);
         return hipGetLastError();
     }
     template <typename T>

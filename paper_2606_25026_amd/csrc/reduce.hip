@@ -38,6 +38,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // what 0: sum |psi|^2 -> field 0, max |Phi| -> field 7, max |psi|^2 -> field 8,
 //         sum |psi|^4 -> field 9
 // what 1: sum (|psi|^2 + scratch) Phi -> field 2 (scratch holds CIC rho_b)
+// what 2: sum (|psi|^2 + scratch) Phi_ext -> field 10
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __restrict__ mems,
                                                              int first, int64_t n, int what) {
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __
     const int64_t b = int64_t(blockIdx.x) * chunk;
     const int64_t e = b + chunk < n ? b + chunk : n;
     const cplx<T>* psi = static_cast<const cplx<T>*>(m.psi);
-    const T* phi = static_cast<const T*>(m.phi);
+    const T* phi = static_cast<const T*>(what == 2 ? m.ext : m.phi);
     const T* rb = static_cast<const T*>(m.scratch);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int64_t i = b + threadIdx.x; i < e; i += kRedThreads) {
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_grid(const MemberDev* __
             m.partials[int64_t(blockIdx.x) * kRedFields + 9] = t3;
         }
     } else if (threadIdx.x == 0) {
-        m.partials[int64_t(blockIdx.x) * kRedFields + 2] = t0;
+        m.partials[int64_t(blockIdx.x) * kRedFields + (what == 2 ? 10 : 2)] = t0;
     }
 }
 

@@ -48,6 +48,12 @@ struct MemberDev {
     // absorbing-boundary factors of the step's dt, b_a = exp(-alpha dt g_a) at
     // the nodes: [0, nx) x, [nx, nx + ny) y, [nx + ny, nx + ny + nz) z (FP64)
     double* absorb;
+    // vacuum boundary: zero-padded (2nx, 2ny, 2nz) complex work grid and the
+    // real transform of the padded Green's function on it (null if periodic)
+    void* pad;
+    void* green;
+    // external potential, real n cells, mean acceleration removed (null if none)
+    void* ext;
     const void* tw_x;  // W_nx^m, m in [0, nx) (complex, plan precision)
     const void* tw_y;
     const void* tw_z;
@@ -78,7 +84,7 @@ struct MemberDev {
     double* results;   // [kRedFields]
 };
 
-constexpr int kRedFields = 10;
+constexpr int kRedFields = 11;
 constexpr int kRedBlocks = 1024;
 
 // Launch context shared by all launchers.
@@ -91,16 +97,22 @@ struct Launch {
 
 enum KickMode : int { kHalfKick = 0, kFullKick = 1 };
 enum ZOp : int { kZKickFft = 0, kZKickOnly = 1, kZPhiOnly = 2 };
-enum DensOp : int { kDensInvFft = 0, kDensDirect = 1 };
+// P5 operations: kDensInvFft inverse z-FFT of psi, density, R2C into the half
+// spectrum; kDensDirect the same from psi in real space; kDensInvToPhi and
+// kDensDirectToPhi stop at the density, written to Phi (the vacuum solve's
+// input); kPhiR2C R2C of Phi into the half spectrum (its output).
+enum DensOp : int {
+    kDensInvFft = 0, kDensDirect = 1, kDensInvToPhi = 2, kDensDirectToPhi = 3, kPhiR2C = 4
+};
 
 // ---- FFT passes (passes_z.hip, passes_y.hip, passes_x.hip); `prec` is 0 for complex64, 1 for complex128 ----
 bool axis_supported(int n);
 // True where the axis length has a second FFT plan (the autotuner's choice).
 bool axis_has_variant(int n);
 // P1: half spectrum -> Phi (C2R along z), then kick and optionally z-FFT.
-// `extended` selects the kick with the local self-interaction and the
-// absorbing boundary (needed when a member of the class has either; it runs
-// the default FFT plan whatever `variant` says).
+// `extended` selects the kick with the local self-interaction, the absorbing
+// boundary and the external potential (needed when a member of the class has
+// one; it runs the default FFT plan whatever `variant` says).
 hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, int nz, ZOp op,
                                    KickMode kick, int variant = 0, bool extended = false);
 // P2 / P4 on psi, P6 / P8 on the half spectrum (+ Nyquist plane).
@@ -134,6 +146,20 @@ hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos_
 hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float* pos,
                                   const float* vel);
 
+// ---- vacuum boundary and external potential (isolated.hip) ----
+// Padded grid from the density held in Phi (zero outside the nx ny nz corner).
+hipError_t launch_pad_density(const Launch& L, int prec, int64_t max_cells);
+// Green's function on the padded grid (into pad), then its transform's real
+// part into green (after the caller's forward transform of pad).
+hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells);
+hipError_t launch_green_extract(const Launch& L, int prec, int64_t max_cells);
+hipError_t launch_mul_green(const Launch& L, int prec, int64_t max_cells);
+// Phi / nz = real part of the padded grid's nx ny nz corner (the z round trip
+// into P1 restores the factor).
+hipError_t launch_unpad(const Launch& L, int prec, int64_t max_cells);
+// Remove the mean acceleration of the member's ext (one member).
+hipError_t launch_tidal_correct(const Launch& L, int prec, int64_t ncells);
+
 // ---- diagnostics (diag.hip) ----
 // Partials of K, Q, V, Px, Py, Pz, sum |psi|^2 (per 1/dV) into fields 0..6
 // over `nblocks` work-groups; finish each with launch_reduce_finish.
@@ -145,7 +171,7 @@ hipError_t launch_mass_radii(const Launch& L, int prec, int64_t ncells, const in
 
 // ---- reductions and small kernels (reduce.hip) ----
 // fields of `results`: 0 mass, 1 e_kin, 2 sum rho Phi, 3 sum v^2, 4..6 sum v,
-// 7 max |Phi|, 8 max |psi|^2, 9 sum |psi|^4
+// 7 max |Phi|, 8 max |psi|^2, 9 sum |psi|^4, 10 sum rho Phi_ext
 hipError_t launch_reduce_grid(const Launch& L, int prec, int64_t ncells, int what);
 hipError_t launch_reduce_finish(const Launch& L, int field, int nblocks, bool is_max);
 hipError_t launch_reduce_particles(const Launch& L, int64_t max_np);

@@ -15,6 +15,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libwdm.so"
 
 WDM_C64, WDM_C128 = 0, 1
 WDM_BARYON_DYNAMIC, WDM_BARYON_STATIC = 0, 1
+WDM_BOUNDARY_PERIODIC, WDM_BOUNDARY_VACUUM = 0, 1
 STATUS = {0: "WDM_OK", 1: "WDM_EINVAL", 2: "WDM_ENOMEM", 3: "WDM_EDEVICE", 4: "WDM_ESTATE",
           5: "WDM_EUNSTABLE", 6: "WDM_EUNSUPPORTED"}
 
@@ -32,7 +33,8 @@ class wdm_config(C.Structure):
                 ("n_particles", C.c_int64), ("particle_mass", C.c_double),
                 ("precision", C.c_int32), ("flags", C.c_uint32),
                 ("kappa", C.c_double), ("absorb_alpha", C.c_double), ("absorb_nb", C.c_double),
-                ("baryon_mode", C.c_int32), ("nbody_substeps", C.c_int32)]
+                ("baryon_mode", C.c_int32), ("nbody_substeps", C.c_int32),
+                ("boundary", C.c_int32), ("external_potential", C.c_int32)]
 
 
 class wdm_energy_t(C.Structure):
@@ -40,7 +42,7 @@ class wdm_energy_t(C.Structure):
                 ("e_kin_particles", C.c_double), ("e_total", C.c_double),
                 ("momentum", C.c_double * 3), ("max_abs_phi", C.c_double), ("t", C.c_double),
                 ("dt", C.c_double), ("dt_auto", C.c_double), ("e_self", C.c_double),
-                ("max_rho", C.c_double)]
+                ("max_rho", C.c_double), ("e_ext", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "momentum"}
@@ -78,6 +80,7 @@ _SIGS = {
     "wdm_potential": (C.c_int, [_vp, _i32, _vp]),
     "wdm_energy": (C.c_int, [_vp, _i32, C.POINTER(wdm_energy_t)]),
     "wdm_diagnostics": (C.c_int, [_vp, _i32, C.POINTER(C.c_int32), C.POINTER(wdm_diagnostics_t)]),
+    "wdm_set_external_potential": (C.c_int, [_vp, _i32, _vp]),
     "wdm_particles": (C.c_int, [_vp, _i32, _vp, _vp]),
     "wdm_fft3d": (C.c_int, [_vp, _i32, _i32]),
     "wdm_set_sort_interval": (C.c_int, [_vp, _i32]),
@@ -155,12 +158,14 @@ def _cfg_array(configs):
 
 def make_config(n, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0, particle_mass=0.0,
                 precision=WDM_C64, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0,
-                baryon_mode=0, nbody_substeps=1) -> wdm_config:
+                baryon_mode=0, nbody_substeps=1, boundary=0,
+                external_potential=0) -> wdm_config:
     nx, ny, nz = (n, n, n) if isinstance(n, int) else n
     lx, ly, lz = (L, L, L) if isinstance(L, (int, float)) else L
     return wdm_config(nx, ny, nz, lx, ly, lz, hbar_over_m, four_pi_G, int(n_particles),
                       float(particle_mass), precision, 0, float(kappa), float(absorb_alpha),
-                      float(absorb_nb), int(baryon_mode), int(nbody_substeps))
+                      float(absorb_nb), int(baryon_mode), int(nbody_substeps), int(boundary),
+                      int(external_potential))
 
 
 # ---- entry points --------------------------------------------------------
@@ -213,6 +218,10 @@ def wdm_energy(plan, member=0) -> dict:
     e = wdm_energy_t()
     _check(load().wdm_energy(plan, member, C.byref(e)))
     return e.as_dict()
+
+
+def wdm_set_external_potential(plan, member, phi_ext):
+    _check(load().wdm_set_external_potential(plan, member, _ptr(phi_ext)))
 
 
 def wdm_diagnostics(plan, member=0, centre=None) -> dict:
