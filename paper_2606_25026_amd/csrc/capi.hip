@@ -338,13 +338,18 @@ hipError_t enqueue_vacuum_poisson(wdm_plan* p, hipStream_t s, int first, int cou
     hipError_t e = timed_on(p, s, kKZDens,
                             [&] { return launch_z_density(L, prec, nx, ny, nz, op); });
     if (e != hipSuccess) return e;
+    // Only the x < nx half of the padded grid is ever written: the forward z
+    // and y transforms would see zeros in every pencil with x >= nx, and the
+    // inverse y and z results there are not needed, so those four passes
+    // cover the lower half; the x pass reads and writes that half only, with
+    // the zeros of the other half implied (it stays zero from plan creation).
     e = timed_on(p, s, kKVacuum, [&] {
         hipError_t r = launch_pad_density(L, prec, cells);
-        for (int axis = 2; axis >= 0 && r == hipSuccess; --axis)
-            r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, axis, false, 0);
-        if (r == hipSuccess) r = launch_mul_green(L, prec, cells);
-        for (int axis = 0; axis < 3 && r == hipSuccess; ++axis)
-            r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, axis, true, 0);
+        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 2, false, 0, true);
+        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 1, false, 0, true);
+        if (r == hipSuccess) r = launch_x_mul_green(LP, prec, 2 * nx, 2 * ny, 2 * nz);
+        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 1, true, 0, true);
+        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 2, true, 0, true);
         if (r == hipSuccess) r = launch_unpad(L, prec, cells);
         return r;
     });
@@ -367,6 +372,11 @@ hipError_t compute_green(wdm_plan* p) {
                 hipSuccess)
                 return e;
         if ((e = launch_green_extract(L, p->prec, cells)) != hipSuccess) return e;
+        // the solves never write the x >= nx half of the padded grid again
+        for (int d = c.first; d < c.first + c.count; ++d)
+            if ((e = launch_zero(p->stream, p->host[d].pad,
+                                 size_t(8 * cells) * (p->prec ? 16 : 8))) != hipSuccess)
+                return e;
     }
     return e;
 }

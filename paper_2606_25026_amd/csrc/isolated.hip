@@ -6,8 +6,9 @@
 // zero-padded to (2 nx, 2 ny, 2 nz): the density is copied into the padded
 // grid's corner, transformed, multiplied by the transform of the padded Green's
 // function (real and even, computed once per plan) and transformed back; the
-// corner is the potential.  The plain axis transforms run on the padded grid
-// through a second member table whose entries describe it.
+// corner is the potential.  The axis transforms run on the padded grid through
+// a second member table whose entries describe it; the x pass multiplies by
+// the Green's function between its forward and inverse transforms.
 #include "wdm_internal.hpp"
 #include "fft_device.hpp"
 
@@ -31,11 +32,13 @@ __device__ __forceinline__ bool corner_index(const MemberDev& m, int64_t q, int6
     return true;
 }
 
+// The x < nx half of the padded grid from the density held in Phi (zeros
+// outside the nx ny nz corner); the other half stays zero from plan creation.
 template <typename T>
 __global__ __launch_bounds__(kIsoThreads) void k_pad_density(const MemberDev* __restrict__ mems,
                                                              int first) {
     const MemberDev& m = mems[first + blockIdx.y];
-    const int64_t total = 8 * int64_t(m.nx) * m.ny * m.nz;
+    const int64_t total = 4 * int64_t(m.nx) * m.ny * m.nz;
     cplx<T>* pad = static_cast<cplx<T>*>(m.pad);
     const T* rho = static_cast<const T*>(m.phi);
     for (int64_t q = int64_t(blockIdx.x) * kIsoThreads + threadIdx.x; q < total;
@@ -91,21 +94,6 @@ __global__ __launch_bounds__(kIsoThreads) void k_green_extract(const MemberDev* 
     for (int64_t q = int64_t(blockIdx.x) * kIsoThreads + threadIdx.x; q < total;
          q += int64_t(gridDim.x) * kIsoThreads)
         gstr(green, q, T(double(gld(pad, q).re) * scale));
-}
-
-template <typename T>
-__global__ __launch_bounds__(kIsoThreads) void k_mul_green(const MemberDev* __restrict__ mems,
-                                                           int first) {
-    const MemberDev& m = mems[first + blockIdx.y];
-    const int64_t total = 8 * int64_t(m.nx) * m.ny * m.nz;
-    cplx<T>* pad = static_cast<cplx<T>*>(m.pad);
-    const T* green = static_cast<const T*>(m.green);
-    for (int64_t q = int64_t(blockIdx.x) * kIsoThreads + threadIdx.x; q < total;
-         q += int64_t(gridDim.x) * kIsoThreads) {
-        const T g = gldr(green, q);
-        const cplx<T> v = gld(pad, q);
-        gst(pad, q, cplx<T>{v.re * g, v.im * g});
-    }
 }
 
 template <typename T>
@@ -192,16 +180,13 @@ __global__ __launch_bounds__(kIsoThreads) void k_tidal_apply(const MemberDev* __
     } while (0)
 
 hipError_t launch_pad_density(const Launch& L, int prec, int64_t max_cells) {
-    WDM_ISO_LAUNCH(k_pad_density, 8 * max_cells);
+    WDM_ISO_LAUNCH(k_pad_density, 4 * max_cells);
 }
 hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_green_fill, 8 * max_cells);
 }
 hipError_t launch_green_extract(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_green_extract, 8 * max_cells);
-}
-hipError_t launch_mul_green(const Launch& L, int prec, int64_t max_cells) {
-    WDM_ISO_LAUNCH(k_mul_green, 8 * max_cells);
 }
 hipError_t launch_unpad(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_unpad, max_cells);

@@ -124,6 +124,52 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
 }
 
 
+// Vacuum-boundary convolution, x pass on the zero-padded grid (a padded
+// member descriptor: lengths 2n, psi = the padded grid): x forward transform,
+// multiplication by the stored real transform of the padded Green's function
+// (same [x][y][z] layout), x inverse transform, in one pass as P7 does.  Only
+// the x < NX/2 half is read (the padding half holds zeros and is never
+// written) and only that half of the result, the one the potential needs, is
+// stored.
+template <int NX, typename T>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_mul_green(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<NX>::type;
+    using IP = Reversed<FP>;
+    using LN = Lanes<FP, T, true>;
+    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ cplx<T> tw[tw_entries<T>(NX)];
+    const MemberDev& m = mems[first + blockIdx.y];
+    load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
+    __syncthreads();
+    const LN ln;
+    const int64_t plane = int64_t(m.ny) * m.nz;
+    const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
+    const bool ok = q < plane;
+    cplx<T>* lane = static_cast<cplx<T>*>(m.psi) + (q + int64_t(ln.t) * plane);
+    const T* green = static_cast<const T*>(m.green) + q;
+    constexpr int HALF = NX / 2;
+    cplx<T> v[FP::E];
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s)
+        v[s] = (ok && slot_elem<FP, FP::first()>(ln.t, s) < HALF)
+                   ? gld(lane, int64_t(slot_const<FP, FP::first()>(s)) * plane)
+                   : cplx<T>{T(0), T(0)};
+    pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s) {
+        const int64_t e = slot_elem<FP, FP::last()>(ln.t, s);
+        v[s] = cscale(v[s], ok ? gldr(green, e * plane) : T(0));
+    }
+    __syncthreads();
+    pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
+    if (!ok) return;
+#pragma unroll
+    for (int s = 0; s < FP::E; ++s)
+        if (slot_elem<IP, IP::last()>(ln.t, s) < HALF)
+            gst(lane, int64_t(slot_const<IP, IP::last()>(s)) * plane, v[s]);
+}
+
 template <int NX, typename T>
 __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_kinetic_energy(
     const MemberDev* __restrict__ mems, int first) {
@@ -214,6 +260,23 @@ struct XKinE {
         return prec ? go<double>(L, ny, nz) : go<float>(L, ny, nz);
     }
 };
+
+template <int NX>
+struct XMulGreen {
+    template <typename T>
+    static hipError_t go(const Launch& L, int ny, int nz) {
+        dim3 grid(unsigned(tiles<NX, T>(int64_t(ny) * nz)), unsigned(L.count));
+        k_x_mul_green<NX, T><<<grid, block<NX, T>(), 0, L.stream>>>(L.members, L.first);
+        return hipGetLastError();
+    }
+    static hipError_t run(const Launch& L, int prec, int ny, int nz) {
+        return prec ? go<double>(L, ny, nz) : go<float>(L, ny, nz);
+    }
+};
+
+hipError_t launch_x_mul_green(const Launch& L, int prec, int nx, int ny, int nz) {
+    return dispatch_n<XMulGreen>(nx, L, prec, ny, nz);
+}
 
 hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz, int variant) {
     return dispatch_n<XKin>(nx, L, prec, ny, nz, variant);

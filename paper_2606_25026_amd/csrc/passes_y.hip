@@ -143,10 +143,13 @@ hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, 
     return dispatch_n<YFft>(ny, L, prec, nx, nz, inverse, true, variant);
 }
 hipError_t launch_axis_fft(const Launch& L, int prec, int nx, int ny, int nz, int axis,
-                           bool inverse, int which) {
+                           bool inverse, int which, bool lower_x_half) {
     const int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
-    const int64_t pencils = axis == 0 ? int64_t(ny) * nz
-                                      : (axis == 1 ? int64_t(nx) * nz : int64_t(nx) * ny);
+    int64_t pencils = axis == 0 ? int64_t(ny) * nz
+                                : (axis == 1 ? int64_t(nx) * nz : int64_t(nx) * ny);
+    // y and z pencils are numbered with x outermost: the first half are those
+    // with x < nx / 2 (launching fewer tiles; each tile checks the full count)
+    if (lower_x_half && axis != 0) pencils /= 2;
     return dispatch_n<AxisFft>(n, L, prec, pencils, axis, inverse, which);
 }
 
