@@ -334,7 +334,6 @@ hipError_t enqueue_vacuum_poisson(wdm_plan* p, hipStream_t s, int first, int cou
     const int prec = p->prec;
     const Launch L{s, p->table, first, count};
     const Launch LP{s, p->iso_table, first, count};
-    const int64_t cells = int64_t(nx) * ny * nz;
     hipError_t e = timed_on(p, s, kKZDens,
                             [&] { return launch_z_density(L, prec, nx, ny, nz, op); });
     if (e != hipSuccess) return e;
@@ -344,13 +343,13 @@ hipError_t enqueue_vacuum_poisson(wdm_plan* p, hipStream_t s, int first, int cou
     // cover the lower half; the x pass reads and writes that half only, with
     // the zeros of the other half implied (it stays zero from plan creation).
     e = timed_on(p, s, kKVacuum, [&] {
-        hipError_t r = launch_pad_density(L, prec, cells);
+        hipError_t r = launch_pad_density(L, prec, nx, ny);
         if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 2, false, 0, true);
         if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 1, false, 0, true);
         if (r == hipSuccess) r = launch_x_mul_green(LP, prec, 2 * nx, 2 * ny, 2 * nz);
         if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 1, true, 0, true);
         if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 2, true, 0, true);
-        if (r == hipSuccess) r = launch_unpad(L, prec, cells);
+        if (r == hipSuccess) r = launch_unpad(L, prec, nx, ny);
         return r;
     });
     if (e != hipSuccess) return e;

@@ -21,31 +21,26 @@ static unsigned iso_grid(int64_t count) {
     return unsigned(g < 8192 ? g : 8192);
 }
 
-// Padded element q of member m: its corner coordinates (i, j, k), or false
-// outside the nx ny nz corner.
-__device__ __forceinline__ bool corner_index(const MemberDev& m, int64_t q, int64_t& cell) {
-    const int64_t pz = 2 * int64_t(m.nz), pyz = 2 * int64_t(m.ny) * pz;
-    const int64_t i = q / pyz, r = q - i * pyz;
-    const int64_t j = r / pz, k = r - j * pz;
-    if (i >= m.nx || j >= m.ny || k >= m.nz) return false;
-    cell = (i * m.ny + j) * m.nz + k;
-    return true;
-}
-
 // The x < nx half of the padded grid from the density held in Phi (zeros
 // outside the nx ny nz corner); the other half stays zero from plan creation.
+// One work-group per padded z row (x < nx), its threads along z.
 template <typename T>
 __global__ __launch_bounds__(kIsoThreads) void k_pad_density(const MemberDev* __restrict__ mems,
                                                              int first) {
     const MemberDev& m = mems[first + blockIdx.y];
-    const int64_t total = 4 * int64_t(m.nx) * m.ny * m.nz;
+    const int pny = 2 * m.ny, pnz = 2 * m.nz;
+    const int rows = m.nx * pny;
     cplx<T>* pad = static_cast<cplx<T>*>(m.pad);
     const T* rho = static_cast<const T*>(m.phi);
-    for (int64_t q = int64_t(blockIdx.x) * kIsoThreads + threadIdx.x; q < total;
-         q += int64_t(gridDim.x) * kIsoThreads) {
-        int64_t cell;
-        const T v = corner_index(m, q, cell) ? gldr(rho, cell) : T(0);
-        gst(pad, q, cplx<T>{v, T(0)});
+    for (int r = int(blockIdx.x); r < rows; r += int(gridDim.x)) {
+        const int i = r / pny, j = r - i * pny;
+        cplx<T>* row = pad + int64_t(r) * pnz;
+        const bool inside = j < m.ny;
+        const T* src = rho + (int64_t(i) * m.ny + (inside ? j : 0)) * m.nz;
+        for (int k = int(threadIdx.x); k < pnz; k += kIsoThreads) {
+            const T v = (inside && k < m.nz) ? gldr(src, k) : T(0);
+            gst(row, k, cplx<T>{v, T(0)});
+        }
     }
 }
 
@@ -96,19 +91,20 @@ __global__ __launch_bounds__(kIsoThreads) void k_green_extract(const MemberDev* 
         gstr(green, q, T(double(gld(pad, q).re) * scale));
 }
 
+// Phi / nz from the corner of the padded grid; one work-group per z row.
 template <typename T>
 __global__ __launch_bounds__(kIsoThreads) void k_unpad(const MemberDev* __restrict__ mems,
                                                        int first) {
     const MemberDev& m = mems[first + blockIdx.y];
-    const int64_t nyz = int64_t(m.ny) * m.nz, n = int64_t(m.nx) * nyz;
-    const int64_t pz = 2 * int64_t(m.nz), pyz = 2 * int64_t(m.ny) * pz;
+    const int rows = m.nx * m.ny;
+    const int pny = 2 * m.ny, pnz = 2 * m.nz;
     const cplx<T>* pad = static_cast<const cplx<T>*>(m.pad);
     T* phi = static_cast<T*>(m.phi);
-    for (int64_t c = int64_t(blockIdx.x) * kIsoThreads + threadIdx.x; c < n;
-         c += int64_t(gridDim.x) * kIsoThreads) {
-        const int64_t i = c / nyz, r = c - i * nyz;
-        const int64_t j = r / m.nz, k = r - j * m.nz;
-        gstr(phi, c, gld(pad, i * pyz + j * pz + k).re);
+    for (int r = int(blockIdx.x); r < rows; r += int(gridDim.x)) {
+        const int i = r / m.ny, j = r - i * m.ny;
+        const cplx<T>* src = pad + (int64_t(i) * pny + j) * pnz;
+        T* dst = phi + int64_t(r) * m.nz;
+        for (int k = int(threadIdx.x); k < m.nz; k += kIsoThreads) gstr(dst, k, gld(src, k).re);
     }
 }
 
@@ -179,8 +175,25 @@ __global__ __launch_bounds__(kIsoThreads) void k_tidal_apply(const MemberDev* __
         return hipGetLastError();                                                          \
     } while (0)
 
-hipError_t launch_pad_density(const Launch& L, int prec, int64_t max_cells) {
-    WDM_ISO_LAUNCH(k_pad_density, 4 * max_cells);
+// one work-group per z row: padded rows of the lower half, or corner rows
+static hipError_t launch_rows(const Launch& L, int prec, int64_t rows, bool pad) {
+    const dim3 grid(unsigned(rows < 65536 ? rows : 65536), unsigned(L.count));
+    if (pad) {
+        if (prec)
+            k_pad_density<double><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
+        else
+            k_pad_density<float><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
+    } else {
+        if (prec)
+            k_unpad<double><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
+        else
+            k_unpad<float><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_density(const Launch& L, int prec, int nx, int ny) {
+    return launch_rows(L, prec, int64_t(nx) * 2 * ny, true);
 }
 hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_green_fill, 8 * max_cells);
@@ -188,8 +201,8 @@ hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells) {
 hipError_t launch_green_extract(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_green_extract, 8 * max_cells);
 }
-hipError_t launch_unpad(const Launch& L, int prec, int64_t max_cells) {
-    WDM_ISO_LAUNCH(k_unpad, max_cells);
+hipError_t launch_unpad(const Launch& L, int prec, int nx, int ny) {
+    return launch_rows(L, prec, int64_t(nx) * ny, false);
 }
 #undef WDM_ISO_LAUNCH
 

@@ -143,31 +143,33 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
     __syncthreads();
     const LN ln;
-    const int64_t plane = int64_t(m.ny) * m.nz;
-    const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
+    // element offsets fit 32 bits: at most 512 * 512 * 512 per padded grid
+    const int plane = m.ny * m.nz;
+    const int q = int(blockIdx.x) * LN::PP + ln.p;
     const bool ok = q < plane;
-    cplx<T>* lane = static_cast<cplx<T>*>(m.psi) + (q + int64_t(ln.t) * plane);
+    cplx<T>* lane = static_cast<cplx<T>*>(m.psi) + q;
     const T* green = static_cast<const T*>(m.green) + q;
     constexpr int HALF = NX / 2;
+    // the Green's factors of this lane's output slots are loaded with the data
+    T gv[FP::E];
     cplx<T> v[FP::E];
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s)
-        v[s] = (ok && slot_elem<FP, FP::first()>(ln.t, s) < HALF)
-                   ? gld(lane, int64_t(slot_const<FP, FP::first()>(s)) * plane)
-                   : cplx<T>{T(0), T(0)};
+    for (int s = 0; s < FP::E; ++s) {
+        const int ein = slot_elem<FP, FP::first()>(ln.t, s);
+        v[s] = (ok && ein < HALF) ? gld(lane, ein * plane) : cplx<T>{T(0), T(0)};
+        gv[s] = ok ? gldr(green, slot_elem<FP, FP::last()>(ln.t, s) * plane) : T(0);
+    }
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s) {
-        const int64_t e = slot_elem<FP, FP::last()>(ln.t, s);
-        v[s] = cscale(v[s], ok ? gldr(green, e * plane) : T(0));
-    }
+    for (int s = 0; s < FP::E; ++s) v[s] = cscale(v[s], gv[s]);
     __syncthreads();
     pencil_fft<IP, true, T>(v, lds, tw, ln.t, ln);
     if (!ok) return;
 #pragma unroll
-    for (int s = 0; s < FP::E; ++s)
-        if (slot_elem<IP, IP::last()>(ln.t, s) < HALF)
-            gst(lane, int64_t(slot_const<IP, IP::last()>(s)) * plane, v[s]);
+    for (int s = 0; s < FP::E; ++s) {
+        const int eout = slot_elem<IP, IP::last()>(ln.t, s);
+        if (eout < HALF) gst(lane, eout * plane, v[s]);
+    }
 }
 
 template <int NX, typename T>

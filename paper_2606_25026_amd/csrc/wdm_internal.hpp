@@ -150,7 +150,7 @@ hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float
 // ---- vacuum boundary and external potential (isolated.hip) ----
 // The x < nx half of the padded grid from the density held in Phi (zero
 // outside the nx ny nz corner); the x >= nx half must hold zeros.
-hipError_t launch_pad_density(const Launch& L, int prec, int64_t max_cells);
+hipError_t launch_pad_density(const Launch& L, int prec, int nx, int ny);
 // Green's function on the padded grid (into pad), then its transform's real
 // part into green (after the caller's forward transform of pad).
 hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells);
@@ -160,7 +160,7 @@ hipError_t launch_green_extract(const Launch& L, int prec, int64_t max_cells);
 hipError_t launch_x_mul_green(const Launch& L, int prec, int nx, int ny, int nz);
 // Phi / nz = real part of the padded grid's nx ny nz corner (the z round trip
 // into P1 restores the factor).
-hipError_t launch_unpad(const Launch& L, int prec, int64_t max_cells);
+hipError_t launch_unpad(const Launch& L, int prec, int nx, int ny);
 // Remove the mean acceleration of the member's ext (one member).
 hipError_t launch_tidal_correct(const Launch& L, int prec, int64_t ncells);
 
