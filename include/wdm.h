@@ -12,6 +12,11 @@
  * with the periodic FFT Poisson solver of Sec. 3.2.1 and the dynamic baryon
  * mode of Sec. 3.2.2 (particles feed rho_b through a cloud-in-cell deposit and
  * feel -grad Phi, central differences of Sec. 3.1, CIC-interpolated).
+ * Optional, per member (wdm_config): a local self-interaction kappa |psi|^2
+ * and an absorbing boundary (Sec. 2.2, 3.1), static baryons and particle
+ * sub-steps (Sec. 3.2.2), the vacuum gravity boundary (Sec. 3.2.1) and an
+ * external tidal potential (Sec. 4.3); wdm_diagnostics gives the paper's halo
+ * diagnostics (Sec. 3.6, App. A.1).
  *
  * Conventions shared by every entry point:
  *  - Grids are C-ordered [nx][ny][nz] with z contiguous; node i sits at
@@ -25,8 +30,9 @@
  *    and keeps no reference to them afterwards.  Host pointers are noted.
  *  - All device memory the plan needs lives in one caller-provided workspace
  *    (wdm_workspace_bytes); the library never allocates device memory.
- *  - Every call is ordered on the plan's HIP stream.  Only wdm_energy,
- *    wdm_profile_read and wdm_copy_bandwidth synchronise with the host.
+ *  - Every call is ordered on the plan's HIP stream.  Only wdm_plan_create,
+ *    wdm_energy, wdm_diagnostics, wdm_autotune, wdm_profile_read and
+ *    wdm_copy_bandwidth synchronise with the host.
  *  - On an error nothing is launched, the plan keeps its state and
  *    wdm_last_error() describes the failure (thread-local string).
  *  - A plan is not thread safe; distinct plans are independent.
@@ -55,10 +61,10 @@ typedef enum {
 
 typedef enum { WDM_C64 = 0, WDM_C128 = 1 } wdm_precision;
 
-/* One periodic box (an ensemble has several). */
 enum { WDM_BARYON_DYNAMIC = 0, WDM_BARYON_STATIC = 1 };
 enum { WDM_BOUNDARY_PERIODIC = 0, WDM_BOUNDARY_VACUUM = 1 };
 
+/* One box (an ensemble has several). */
 typedef struct {
     int32_t nx, ny, nz;        /* each in {16,32,64,96,128,192,256,384,512} */
     double lx, ly, lz;         /* box lengths; dx = lx / nx */
