@@ -324,7 +324,7 @@ def main():
     else:
         tuning = wdm.autotune(h, cfg, reps=10)
     if args.tidal != 0.0:
-        x = (torch.arange(args.n, dtype=torch.float32, device=dev) + 0.5 - 0.5) / args.n - 0.5
+        x = torch.arange(args.n, dtype=torch.float32, device=dev) / args.n - 0.5
         X, Y, Z = torch.meshgrid(x, x, x, indexing="ij")
         ext = (0.5 * args.tidal * (X * X + Y * Y - 2 * Z * Z)).contiguous()
         wdm.wdm_set_external_potential(h, 0, ext)
