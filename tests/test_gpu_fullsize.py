@@ -12,7 +12,7 @@ from paper_2606_25026_amd import inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-GOLDEN = Path(__file__).resolve().parent / "golden" / "coupled_halo_256_steps100.npz"
+GOLDEN_DIR = Path(__file__).resolve().parent / "golden"
 
 
 def periodic_diff(a, b, L=1.0):
@@ -25,14 +25,12 @@ def halo():
     return inputs.coupled_halo(n=256, n_particles=1_000_000, seed=0)
 
 
-@pytest.mark.parametrize("plans", ["default", "second"])
-@pytest.mark.parametrize("sort_interval", [32])
-def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval, plans):
-    g = np.load(GOLDEN)
-    wl = halo
+def run_vs_golden(wdm, wl, steps, plans, sort_interval=32):
+    """Run the benchmark's configuration for the golden file's steps; errors."""
+    g = np.load(GOLDEN_DIR / f"coupled_halo_256_steps{steps}.npz")
     # the generator must reproduce the stored initial samples
     assert np.max(np.abs(wl.psi.ravel()[g["cells"]] - g["psi0"])) < 1e-12
-    steps = int(g["steps"])
+    assert int(g["steps"]) == steps
     cfg = wdm.make_config(256, n_particles=wl.n_particles, particle_mass=wl.particle_mass)
     plan = wdm.Plan(cfg)
     if plans == "second":     # every tunable pass on its second FFT plan
@@ -51,18 +49,38 @@ def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, sort_interval, plans):
     wdm.wdm_particles(plan.handle, 0, p, v)
     e1 = wdm.wdm_energy(plan.handle, 0)
     torch.cuda.synchronize()
+    plan.close()
     got = out.cpu().numpy().ravel()[g["cells"]].astype(np.complex128)
     ref = g["psi"]
-    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    pp = p.cpu().numpy()[g["parts"]].astype(np.float64)
-    vv = v.cpu().numpy()[g["parts"]].astype(np.float64)
-    perr = float(np.max(np.abs(periodic_diff(pp, g["pos"]))))
-    verr = float(np.linalg.norm(vv - g["vel"]) / np.linalg.norm(g["vel"]))
-    print(f"[{plans} plans] 256^3 + 1e6 particles, {steps} steps: psi rel L2 (65536 samples) {err:.3e}, "
-          f"max |dx| {perr:.2e}, vel rel L2 {verr:.2e}, mass drift {e1['mass'] / e0['mass'] - 1:.2e}")
-    assert err < 1e-5
-    assert perr < 1e-5
-    assert verr < 1e-4
-    assert abs(e1["mass"] / e0["mass"] - 1) < 1e-6
-    assert e1["mass"] == pytest.approx(float(g["mass"]), rel=1e-6)
-    plan.close()
+    res = {
+        "err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+        "perr": float(np.max(np.abs(periodic_diff(p.cpu().numpy()[g["parts"]].astype(np.float64),
+                                                  g["pos"])))),
+        "verr": float(np.linalg.norm(v.cpu().numpy()[g["parts"]].astype(np.float64) - g["vel"]) /
+                      np.linalg.norm(g["vel"])),
+        "drift": e1["mass"] / e0["mass"] - 1,
+        "mass": e1["mass"], "mass_ref": float(g["mass"]),
+    }
+    print(f"[{plans} plans] 256^3 + 1e6 particles, {steps} steps: psi rel L2 (65536 samples) "
+          f"{res['err']:.3e}, max |dx| {res['perr']:.2e}, vel rel L2 {res['verr']:.2e}, "
+          f"mass drift {res['drift']:.2e}")
+    return res
+
+
+@pytest.mark.parametrize("plans", ["default", "second"])
+def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, plans):
+    r = run_vs_golden(wdm, halo, 100, plans)
+    assert r["err"] < 1e-5
+    assert r["perr"] < 1e-5
+    assert r["verr"] < 1e-4
+    assert abs(r["drift"]) < 1e-6
+    assert r["mass"] == pytest.approx(r["mass_ref"], rel=1e-6)
+
+
+def test_coupled_halo_256_1000_steps_reported(wdm, halo):
+    # the gate is 100 steps; over 1000 steps the complex64 rounding keeps
+    # accumulating, so this run reports its error and holds it to a loose bound
+    r = run_vs_golden(wdm, halo, 1000, "default")
+    assert r["err"] < 1e-3
+    assert r["perr"] < 1e-4
+    assert abs(r["drift"]) < 1e-5
