@@ -336,6 +336,70 @@ __device__ __forceinline__ void stockham_level(cplx<T>* v, cplx<T>* lds, const c
     }
 }
 
+// stockham_level with the LDS exchange split in two: the real parts move
+// through a buffer of one real value per pencil element, then the imaginary
+// parts through the same buffer.  Half the LDS of the complex exchange, for
+// two more barriers per level; a lane's imaginary parts stay in its registers
+// while the real parts are exchanged.
+template <class P, int LVL, bool INV, typename T, class Idx>
+__device__ __forceinline__ void stockham_level_split(cplx<T>* v, T* lds, const cplx<T>* tw,
+                                                     int t, Idx idx) {
+    constexpr int R = P::radix[LVL];
+    constexpr int Ns = P::stride_before(LVL);
+    constexpr int NB = P::E / R;
+    constexpr int N = P::N;
+    if constexpr (LVL > 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = t + P::T * b;
+            const int jm = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int m = jm * r * (N / (Ns * R));
+                const cplx<T> x = v[b * R + r];
+                if constexpr (std::is_same<T, float>::value) {
+                    const cplx<T> h = tw[m], l = tw[N + m];
+                    v[b * R + r] = INV ? cmul_split(x, conj(h), conj(l)) : cmul_split(x, h, l);
+                } else {
+                    v[b * R + r] = INV ? cmulc(x, tw[m]) : cmul(x, tw[m]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dft<R, INV, T>(v + b * R);
+    if constexpr (LVL + 1 < P::L) {
+        constexpr int R2 = P::radix[LVL + 1];
+        constexpr int NB2 = P::E / R2;
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = t + P::T * b;
+                const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    lds[idx(base + r * Ns)] = part ? v[b * R + r].im : v[b * R + r].re;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < NB2; ++b) {
+                const int j = t + P::T * b;
+#pragma unroll
+                for (int r = 0; r < R2; ++r) {
+                    const T x = lds[idx(j + r * (N / R2))];
+                    if (part)
+                        v[b * R2 + r].im = x;
+                    else
+                        v[b * R2 + r].re = x;
+                }
+            }
+            __syncthreads();
+        }
+        stockham_level_split<P, LVL + 1, INV, T>(v, lds, tw, t, idx);
+    }
+}
+
 // Twiddle entries per table: complex64 keeps W_N^m as hi (first N entries) and
 // lo (next N) floats; complex128 keeps one double table.
 template <typename T>
@@ -351,6 +415,15 @@ __device__ __forceinline__ void pencil_fft(cplx<T>* v, cplx<T>* lds, const cplx<
                                            Idx idx) {
     static_assert(P::valid(), "invalid FFT plan");
     stockham_level<P, 0, INV, T>(v, lds, tw, t, idx);
+}
+
+// The same transform with the split exchange (one real LDS value per pencil
+// element).  Ends with every LDS read done (the last exchange's barrier).
+template <class P, bool INV, typename T, class Idx>
+__device__ __forceinline__ void pencil_fft(cplx<T>* v, T* lds, const cplx<T>* tw, int t,
+                                           Idx idx) {
+    static_assert(P::valid(), "invalid FFT plan");
+    stockham_level_split<P, 0, INV, T>(v, lds, tw, t, idx);
 }
 
 }  // namespace wdm

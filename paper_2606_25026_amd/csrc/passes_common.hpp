@@ -77,7 +77,8 @@ constexpr int wg_size() {
 }
 template <class P, typename T, bool STRIDED>
 constexpr int lds_entries() {
-    // strided layout: N * PP entries; contiguous layout: PP * (N + N/16)
+    // strided layout: N * PP entries; contiguous layout: PP * (N + N/16).  The
+    // passes exchange real and imaginary parts in turn, one real per entry.
     return pencils_per_wg<P, T>() * (STRIDED ? P::N : P::N + P::N / 16);
 }
 
@@ -268,7 +269,7 @@ struct Strides {
 // Plain transform of one batch of pencils.
 template <class P, typename T, bool INV, bool STRIDED>
 __device__ __forceinline__ void transform_tile(cplx<T>* data, const Strides& sd, int64_t tile,
-                                               cplx<T>* lds, const cplx<T>* tw) {
+                                               T* lds, const cplx<T>* tw) {
     using LN = Lanes<P, T, STRIDED>;
     const LN ln;
     const int64_t q = tile * LN::PP + ln.p;

@@ -18,7 +18,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
     using LN = Lanes<FP, T, true>;
     constexpr int WG = wg_size<FP, T>();
     constexpr bool kSplit = std::is_same<T, float>::value;
-    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ T lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ cplx<double> ex[NX];   // e_x in FP64
     const MemberDev& m = mems[first + blockIdx.y];
@@ -84,7 +84,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
     using FP = typename PlanFor<NX, V>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
-    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ T lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double kx2[NX];
     const MemberDev& m = mems[first + blockIdx.y];
@@ -137,7 +137,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     using FP = typename PlanFor<NX>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
-    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ T lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<NX, wg_size<FP, T>()>(tw, m.tw_x);
@@ -178,7 +178,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     using FP = typename PlanFor<NX>::type;
     using LN = Lanes<FP, T, true>;
     constexpr int WG = wg_size<FP, T>();
-    __shared__ cplx<T> lds[lds_entries<FP, T, true>()];
+    __shared__ T lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double red[WG];
     const MemberDev& m = mems[first + blockIdx.y];

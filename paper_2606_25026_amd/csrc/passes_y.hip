@@ -20,7 +20,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY, V>::type, T>())) void
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NY, V>::type;
     constexpr int PP = pencils_per_wg<FP, T>();
-    __shared__ cplx<T> lds[lds_entries<FP, T, !SPEC>()];
+    __shared__ T lds[lds_entries<FP, T, !SPEC>()];
     __shared__ cplx<T> tw[tw_entries<T>(NY)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<NY, wg_size<FP, T>()>(tw, m.tw_y);
@@ -51,7 +51,7 @@ template <int N, typename T, bool INV, int AXIS>
 __global__ __launch_bounds__((wg_size<typename PlanFor<N>::type, T>())) void k_axis_fft(
     const MemberDev* __restrict__ mems, int first, int which) {
     using FP = typename PlanFor<N>::type;
-    __shared__ cplx<T> lds[lds_entries<FP, T, false>()];
+    __shared__ T lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(N)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<N, wg_size<FP, T>()>(tw, AXIS == 0 ? m.tw_x : (AXIS == 1 ? m.tw_y : m.tw_z));
