@@ -25,7 +25,7 @@ def halo():
     return inputs.coupled_halo(n=256, n_particles=1_000_000, seed=0)
 
 
-def run_vs_golden(wdm, wl, steps, plans, sort_interval=32):
+def run_vs_golden(wdm, wl, steps, plans, sort_interval=128):
     """Run the benchmark's configuration for the golden file's steps; errors."""
     g = np.load(GOLDEN_DIR / f"coupled_halo_256_steps{steps}.npz")
     # the generator must reproduce the stored initial samples
