@@ -82,6 +82,19 @@ constexpr int lds_entries() {
     return pencils_per_wg<P, T>() * (STRIDED ? P::N : P::N + P::N / 16);
 }
 
+// Whether a pass exchanges real and imaginary parts in turn (one real LDS
+// entry per element) or whole complex values.  The split halves the LDS and,
+// for the strided passes and the two-level plans, also lowers the register
+// count; along the contiguous axis the three-level plans (96, 192, 384, 512)
+// need more registers with it (P1 at 512: 114 -> 131, 3 waves per SIMD, 628
+// -> 1125 us a pass), so they keep the complex exchange.
+template <class P, bool STRIDED>
+constexpr bool split_exchange() {
+    return STRIDED || P::L <= 2;
+}
+template <class P, typename T, bool STRIDED>
+using lds_t = std::conditional_t<split_exchange<P, STRIDED>(), T, cplx<T>>;
+
 // Lane coordinates and LDS addressing for the two pencil mappings.
 //   strided:    neighbouring lanes take neighbouring pencils (rows in memory
 //               run across pencils), LDS slot e * PP + p

@@ -76,8 +76,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     // the closing kick and the merged kick end a step: the absorbing boundary
     // follows them; the opening kick has none before it
     constexpr bool MASK = GEN && (OP == kZKickOnly || KICK == kFullKick);
-    // the transforms exchange real and imaginary parts in turn (half the LDS)
-    __shared__ T lds[lds_entries<FP, T, false>()];
+    // real entries for a split exchange, complex ones otherwise
+    __shared__ lds_t<FP, T, false> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     __shared__ double bz[MASK ? NZ : 1];
     const MemberDev& m = mems[first + blockIdx.y];
@@ -103,22 +103,36 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     hs[HE] = (ok && ln.t == 0) ? gld(static_cast<const cplx<T>*>(m.spec_nyq), q)
                                : cplx<T>{T(0), T(0)};
     // Hermitian completion F[e] = conj(F[NZ - e]) for e > NZ/2, in the input
-    // layout of the inverse plan: real parts, then imaginary parts, through LDS
+    // layout of the inverse plan (with the split exchange: real parts, then
+    // imaginary parts, through LDS)
     cplx<T> v[FP::E];
+    if constexpr (split_exchange<FP, false>()) {
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
+        for (int part = 0; part < 2; ++part) {
 #pragma unroll
-        for (int k = 0; k < HE; ++k) lds[ln(ln.t + k * FP::T)] = part ? hs[k].im : hs[k].re;
-        if (ln.t == 0) lds[ln(H)] = part ? hs[HE].im : hs[HE].re;
+            for (int k = 0; k < HE; ++k) lds[ln(ln.t + k * FP::T)] = part ? hs[k].im : hs[k].re;
+            if (ln.t == 0) lds[ln(H)] = part ? hs[HE].im : hs[HE].re;
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < FP::E; ++s) {
+                const int e = slot_elem<IP, IP::first()>(ln.t, s);
+                const T x = e <= H ? lds[ln(e)] : lds[ln(NZ - e)];
+                if (part)
+                    v[s].im = e <= H ? x : -x;
+                else
+                    v[s].re = x;
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < HE; ++k) lds[ln(ln.t + k * FP::T)] = hs[k];
+        if (ln.t == 0) lds[ln(H)] = hs[HE];
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < FP::E; ++s) {
             const int e = slot_elem<IP, IP::first()>(ln.t, s);
-            const T x = e <= H ? lds[ln(e)] : lds[ln(NZ - e)];
-            if (part)
-                v[s].im = e <= H ? x : -x;
-            else
-                v[s].re = x;
+            v[s] = e <= H ? lds[ln(e)] : conj(lds[ln(NZ - e)]);
         }
         __syncthreads();
     }
@@ -177,8 +191,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     constexpr bool INV = OP == kDensInvFft || OP == kDensInvToPhi;
     constexpr bool TO_PHI = OP == kDensInvToPhi || OP == kDensDirectToPhi;
     constexpr bool FROM_PHI = OP == kPhiR2C;
-    // the transforms exchange real and imaginary parts in turn (half the LDS)
-    __shared__ T lds[lds_entries<FP, T, false>()];
+    // real entries for a split exchange, complex ones otherwise
+    __shared__ lds_t<FP, T, false> lds[lds_entries<FP, T, false>()];
     __shared__ cplx<T> tw[tw_entries<T>(NZ)];
     const MemberDev& m = mems[first + blockIdx.y];
     const LN ln;
