@@ -197,7 +197,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         m.absorb = c.take((int64_t(g.nx) + g.ny + g.nz) * sizeof(double));
         if (g.boundary == WDM_BOUNDARY_VACUUM) {
             m.pad = c.take(8 * cells * cs);
-            m.green = c.take(8 * cells * rs);
+            m.green = c.take((int64_t(g.nx) + 1) * (g.ny + 1) * (g.nz + 1) * rs);
         }
         if (g.external_potential) m.ext = c.take(cells * rs);
         m.dt = c.take(4 * sizeof(double));

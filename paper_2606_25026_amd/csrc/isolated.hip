@@ -77,18 +77,26 @@ __global__ __launch_bounds__(kIsoThreads) void k_green_fill(const MemberDev* __r
 
 // The step's transforms are unnormalised in both directions: the padded round
 // trip and the z round trip through the half spectrum (into P1) multiply by
-// 8 nx ny nz and by nz; both factors are taken out here, once.
+// 8 nx ny nz and by nz; both factors are taken out here, once.  The padded
+// kernel is even along each axis (g[i] = g[2n - i]), so its transform is real
+// and even along each axis: only modes 0..n of each axis are kept, a
+// (nx + 1)(ny + 1)(nz + 1) table, and mode k > n reads mode 2n - k.
 template <typename T>
 __global__ __launch_bounds__(kIsoThreads) void k_green_extract(const MemberDev* __restrict__ mems,
                                                                int first) {
     const MemberDev& m = mems[first + blockIdx.y];
-    const int64_t total = 8 * int64_t(m.nx) * m.ny * m.nz;
-    const double scale = 1.0 / (double(total) * double(m.nz));
+    const int64_t fy = m.ny + 1, fz = m.nz + 1;
+    const int64_t total = (m.nx + 1) * fy * fz;
+    const int64_t py = 2 * int64_t(m.ny), pz = 2 * int64_t(m.nz);
+    const double scale = 1.0 / (8.0 * double(m.nx) * m.ny * m.nz * double(m.nz));
     const cplx<T>* pad = static_cast<const cplx<T>*>(m.pad);
     T* green = static_cast<T*>(m.green);
     for (int64_t q = int64_t(blockIdx.x) * kIsoThreads + threadIdx.x; q < total;
-         q += int64_t(gridDim.x) * kIsoThreads)
-        gstr(green, q, T(double(gld(pad, q).re) * scale));
+         q += int64_t(gridDim.x) * kIsoThreads) {
+        const int64_t i = q / (fy * fz), r = q - i * fy * fz;
+        const int64_t j = r / fz, k = r - j * fz;
+        gstr(green, q, T(double(gld(pad, (i * py + j) * pz + k).re) * scale));
+    }
 }
 
 // Phi / nz from the corner of the padded grid; one work-group per z row.

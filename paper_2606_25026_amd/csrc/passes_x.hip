@@ -131,10 +131,10 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
 // the x < NX/2 half is read (the padding half holds zeros and is never
 // written) and only that half of the result, the one the potential needs, is
 // stored.
-template <int NX, typename T>
-__global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_x_mul_green(
+template <int NX, typename T, int V>
+__global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void k_x_mul_green(
     const MemberDev* __restrict__ mems, int first) {
-    using FP = typename PlanFor<NX>::type;
+    using FP = typename PlanFor<NX, V>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
     __shared__ T lds[lds_entries<FP, T, true>()];
@@ -148,8 +148,14 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     const int q = int(blockIdx.x) * LN::PP + ln.p;
     const bool ok = q < plane;
     cplx<T>* lane = static_cast<cplx<T>*>(m.psi) + q;
-    const T* green = static_cast<const T*>(m.green) + q;
     constexpr int HALF = NX / 2;
+    // The Green's factors are even in each wavenumber and stored for modes
+    // 0..n of each axis (n = half the padded length): mode k > n reads 2n - k.
+    const int hy = m.ny / 2, hz = m.nz / 2;
+    const int qy = q / m.nz, qz = q - qy * m.nz;
+    const int gplane = (hy + 1) * (hz + 1);
+    const T* green = static_cast<const T*>(m.green) +
+                     (min(qy, m.ny - qy) * (hz + 1) + min(qz, m.nz - qz));
     // the Green's factors of this lane's output slots are loaded with the data
     T gv[FP::E];
     cplx<T> v[FP::E];
@@ -157,7 +163,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX>::type, T>())) void k_
     for (int s = 0; s < FP::E; ++s) {
         const int ein = slot_elem<FP, FP::first()>(ln.t, s);
         v[s] = (ok && ein < HALF) ? gld(lane, ein * plane) : cplx<T>{T(0), T(0)};
-        gv[s] = ok ? gldr(green, slot_elem<FP, FP::last()>(ln.t, s) * plane) : T(0);
+        const int kx = slot_elem<FP, FP::last()>(ln.t, s);
+        gv[s] = ok ? gldr(green, min(kx, NX - kx) * gplane) : T(0);
     }
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
 #pragma unroll
@@ -267,8 +274,9 @@ template <int NX>
 struct XMulGreen {
     template <typename T>
     static hipError_t go(const Launch& L, int ny, int nz) {
-        dim3 grid(unsigned(tiles<NX, T>(int64_t(ny) * nz)), unsigned(L.count));
-        k_x_mul_green<NX, T><<<grid, block<NX, T>(), 0, L.stream>>>(L.members, L.first);
+        constexpr int V = 0;   // the second plan measured slower on the padded 512 axis
+        dim3 grid(unsigned(tiles<NX, T, V>(int64_t(ny) * nz)), unsigned(L.count));
+        k_x_mul_green<NX, T, V><<<grid, block<NX, T, V>(), 0, L.stream>>>(L.members, L.first);
         return hipGetLastError();
     }
     static hipError_t run(const Launch& L, int prec, int ny, int nz) {
