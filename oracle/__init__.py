@@ -74,6 +74,7 @@ def lib():
         L.orc_mass_fraction_radii.restype = ip
         L.orc_kdk_ext.argtypes = [cp, dp, dp, dp, C.c_int64, C.c_double, dp]
         L.orc_poisson_direct.argtypes = [cp, dp, dp]
+        L.orc_poisson_direct_at.argtypes = [cp, dp, C.POINTER(C.c_int64), C.c_int64, dp]
         L.orc_cube_self_integral.restype = C.c_double
         L.orc_tidal_correct.argtypes = [cp, dp, dp]
         L.orc_energy_ext.argtypes = [cp, dp, dp, dp, dp, dp]
@@ -190,6 +191,16 @@ def poisson_direct(cfg: Config, rho):
     r = _f64(rho)
     phi = np.empty_like(r)
     lib().orc_poisson_direct(C.byref(cfg), _p(r), _p(phi))
+    return phi
+
+
+def poisson_direct_at(cfg: Config, rho, nodes):
+    """Isolated potential by direct summation at the listed (i, j, k) nodes."""
+    r = _f64(rho)
+    nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).reshape(-1, 3))
+    phi = np.empty(nd.shape[0])
+    lib().orc_poisson_direct_at(C.byref(cfg), _p(r), nd.ctypes.data_as(C.POINTER(C.c_int64)),
+                                nd.shape[0], _p(phi))
     return phi
 
 

@@ -94,6 +94,9 @@ void orc_kdk_ext(const orc_config* c, double* psi, double* pos, double* vel, int
 /* Isolated Poisson solve by direct summation over all node pairs with the
  * same sampled Green's function (O(N^6): small grids only). */
 void orc_poisson_direct(const orc_config* c, const double* rho, double* phi);
+/* The same sum at `count` listed nodes (i, j, k triples in `nodes`); phi[count]. */
+void orc_poisson_direct_at(const orc_config* c, const double* rho, const int64_t* nodes,
+                           int64_t count, double* phi);
 /* Integral of 1/|u| over the unit cube centred at the origin. */
 double orc_cube_self_integral(void);
 /* External (tidal) potential with its mean acceleration removed (Sec. 4.3). */

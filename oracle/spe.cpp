@@ -374,6 +374,24 @@ void orc_poisson_direct(const orc_config* c, const double* rho, double* phi) {
             }
 }
 
+// The same direct sum evaluated at listed nodes only (i, j, k triples), so that
+// the potential of a large grid can be checked node by node.
+void orc_poisson_direct_at(const orc_config* c, const double* rho, const int64_t* nodes,
+                           int64_t count, double* phi) {
+    Grid g(c);
+    const double self = cube_self_integral();
+    for (int64_t n = 0; n < count; ++n) {
+        const int64_t i = nodes[3 * n], j = nodes[3 * n + 1], k = nodes[3 * n + 2];
+        double sum = 0.0;
+        for (int64_t a = 0; a < g.nx; ++a)
+            for (int64_t b = 0; b < g.ny; ++b)
+                for (int64_t d = 0; d < g.nz; ++d)
+                    sum += green_iso(c, g, i - a, j - b, k - d, self) *
+                           rho[(a * g.ny + b) * g.nz + d];
+        phi[n] = sum;
+    }
+}
+
 double orc_cube_self_integral(void) { return cube_self_integral(); }
 
 // Tidal potential with its mean acceleration removed (Sec. 4.3): the mean

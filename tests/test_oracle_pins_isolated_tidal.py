@@ -50,6 +50,19 @@ def test_isolated_solve_equals_direct_sum(orc, shape, L):
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
 
 
+@pytest.mark.parametrize("shape,L", [((8, 8, 8), 1.0), ((8, 12, 6), (1.0, 1.5, 0.75))])
+def test_sampled_direct_sum_equals_full_direct_sum(orc, shape, L):
+    # the node-by-node form used to check full-size potentials
+    rng = np.random.default_rng(11 + sum(shape))
+    rho = rng.random(shape)
+    cfg = orc.make_config(shape, L=L, boundary=orc.BOUNDARY_VACUUM, four_pi_G=2.0)
+    full = orc.poisson_direct(cfg, rho)
+    nodes = np.stack([rng.integers(0, n, 20) for n in shape], axis=1)
+    nodes = np.vstack([nodes, [[0, 0, 0]], [[n - 1 for n in shape]]])
+    got = orc.poisson_direct_at(cfg, rho, nodes)
+    assert np.array_equal(got, full[nodes[:, 0], nodes[:, 1], nodes[:, 2]])
+
+
 def test_isolated_gaussian_converges_to_closed_form(orc):
     sig, G4 = 0.06, 2.0
     errs = []
