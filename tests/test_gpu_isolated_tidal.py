@@ -82,6 +82,26 @@ def test_vacuum_halo_steps_match_oracle(wdm, orc, prec):
     r.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vacuum_potential_full_size_sampled(wdm, orc, prec):
+    # 256^3 (the largest vacuum grid: a 512^3 padded solve), checked node by
+    # node against the oracle's direct sum over all 256^3 source nodes
+    n = 256
+    wl = inputs.coupled_halo(n=n, n_particles=0, seed=55, steps=0)
+    r = Run(wdm, wl.psi, prec=prec, boundary=VAC)
+    phi = r.get_phi()
+    r.close()
+    rng = np.random.default_rng(56)
+    nodes = np.vstack([rng.integers(0, n, (12, 3)), [[0, 0, 0], [n - 1] * 3, [n // 2] * 3,
+                                                     [n // 2, 0, n - 1]]])
+    cfg = orc.make_config((n,) * 3, boundary=orc.BOUNDARY_VACUUM)
+    ref = orc.poisson_direct_at(cfg, np.abs(stored(wl.psi, prec)) ** 2, nodes)
+    got = phi[nodes[:, 0], nodes[:, 1], nodes[:, 2]]
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"vacuum potential 256^3 sampled, prec={prec}: {err:.3e}")
+    assert err < tol(prec)
+
+
 def test_vacuum_and_periodic_members_in_one_plan(wdm, orc):
     # same grid size, different boundaries: two size classes, each right
     wl = inputs.coupled_halo(n=32, n_particles=0, seed=52, steps=0)
