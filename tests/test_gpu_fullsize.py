@@ -1,6 +1,9 @@
 """Full-size parity: the 256^3 + 1e6-particle coupled halo, in the launch
 configuration the benchmark times, against sampled FP64-oracle values written
-by tests/golden/make_coupled_halo_reference.py (65536 cells, 10000 particles).
+by tests/golden/make_coupled_halo_reference.py (65536 cells, 10000 particles);
+and the optional parts of the step (self-interaction, absorbing layer, external
+tidal field, particle sub-steps; static baryons) on the same workload over 3
+steps against the oracle run in the test, on the whole grid and every particle.
 """
 from pathlib import Path
 
@@ -84,3 +87,64 @@ def test_coupled_halo_256_1000_steps_reported(wdm, halo):
     assert r["err"] < 1e-3
     assert r["perr"] < 1e-4
     assert abs(r["drift"]) < 1e-5
+
+
+EXTENDED = {
+    # self-interaction, absorbing layer (the paper's alpha = 10, N_b = 50), an
+    # external tidal field and four particle sub-steps per wave step
+    "kappa-mask-tidal-substeps": dict(kappa=50.0, absorb_alpha=10.0, absorb_nb=50.0,
+                                      nbody_substeps=4),
+    "static-baryons": dict(baryon_mode=1),
+}
+
+
+@pytest.mark.parametrize("name", list(EXTENDED))
+def test_extended_256_steps_vs_oracle(wdm, orc, halo, name):
+    # the optional parts at the benchmark's size, 3 steps against the oracle
+    # run here over the whole grid and every particle
+    extra, steps, n = EXTENDED[name], 3, 256
+    tidal = name.startswith("kappa")
+    cfg = wdm.make_config(n, n_particles=halo.n_particles, particle_mass=halo.particle_mass,
+                          external_potential=1 if tidal else 0, **extra)
+    plan = wdm.Plan(cfg)
+    ext = None
+    if tidal:
+        x = np.arange(n, dtype=np.float32) / np.float32(n) - np.float32(0.5)
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        ext = np.float32(25.0) * (X * X + Y * Y - np.float32(2.0) * Z * Z)
+        del X, Y, Z
+        wdm.wdm_set_external_potential(plan.handle, 0, torch.from_numpy(ext).cuda())
+    psi = torch.from_numpy(halo.psi.astype(np.complex64)).cuda()
+    pos = torch.from_numpy(halo.pos).cuda()
+    vel = torch.from_numpy(halo.vel).cuda()
+    wdm.wdm_set_state(plan.handle, 0, psi, pos, vel)
+    wdm.wdm_set_sort_interval(plan.handle, 128)
+    wdm.wdm_step(plan.handle, steps, halo.dt)
+    out = torch.empty_like(psi)
+    wdm.wdm_get_psi(plan.handle, 0, out)
+    p, v = torch.empty_like(pos), torch.empty_like(vel)
+    wdm.wdm_particles(plan.handle, 0, p, v)
+    torch.cuda.synchronize()
+    plan.close()
+    got = out.cpu().numpy().astype(np.complex128)
+    p, v = p.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+    ocfg = orc.make_config((n,) * 3, n_particles=halo.n_particles,
+                           particle_mass=halo.particle_mass, **extra)
+    phi_ext = orc.tidal_correct(ocfg, ext.astype(np.float64)) if tidal else None
+    ref, p_ref, v_ref = orc.kdk(ocfg, halo.psi.astype(np.complex64).astype(np.complex128),
+                                halo.pos.astype(np.float64), halo.vel.astype(np.float64),
+                                nsteps=steps, dt=halo.dt, phi_ext=phi_ext)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    drifts = steps * extra.get("nbody_substeps", 1)
+    perr = np.max(np.abs(periodic_diff(p, p_ref)))
+    verr = np.linalg.norm(v - v_ref) / np.linalg.norm(v_ref)
+    print(f"[{name}] 256^3 + 1e6 particles, {steps} steps: psi rel L2 {err:.3e}, "
+          f"max |dx| {perr:.2e}, vel rel L2 {verr:.2e}")
+    assert err < 1e-5
+    if extra.get("baryon_mode") == 1:
+        assert np.array_equal(p, halo.pos.astype(np.float64))
+        assert np.array_equal(v, halo.vel.astype(np.float64))
+    else:
+        # float32 storage: half an ulp of a coordinate below 1 per drift
+        assert perr < drifts * 2.0 ** -25 + 1e-7
+        assert verr < 1e-5
