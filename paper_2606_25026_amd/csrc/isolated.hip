@@ -15,6 +15,7 @@
 namespace wdm {
 
 constexpr int kIsoThreads = 256;
+typedef float wdm_f4v __attribute__((ext_vector_type(4)));
 
 static unsigned iso_grid(int64_t count) {
     int64_t g = (count + kIsoThreads - 1) / kIsoThreads;
@@ -37,9 +38,20 @@ __global__ __launch_bounds__(kIsoThreads) void k_pad_density(const MemberDev* __
         cplx<T>* row = pad + int64_t(r) * pnz;
         const bool inside = j < m.ny;
         const T* src = rho + (int64_t(i) * m.ny + (inside ? j : 0)) * m.nz;
-        for (int k = int(threadIdx.x); k < pnz; k += kIsoThreads) {
-            const T v = (inside && k < m.nz) ? gldr(src, k) : T(0);
-            gst(row, k, cplx<T>{v, T(0)});
+        // two neighbouring values per thread (every length is even); complex64
+        // pairs go out as one 16-byte store
+        for (int k = 2 * int(threadIdx.x); k < pnz; k += 2 * kIsoThreads) {
+            T v0 = T(0), v1 = T(0);
+            if (inside && k < m.nz) {
+                v0 = gldr(src, k);
+                v1 = gldr(src, k + 1);
+            }
+            if constexpr (std::is_same_v<T, float>) {
+                ((WDM_GAS wdm_f4v*)(row + k))[0] = wdm_f4v{v0, 0.0f, v1, 0.0f};
+            } else {
+                gst(row, k, cplx<T>{v0, T(0)});
+                gst(row, k + 1, cplx<T>{v1, T(0)});
+            }
         }
     }
 }
@@ -112,7 +124,15 @@ __global__ __launch_bounds__(kIsoThreads) void k_unpad(const MemberDev* __restri
         const int i = r / m.ny, j = r - i * m.ny;
         const cplx<T>* src = pad + (int64_t(i) * pny + j) * pnz;
         T* dst = phi + int64_t(r) * m.nz;
-        for (int k = int(threadIdx.x); k < m.nz; k += kIsoThreads) gstr(dst, k, gld(src, k).re);
+        if constexpr (std::is_same_v<T, float>) {
+            // two neighbouring nodes per thread: one 16-byte load, one 8-byte store
+            for (int k = 2 * int(threadIdx.x); k < m.nz; k += 2 * kIsoThreads) {
+                const wdm_f4v a = ((const WDM_GAS wdm_f4v*)(src + k))[0];
+                ((WDM_GAS wdm_f2v*)(dst + k))[0] = wdm_f2v{a.x, a.z};
+            }
+        } else {
+            for (int k = int(threadIdx.x); k < m.nz; k += kIsoThreads) gstr(dst, k, gld(src, k).re);
+        }
     }
 }
 
