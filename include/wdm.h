@@ -62,6 +62,35 @@ typedef enum {
 typedef enum { WDM_C64 = 0, WDM_C128 = 1 } wdm_precision;
 
 enum { WDM_BARYON_DYNAMIC = 0, WDM_BARYON_STATIC = 1 };
+
+/* Bits of wdm_config.flags.
+ *
+ * WDM_DETERMINISTIC_DEPOSIT (must be the same on every member of a plan):
+ * results are bitwise reproducible -- from run to run, between graph replays
+ * and direct launches, and across a state saved between wdm_step calls
+ * (wdm_get_psi, wdm_particles, wdm_energy's t) and set again with
+ * wdm_set_state, on this plan or another with the same members.  The CIC
+ * deposit (Sec. 3.2.2) sums 64-bit fixed-point contributions round(q w 2^S)
+ * (S per member, such that all the member's particle mass on one node stays
+ * below 2^62), so its sums are exact whatever the order of the particles or of
+ * the atomic additions; and every wdm_step call starts by rebuilding the
+ * potential from the synchronised state (one Poisson solve per call), exactly
+ * as wdm_set_state builds it.  Costs an n-cell 8-byte grid per member and a
+ * conversion pass per step.
+ *
+ * WDM_STRICT_CFL: a step above the CFL bound of Sec. 3.5 makes the next
+ * wdm_energy / wdm_diagnostics call fail with WDM_EUNSTABLE (without it the
+ * bound is only reported, wdm_energy_t.cfl_ratio).  Every step checks, on the
+ * device, |dt| <= dt_max = 0.5 min{(4 / (3 pi)) dx_min^2 / eta,
+ * 2 pi eta / max|Phi|, 2 pi eta / (|kappa| max|psi|^2)} with the maxima of the
+ * potentials its kicks used; a non-finite potential or density always makes
+ * those calls fail with WDM_EUNSTABLE.  The check stays set until
+ * wdm_set_state.
+ *
+ * The kick and drift phase arguments are always formed in FP64 and reduced
+ * mod 2 pi (there is no FP32-argument mode). */
+#define WDM_DETERMINISTIC_DEPOSIT 0x1u
+#define WDM_STRICT_CFL 0x2u
 enum { WDM_BOUNDARY_PERIODIC = 0, WDM_BOUNDARY_VACUUM = 1 };
 
 /* One box (an ensemble has several). */
@@ -73,7 +102,7 @@ typedef struct {
     int64_t n_particles;       /* baryon particles (0 = none) */
     double particle_mass;      /* equal-mass particles */
     int32_t precision;         /* wdm_precision; all members of a plan share it */
-    uint32_t flags;            /* reserved, must be 0 */
+    uint32_t flags;            /* WDM_DETERMINISTIC_DEPOSIT and / or WDM_STRICT_CFL (below) */
     /* Local self-interaction (Sec. 2.2, 2.4): the kick potential becomes
      * Phi + kappa |psi|^2 (kappa > 0 repulsive, < 0 attractive; 0 = none), the
      * energy gains kappa/2 int |psi|^4 and the CFL step a third term. */
@@ -125,6 +154,9 @@ typedef struct {
     double e_ext;              /* int rho_tot Phi_ext dV of an external potential (in e_total;
                                   e_pot is then the self-gravity part, max_abs_phi and the
                                   CFL step are of the potential felt, self plus external) */
+    double cfl_ratio;          /* largest |dt| / dt_max (Sec. 3.5) over the steps since the last
+                                  wdm_set_state, dt_max from the potentials the steps' kicks
+                                  used (see WDM_STRICT_CFL); 0 before the first step */
 } wdm_energy_t;
 
 /* The paper's diagnostics of a synchronised state (Sec. 3.6, App. A.1),
@@ -193,7 +225,9 @@ wdm_status wdm_density(wdm_plan* plan, int32_t member, void* rho_out, int32_t in
 /* Total potential Phi of the synchronised state (dev out, real grid). */
 wdm_status wdm_potential(wdm_plan* plan, int32_t member, void* phi_out);
 
-/* FP64 diagnostics (host out).  Synchronises the plan's stream. */
+/* FP64 diagnostics (host out).  Synchronises the plan's stream.  Returns
+ * WDM_EUNSTABLE, leaving *out untouched, when the state or a step's potential
+ * was non-finite, or (WDM_STRICT_CFL) a step exceeded the CFL bound. */
 wdm_status wdm_energy(wdm_plan* plan, int32_t member, wdm_energy_t* out);
 
 /* External (tidal) potential of a member created with external_potential =

@@ -59,6 +59,8 @@ wdm_status fail(wdm_status st, const std::string& msg) {
 }
 
 constexpr size_t kAlign = 256;
+// kinetic constant of the CFL step (Sec. 3.5): dt_max = 0.5 min{(4 / (3 pi)) dx^2 / eta, ...}
+constexpr double kCKin = 4.0 / (3.0 * kPi);
 
 struct Carver {
     size_t off = 0;
@@ -71,7 +73,7 @@ struct Carver {
 };
 
 struct MemberLayout {
-    size_t psi, phi, rho_b, spec, nyq, kin, absorb, dt, results;
+    size_t psi, phi, rho_b, spec, nyq, kin, absorb, dt, results, watch, stab, rho_fx = 0;
     size_t pad = 0, green = 0, ext = 0;   // vacuum boundary, external potential
     size_t p[7], a[7], key_a, key_b, idx_a, idx_b, hist;
 };
@@ -120,8 +122,8 @@ bool valid_config(const wdm_config& c, std::string& why) {
         why = "precision must be WDM_C64 or WDM_C128";
         return false;
     }
-    if (c.flags != 0) {
-        why = "flags must be 0";
+    if ((c.flags & ~uint32_t(WDM_DETERMINISTIC_DEPOSIT | WDM_STRICT_CFL)) != 0) {
+        why = "flags may only hold WDM_DETERMINISTIC_DEPOSIT and WDM_STRICT_CFL";
         return false;
     }
     if (!std::isfinite(c.kappa) || !std::isfinite(c.absorb_alpha) || c.absorb_alpha < 0) {
@@ -177,6 +179,10 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
             why = "all members must share one precision";
             return false;
         }
+        if ((mem[i].flags ^ mem[0].flags) & WDM_DETERMINISTIC_DEPOSIT) {
+            why = "all members must share the WDM_DETERMINISTIC_DEPOSIT flag";
+            return false;
+        }
     }
     const size_t cs = prec ? 16 : 8, rs = prec ? 8 : 4;
     Carver c;
@@ -202,6 +208,9 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         if (g.external_potential) m.ext = c.take(cells * rs);
         m.dt = c.take(4 * sizeof(double));
         m.results = c.take(kRedFields * sizeof(double));
+        m.watch = c.take(128 * sizeof(unsigned long long));
+        m.stab = c.take(2 * sizeof(double));
+        if (g.flags & WDM_DETERMINISTIC_DEPOSIT) m.rho_fx = c.take(cells * 8);
         const int64_t np = std::max<int64_t>(g.n_particles, 0);
         for (int a = 0; a < 7; ++a) m.p[a] = c.take(np * 4);
         for (int a = 0; a < 7; ++a) m.a[a] = c.take(np * 4);
@@ -249,6 +258,11 @@ struct Rec {
 
 }  // namespace
 
+namespace wdm {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace wdm
+
+
 struct wdm_plan {
     hipStream_t stream = nullptr;
     int prec = 0;
@@ -264,6 +278,7 @@ struct wdm_plan {
     uint8_t* ws = nullptr;
     int sort_interval = 32;
     int64_t steps_done = 0;
+    bool det = false;                   // WDM_DETERMINISTIC_DEPOSIT (shared by all members)
     bool profiling = false;
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -405,6 +420,42 @@ hipError_t potential_from_state(wdm_plan* p, const Launch& L, const wdm_config& 
                                    member_extended(c));
 }
 
+// Outcome of the stability checks of the steps since wdm_set_state (stab as
+// read back from the device): a non-finite potential or density always fails,
+// a step above dt_max only under WDM_STRICT_CFL.
+wdm_status stability_status(const wdm_config& c, const double stab[2]) {
+    if (stab[1] != 0.0) return fail(WDM_EUNSTABLE, "non-finite potential or density in a step");
+    if ((c.flags & WDM_STRICT_CFL) && stab[0] > 1.0) {
+        char msg[160];
+        std::snprintf(msg, sizeof(msg),
+                      "time step above the CFL bound of Sec. 3.5: |dt| / dt_max = %.6g", stab[0]);
+        return fail(WDM_EUNSTABLE, msg);
+    }
+    return WDM_OK;
+}
+
+// The stability checks of a member's steps so far (synchronises the stream).
+wdm_status check_stability(wdm_plan* p, int32_t member) {
+    double stab[2];
+    const MemberDev& m = p->host[p->dev_index[member]];
+    HIPCHK(hipMemcpyAsync(stab, m.stab, sizeof(stab), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return stability_status(p->cfg[member], stab);
+}
+
+// Potential of a member's synchronised state (psi, particle positions): the
+// moving particles are deposited (static ones keep their deposit in rho_b)
+// and Poisson is solved, as wdm_set_state does.
+hipError_t rebuild_potential(wdm_plan* p, int32_t member) {
+    const wdm_config& c = p->cfg[member];
+    const Launch L = one(p, member);
+    if (c.n_particles > 0 && c.baryon_mode == WDM_BARYON_DYNAMIC) {
+        const hipError_t e = launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det);
+        if (e != hipSuccess) return e;
+    }
+    return potential_from_state(p, L, c);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -444,6 +495,7 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
     p->layout = L;
     p->ws = static_cast<uint8_t*>(workspace);
     p->has_state.assign(n_members, false);
+    p->det = (members[0].flags & WDM_DETERMINISTIC_DEPOSIT) != 0;
     uint8_t* ws = p->ws;
     const size_t cs = p->prec ? 16 : 8;
 
@@ -517,6 +569,20 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.particle_mass = c.particle_mass;
         m.partials = reinterpret_cast<double*>(ws + L.partials);
         m.results = reinterpret_cast<double*>(ws + ml.results);
+        m.watch = reinterpret_cast<unsigned long long*>(ws + ml.watch);
+        m.stab = reinterpret_cast<double*>(ws + ml.stab);
+        if (c.flags & WDM_DETERMINISTIC_DEPOSIT) {
+            // fixed point with round(value * 2^S): the largest possible node sum,
+            // all the member's particle mass on one node, stays below 2^62
+            m.deterministic = 1;
+            m.rho_fx = reinterpret_cast<unsigned long long*>(ws + ml.rho_fx);
+            const double total = double(c.n_particles) * c.particle_mass * m.inv_dx * m.inv_dy *
+                                 m.inv_dz;
+            int ex = 0;
+            (void)std::frexp(total, &ex);
+            m.fx_scale = std::ldexp(1.0, 62 - ex);
+            m.fx_inv = std::ldexp(1.0, ex - 62);
+        }
         if (p->classes.empty() || p->classes.back().nx != c.nx || p->classes.back().ny != c.ny ||
             p->classes.back().nz != c.nz ||
             p->classes.back().vacuum != (c.boundary == WDM_BOUNDARY_VACUUM)) {
@@ -572,8 +638,10 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         }
         const void* src = p->prec ? static_cast<const void*>(d.data()) : f.data();
         const size_t bytes = size_t(n) * cs * (p->prec ? 1 : 2);
-        if (hipMemcpy(ws + kv.second, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
-            return cleanup(WDM_EDEVICE, "twiddle upload failed");
+        if (const hipError_t e = hipMemcpy(ws + kv.second, src, bytes, hipMemcpyHostToDevice);
+            e != hipSuccess)
+            return cleanup(WDM_EDEVICE, std::string("twiddle upload failed: ") +
+                                            hipGetErrorString(e));
     }
     if (hipMemcpy(p->table, p->host.data(), sizeof(MemberDev) * n_members,
                   hipMemcpyHostToDevice) != hipSuccess ||
@@ -586,7 +654,10 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         const int64_t cells = int64_t(m.nx) * m.ny * m.nz;
         if (launch_zero(p->stream, m.rho_b, size_t(cells) * (p->prec ? 8 : 4)) != hipSuccess ||
             launch_zero(p->stream, m.dt, 4 * sizeof(double)) != hipSuccess ||
-            launch_zero(p->stream, m.results, kRedFields * sizeof(double)) != hipSuccess)
+            launch_zero(p->stream, m.results, kRedFields * sizeof(double)) != hipSuccess ||
+            launch_zero(p->stream, m.watch, 128 * sizeof(unsigned long long)) != hipSuccess ||
+            launch_zero(p->stream, m.stab, 2 * sizeof(double)) != hipSuccess ||
+            (m.rho_fx && launch_zero(p->stream, m.rho_fx, size_t(cells) * 8) != hipSuccess))
             return cleanup(WDM_EDEVICE, "plan initialisation failed");
     }
     // absorbing factors of dt = 0 (all ones) until the first step sets dt
@@ -638,16 +709,18 @@ wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const flo
     HIPCHK(hipMemcpyAsync(m.psi, psi, size_t(n) * (p->prec ? 16 : 8), hipMemcpyDeviceToDevice,
                           p->stream));
     HIPCHK(launch_zero(p->stream, m.rho_b, size_t(n) * (p->prec ? 8 : 4)));
+    HIPCHK(launch_zero(p->stream, m.watch, 128 * sizeof(unsigned long long)));
+    HIPCHK(launch_zero(p->stream, m.stab, 2 * sizeof(double)));
     if (c.n_particles > 0) {
         HIPCHK(launch_particle_upload(p->stream, m, pos, vel));
         HIPCHK(launch_particle_sort(L, c.n_particles, c.nx, c.ny, c.nz));
-        HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick));
+        HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det));
     }
     HIPCHK(potential_from_state(p, L, c));
     HIPCHK(launch_reduce_grid(L, p->prec, n, 0));
     HIPCHK(launch_reduce_finish(L, 7, kRedBlocks, true));
     HIPCHK(launch_reduce_finish(L, 8, kRedBlocks, true));
-    HIPCHK(launch_dt_auto(L, 0.9, 4.0 / (3.0 * kPi)));
+    HIPCHK(launch_dt_auto(L, 0.9, kCKin));
     HIPCHK(launch_set_dt(L, t0, 3));
     p->has_state[member] = true;
     return WDM_OK;
@@ -687,13 +760,14 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             const Launch LA{aux, p->table, c.first, c.count};
             if (!chk(hipEventRecord(p->ev_fork, s))) return e;
             if (!chk(hipStreamWaitEvent(aux, p->ev_fork, 0))) return e;
-            if (!chk(timed_on(p, aux, kKParticles,
-                              [&] { return launch_particles(LA, prec, c.moving_np, 0, km); })))
+            if (!chk(timed_on(p, aux, kKParticles, [&] {
+                    return launch_particles(LA, prec, c.moving_np, 0, km, p->det);
+                })))
                 return e;
             if (!chk(hipEventRecord(p->ev_join, aux))) return e;
         } else if (parts) {
             if (!chk(timed(p, kKParticles,
-                           [&] { return launch_particles(L, prec, c.moving_np, 0, km); })))
+                           [&] { return launch_particles(L, prec, c.moving_np, 0, km, p->det); })))
                 return e;
         }
         if (!chk(timed(p, kKYPsiF, [&] {
@@ -758,9 +832,10 @@ hipError_t enqueue_close(wdm_plan* p, hipStream_t s, int64_t n) {
         });
         if (e == hipSuccess && c.moving_np > 0)
             e = timed(p, kKCloseParticles, [&] {
-                return launch_particles(L, p->prec, c.moving_np, 1, kHalfKick);
+                return launch_particles(L, p->prec, c.moving_np, 1, kHalfKick, p->det);
             });
         if (e == hipSuccess) e = launch_advance_time(L, n);
+        if (e == hipSuccess) e = launch_stability(L, kCKin);
         if (e != hipSuccess) return e;
     }
     return e;
@@ -817,6 +892,11 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
                 return wdm_step(p, n, dt);
             }
     }
+    // deterministic mode: each call starts from the synchronised state alone,
+    // its potential rebuilt as wdm_set_state builds it, so a state saved
+    // between calls and set again continues bit for bit
+    if (p->det)
+        for (int32_t u = 0; u < int32_t(p->cfg.size()); ++u) HIPCHK(rebuild_potential(p, u));
     // direct launches run on the caller's stream and fork the particle
     // kernel onto the auxiliary stream, as the captured graph does
     HIPCHK(ensure_streams(p));
@@ -1017,7 +1097,7 @@ wdm_status wdm_density(wdm_plan* p, int32_t member, void* out, int32_t include_b
     const bool inc = include_baryons && c.n_particles > 0;
     if (inc) {
         HIPCHK(launch_zero(p->stream, m.scratch, size_t(n) * (p->prec ? 8 : 4)));
-        HIPCHK(launch_particles(L, p->prec, c.n_particles, 3, kHalfKick));
+        HIPCHK(launch_particles(L, p->prec, c.n_particles, 3, kHalfKick, p->det));
     }
     HIPCHK(launch_density_out(L, p->prec, n, out, inc ? 1 : 0));
     return WDM_OK;
@@ -1032,6 +1112,7 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     const MemberDev& m = p->host[p->dev_index[member]];
     const int64_t n = cells_of(c);
     const int prec = p->prec;
+    if (wdm_status st = check_stability(p, member)) return st;
     // mass, max |Phi|, max |psi|^2 and sum |psi|^4
     HIPCHK(launch_reduce_grid(L, prec, n, 0));
     HIPCHK(launch_reduce_finish(L, 0, kRedBlocks, false));
@@ -1040,7 +1121,7 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
     HIPCHK(launch_reduce_finish(L, 9, kRedBlocks, false));
     // potential energy with the deposited baryons
     HIPCHK(launch_zero(p->stream, m.scratch, size_t(n) * (prec ? 8 : 4)));
-    if (c.n_particles > 0) HIPCHK(launch_particles(L, prec, c.n_particles, 3, kHalfKick));
+    if (c.n_particles > 0) HIPCHK(launch_particles(L, prec, c.n_particles, 3, kHalfKick, p->det));
     HIPCHK(launch_reduce_grid(L, prec, n, 1));
     HIPCHK(launch_reduce_finish(L, 2, kRedBlocks, false));
     // the stored Phi carries the external potential; its energy enters once
@@ -1059,32 +1140,36 @@ wdm_status wdm_energy(wdm_plan* p, int32_t member, wdm_energy_t* out) {
         HIPCHK(launch_reduce_particles(L, c.n_particles));
         for (int f = 3; f < 7; ++f) HIPCHK(launch_reduce_finish(L, f, kRedBlocks, false));
     }
-    double res[kRedFields], dts[4];
+    double res[kRedFields], dts[4], stab[2];
     HIPCHK(hipMemcpyAsync(res, m.results, sizeof(res), hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipMemcpyAsync(dts, m.dt, sizeof(dts), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipMemcpyAsync(stab, m.stab, sizeof(stab), hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
     const double dv = (c.lx / c.nx) * (c.ly / c.ny) * (c.lz / c.nz);
     const double eta = c.hbar_over_m;
-    std::memset(out, 0, sizeof(*out));
-    out->mass = res[0] * dv;
-    out->e_kin = 0.5 * eta * eta * res[1] * dv / double(n);
+    wdm_energy_t r;
+    std::memset(&r, 0, sizeof(r));
+    r.mass = res[0] * dv;
+    r.e_kin = 0.5 * eta * eta * res[1] * dv / double(n);
     const double s_ext = m.ext ? res[10] : 0.0;
-    out->e_pot = 0.5 * (res[2] - s_ext) * dv;
-    out->e_ext = s_ext * dv;
+    r.e_pot = 0.5 * (res[2] - s_ext) * dv;
+    r.e_ext = s_ext * dv;
     if (c.n_particles > 0) {
-        out->e_kin_particles = 0.5 * c.particle_mass * res[3];
-        for (int a = 0; a < 3; ++a) out->momentum[a] = c.particle_mass * res[4 + a];
+        r.e_kin_particles = 0.5 * c.particle_mass * res[3];
+        for (int a = 0; a < 3; ++a) r.momentum[a] = c.particle_mass * res[4 + a];
     }
-    out->e_self = 0.5 * c.kappa * res[9] * dv;
-    out->e_total = out->e_kin + out->e_pot + out->e_kin_particles + out->e_self + out->e_ext;
-    out->max_abs_phi = res[7];
-    out->max_rho = res[8];
-    out->t = dts[3];
-    out->dt = dts[0] != 0.0 ? dts[0] : dts[1];
-    out->dt_auto = dts[1];
-    const bool finite = std::isfinite(out->mass) && std::isfinite(out->e_total) &&
-                        std::isfinite(out->max_abs_phi);
+    r.e_self = 0.5 * c.kappa * res[9] * dv;
+    r.e_total = r.e_kin + r.e_pot + r.e_kin_particles + r.e_self + r.e_ext;
+    r.max_abs_phi = res[7];
+    r.max_rho = res[8];
+    r.t = dts[3];
+    r.dt = dts[0] != 0.0 ? dts[0] : dts[1];
+    r.dt_auto = dts[1];
+    r.cfl_ratio = stab[0];
+    const bool finite = std::isfinite(r.mass) && std::isfinite(r.e_total) &&
+                        std::isfinite(r.max_abs_phi);
     if (!finite) return fail(WDM_EUNSTABLE, "non-finite state");
+    *out = r;
     return WDM_OK;
 }
 
@@ -1122,6 +1207,7 @@ wdm_status wdm_diagnostics(wdm_plan* p, int32_t member, const int32_t* centre,
     const Launch L = one(p, member);
     const MemberDev& m = p->host[p->dev_index[member]];
     const int64_t n = cells_of(c);
+    if (wdm_status st = check_stability(p, member)) return st;
     HIPCHK(launch_diag_energies(L, p->prec, kRedBlocks));
     for (int f = 0; f < 7; ++f) HIPCHK(launch_reduce_finish(L, f, kRedBlocks, false));
     const double dx = c.lx / c.nx;
@@ -1515,8 +1601,7 @@ wdm_status wdm_net_apply(wdm_net* net, wdm_plan* p, int32_t member, double s_psi
                            net->at<double>(net->L.dpart), scal + 1, scal + 2));
     // the corrected psi needs its own potential: redeposit the particles and
     // re-solve Poisson so the state is synchronised again
-    if (c.n_particles > 0) HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick));
-    HIPCHK(potential_from_state(p, L, c));
+    HIPCHK(rebuild_potential(p, member));
     return WDM_OK;
 }
 

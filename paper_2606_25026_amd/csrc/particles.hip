@@ -12,6 +12,7 @@
 #include "wdm_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace wdm {
 
@@ -136,17 +137,32 @@ __device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const Membe
 __device__ __forceinline__ float wrap_pos(double x, double L, double inv_l) {
     x -= L * floor(x * inv_l);
     float f = float(x);
-    if (f >= float(L) || f < 0.0f) f = 0.0f;
+    if (!(f >= 0.0f && f < float(L))) f = 0.0f;   // also a non-finite position
     return f;
+}
+
+// A deposit contribution in the accumulator type A: the grid precision T
+// itself, or (deterministic deposit) the 64-bit fixed-point value
+// round(v * scale), whose sums are exact and so independent of their order.
+template <typename A, typename T>
+__device__ __forceinline__ A to_acc(T v, double scale) {
+    if constexpr (std::is_same<A, T>::value)
+        return v;
+    else
+        return A(__double2ll_rn(double(v) * scale));
+}
+
+__device__ __forceinline__ void gatomic_add(unsigned long long* p, unsigned long long v) {
+    atomicAdd(p, v);
 }
 
 // Per-run sums of the eight CIC contributions q * w of a wavefront: lanes
 // holding the same base cell (consecutive after the cell sort) form a run; on
 // return the run's first lane holds the run's sums in val[] and head = true.
 // All 64 lanes of the wavefront must call this together.
-template <typename T>
+template <typename T, typename A>
 __device__ __forceinline__ bool wave_runs(const MemberDev& m, const CellW<T>& c, T q, bool act,
-                                          T val[8]) {
+                                          A val[8], double scale) {
     const int lane = int(__lane_id());
     const int64_t key = act ? (int64_t(c.i) * m.ny + c.j) * m.nz + c.k : -1 - lane;
 #pragma unroll
@@ -155,7 +171,8 @@ __device__ __forceinline__ bool wave_runs(const MemberDev& m, const CellW<T>& c,
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-                val[a * 4 + b * 2 + d] = act ? q * c.w[0][a] * c.w[1][b] * c.w[2][d] : T(0);
+                val[a * 4 + b * 2 + d] =
+                    act ? to_acc<A>(T(q * c.w[0][a] * c.w[1][b] * c.w[2][d]), scale) : A(0);
     // run heads: lanes whose key differs from the previous lane's
     const int64_t prev = __shfl_up(key, 1);
     const bool head = lane == 0 || prev != key;
@@ -168,7 +185,7 @@ __device__ __forceinline__ bool wave_runs(const MemberDev& m, const CellW<T>& c,
         const bool take = (lane + off < 64) && (oseg == seg);
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-            const T o = __shfl_down(val[v], off);
+            const A o = __shfl_down(val[v], off);
             if (take) val[v] += o;
         }
     }
@@ -177,11 +194,11 @@ __device__ __forceinline__ bool wave_runs(const MemberDev& m, const CellW<T>& c,
 
 // Deposit q * w into `grid` at the 8 nodes of cell c, one global atomic add
 // per node and wavefront run.
-template <typename T>
-__device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberDev& m,
-                                             const CellW<T>& c, T q, bool act) {
-    T val[8];
-    if (!wave_runs(m, c, q, act, val)) return;
+template <typename T, typename A>
+__device__ __forceinline__ void deposit_wave(A* __restrict__ grid, const MemberDev& m,
+                                             const CellW<T>& c, T q, bool act, double scale) {
+    A val[8];
+    if (!wave_runs(m, c, q, act, val, scale)) return;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int i1 = c.i + 1 == nx ? 0 : c.i + 1;
     const int j1 = c.j + 1 == ny ? 0 : c.j + 1;
@@ -194,7 +211,7 @@ __device__ __forceinline__ void deposit_wave(T* __restrict__ grid, const MemberD
 #pragma unroll
             for (int d = 0; d < 2; ++d)
                 gatomic_add(&grid[(int64_t(I[a]) * ny + J[b]) * nz + K[d]],
-                            T(val[a * 4 + b * 2 + d]));
+                            A(val[a * 4 + b * 2 + d]));
 }
 
 // LDS staging of a work-group's deposit: 16 KB of nodes.
@@ -221,10 +238,10 @@ __device__ __forceinline__ int wave_max(int v) {
 // into LDS and issues one global atomic add per non-zero node; otherwise each
 // wavefront deposits its runs directly.  Every lane of the work-group must
 // call this (inactive lanes pass act = false).
-template <typename T>
-__device__ __forceinline__ void deposit_group(T* __restrict__ grid, const MemberDev& m,
-                                              const CellW<T>& c, T q, bool act) {
-    __shared__ T tile[tile_nodes<T>()];
+template <typename T, typename A>
+__device__ __forceinline__ void deposit_group(A* __restrict__ grid, const MemberDev& m,
+                                              const CellW<T>& c, T q, bool act, double scale) {
+    __shared__ A tile[tile_nodes<A>()];
     __shared__ int box[6];
     const int tid = int(threadIdx.x);
     constexpr int kBig = 1 << 30;
@@ -251,15 +268,15 @@ __device__ __forceinline__ void deposit_group(T* __restrict__ grid, const Member
     const int ex = box[3] - i0 + 2, ey = box[4] - j0 + 2, ez = box[5] - k0 + 2;
     // extents are at most n + 1 <= 513 each, so the product fits in int64
     const int64_t vol64 = int64_t(ex) * ey * ez;
-    if (vol64 > tile_nodes<T>()) {
-        deposit_wave(grid, m, c, q, act);
+    if (vol64 > tile_nodes<A>()) {
+        deposit_wave(grid, m, c, q, act, scale);
         return;
     }
     const int vol = int(vol64);
-    for (int t = tid; t < vol; t += kParticleWG) tile[t] = T(0);
+    for (int t = tid; t < vol; t += kParticleWG) tile[t] = A(0);
     __syncthreads();
-    T val[8];
-    if (wave_runs(m, c, q, act, val)) {
+    A val[8];
+    if (wave_runs(m, c, q, act, val, scale)) {
         const int base = ((c.i - i0) * ey + (c.j - j0)) * ez + (c.k - k0);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -273,8 +290,8 @@ __device__ __forceinline__ void deposit_group(T* __restrict__ grid, const Member
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int eyz = ey * ez;
     for (int t = tid; t < vol; t += kParticleWG) {
-        const T v = tile[t];
-        if (v == T(0)) continue;
+        const A v = tile[t];
+        if (v == A(0)) continue;
         const int ti = t / eyz;
         const int r = t - ti * eyz;
         const int tj = r / ez;
@@ -303,7 +320,7 @@ constexpr int kGroupsPerCU = 4;
 // runs the opening (or merged) kick, then S drifts with a full kick of h in
 // the same potential between them; the closing half kick of h/2 is mode 1
 // after the step's Poisson solve.  Static baryons skip modes 0 and 1.
-template <typename T>
+template <typename T, bool DET>
 __global__ __launch_bounds__(kParticleWG) void k_particles(const MemberDev* __restrict__ mems,
                                                            int first, int mode, int kick) {
     const MemberDev& m = mems[first + blockIdx.y];
@@ -349,8 +366,13 @@ __global__ __launch_bounds__(kParticleWG) void k_particles(const MemberDev* __re
         }
         const T q = T(m.particle_mass * m.inv_dx * m.inv_dy * m.inv_dz);
         const CellW<T> c = cic<T>(x, y, z, m);
-        T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
-        deposit_group(grid, m, c, q, act);
+        if constexpr (DET) {
+            // fixed-point sums, turned into the real grid by k_fixed_to_real
+            deposit_group(m.rho_fx, m, c, q, act, m.fx_scale);
+        } else {
+            T* grid = static_cast<T*>(mode == 3 ? m.scratch : m.rho_b);
+            deposit_group(grid, m, c, q, act, 0.0);
+        }
         __syncthreads();  // the next chunk reuses the group's LDS box and tile
     }
 }
@@ -370,18 +392,58 @@ static int device_cus() {
     return cus;
 }
 
+// Deterministic deposit, second half: the fixed-point grid of each member of
+// the class becomes the real grid (rho_b, or scratch for `to_scratch`) and is
+// cleared.  With skip_static, members with static baryons keep their rho_b
+// (the step deposits nothing for them).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fixed_to_real(const MemberDev* __restrict__ mems,
+                                                       int first, int to_scratch, int skip_static) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    if (skip_static && m.static_baryons) return;
+    if (m.rho_fx == nullptr) return;
+    T* dst = static_cast<T*>(to_scratch ? m.scratch : m.rho_b);
+    const int64_t n = int64_t(m.nx) * m.ny * m.nz;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        const unsigned long long v = gldr(m.rho_fx, i);
+        gstr(dst, i, T(double((long long)v) * m.fx_inv));
+        gstr(m.rho_fx, i, 0ull);
+    }
+}
+
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
-                            KickMode kick) {
+                            KickMode kick, bool det) {
     if (max_np <= 0) return hipSuccess;
     const int64_t chunks = (max_np + kParticleWG - 1) / kParticleWG;
     const int64_t cap = int64_t(kGroupsPerCU) * device_cus();
     dim3 grid(unsigned(chunks < cap ? chunks : cap), unsigned(L.count));
+    const bool fx = det && mode != 1;   // mode 1 deposits nothing
+    if (prec) {
+        if (fx)
+            k_particles<double, true><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first,
+                                                                          mode, int(kick));
+        else
+            k_particles<double, false><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first,
+                                                                           mode, int(kick));
+    } else {
+        if (fx)
+            k_particles<float, true><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first,
+                                                                         mode, int(kick));
+        else
+            k_particles<float, false><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first,
+                                                                          mode, int(kick));
+    }
+    if (!fx) return hipGetLastError();
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    const dim3 cg(unsigned(4 * device_cus()), unsigned(L.count));
+    const int to_scratch = mode == 3 ? 1 : 0, skip_static = mode == 0 ? 1 : 0;
     if (prec)
-        k_particles<double><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first, mode,
-                                                                  int(kick));
+        k_fixed_to_real<double><<<cg, 256, 0, L.stream>>>(L.members, L.first, to_scratch,
+                                                          skip_static);
     else
-        k_particles<float><<<grid, kParticleWG, 0, L.stream>>>(L.members, L.first, mode,
-                                                                 int(kick));
+        k_fixed_to_real<float><<<cg, 256, 0, L.stream>>>(L.members, L.first, to_scratch,
+                                                         skip_static);
     return hipGetLastError();
 }
 

@@ -153,9 +153,11 @@ __device__ __forceinline__ int signed_mode(int i, int n) { return i < n / 2 ? i 
 // Large-argument branch of rotate(): FP64 sincos and product, rounded once.
 // Kept out of line: it is rarely taken and would otherwise be inlined into
 // every slot of every pass.
+// A non-finite argument (a non-finite potential, which the stability watch
+// reports) rotates by zero rather than reaching sincos.
 __device__ __noinline__ cplx<float> rotate_fp64(cplx<float> a, double r) {
     double s, c;
-    sincos(r, &s, &c);
+    sincos(__builtin_isfinite(r) ? r : 0.0, &s, &c);
     const double re = double(a.re), im = double(a.im);
     return cplx<float>{float(re * c - im * s), float(re * s + im * c)};
 }
@@ -187,7 +189,7 @@ __device__ __forceinline__ cplx<T> rotate(cplx<T> a, double arg) {
         return rotate_fp64(a, r);
     } else {
         double s, c;
-        sincos(r, &s, &c);
+        sincos(__builtin_isfinite(r) ? r : 0.0, &s, &c);
         return cmul(a, cplx<double>{c, s});
     }
 }
@@ -294,6 +296,34 @@ __device__ __forceinline__ void transform_tile(cplx<T>* data, const Strides& sd,
     store_slots<P, P::last()>(v, data, b, sd.st, ok, ln);
 }
 
+
+// ---------------------------------------------------------------------------
+// Stability watch (Sec. 3.5): the largest |x| over a lane's E values, reduced
+// over the wavefront and folded into slots[blockIdx.x % 64] by an unsigned
+// 64-bit atomic maximum of the FP64 bit pattern (the sign bit cleared, so a
+// NaN orders above +inf and is kept).  All lanes of the wavefront must call it.
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ void watch_max(unsigned long long* slots, const float* x) {
+    int u = 0;
+#pragma unroll
+    for (int s = 0; s < E; ++s) u = max(u, int(__float_as_uint(x[s]) & 0x7fffffffu));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) u = max(u, __shfl_xor(u, off));
+    if (__lane_id() == 0)
+        atomicMax(slots + (blockIdx.x & 63u),
+                  (unsigned long long)__double_as_longlong(double(__uint_as_float(unsigned(u)))));
+}
+template <int E>
+__device__ __forceinline__ void watch_max(unsigned long long* slots, const double* x) {
+    long long u = 0;
+#pragma unroll
+    for (int s = 0; s < E; ++s)
+        u = max(u, (long long)(__double_as_longlong(x[s]) & 0x7fffffffffffffffll));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) u = max(u, __shfl_xor(u, off));
+    if (__lane_id() == 0) atomicMax(slots + (blockIdx.x & 63u), (unsigned long long)u);
+}
 
 // ---------------------------------------------------------------------------
 // host-side helpers: dispatch on the axis length, grid and block shapes

@@ -155,11 +155,20 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
 #pragma unroll
     for (int s = 0; s < FP::E; ++s)
         if (ok) gstr(gphi, slot_elem<FP, FP::first()>(ln.t, s), phi[s]);
+    // lanes past the last pencil hold zeros here
+    watch_max<FP::E>(m.watch, phi);
     if constexpr (OP == kZPhiOnly) return;
     const double dt = gldr(m.dt, 0);
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
     const double c = -tau / m.eta;
     if constexpr (GEN) {
+        if (m.kappa != 0.0) {
+            // |psi|^2 before the kick: the self-interaction's CFL term
+            T r2[FP::E];
+#pragma unroll
+            for (int s = 0; s < FP::E; ++s) r2[s] = ok ? w[s].re * w[s].re + w[s].im * w[s].im : T(0);
+            watch_max<FP::E>(m.watch + 64, r2);
+        }
         kick_general<FP, T, MASK, KICK == kFullKick>(v, w, phi, m, bxy, bz, c, ln);
     } else {
 #pragma unroll

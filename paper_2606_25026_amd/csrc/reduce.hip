@@ -3,6 +3,8 @@
 // kernels.  Reductions are deterministic: a fixed number of work-groups, each
 // summing a fixed range in a fixed order, then one work-group summing the
 // partials in order -- no floating-point atomics.
+#include <cfloat>
+
 #include "wdm_internal.hpp"
 #include "fft_device.hpp"
 
@@ -155,6 +157,42 @@ __global__ void k_dt_auto(const MemberDev* __restrict__ mems, int first, double 
 
 hipError_t launch_dt_auto(const Launch& L, double zeta, double c_kin) {
     k_dt_auto<<<unsigned(L.count), 1, 0, L.stream>>>(L.members, L.first, zeta, c_kin);
+    return hipGetLastError();
+}
+
+// Stability check of a wdm_step call (Sec. 3.5): the largest |Phi| (and
+// |psi|^2) the call's P1 launches saw give dt_max = 0.5 min{c_kin dx_min^2 /
+// eta, 2 pi eta / max|Phi|, 2 pi eta / (|kappa| max|psi|^2)}; stab[0] keeps
+// the largest |dt| / dt_max since wdm_set_state, stab[1] is set once a
+// non-finite value was seen.  One wavefront per member; the watch slots are
+// cleared for the next call.
+__global__ __launch_bounds__(64) void k_stability(const MemberDev* __restrict__ mems, int first,
+                                                  double c_kin) {
+    const MemberDev& m = mems[first + blockIdx.x];
+    const int t = int(threadIdx.x);
+    long long a = (long long)m.watch[t], b = (long long)m.watch[64 + t];
+    m.watch[t] = 0ull;
+    m.watch[64 + t] = 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a = max(a, __shfl_xor(a, off));
+        b = max(b, __shfl_xor(b, off));
+    }
+    if (t != 0) return;
+    const double mp = __longlong_as_double(a), mr = __longlong_as_double(b);
+    if (!(mp <= DBL_MAX) || !(mr <= DBL_MAX)) {
+        m.stab[1] = 1.0;
+        return;
+    }
+    const double dx = fmin(m.lx / m.nx, fmin(m.ly / m.ny, m.lz / m.nz));
+    double tm = c_kin * dx * dx / m.eta;
+    if (mp > 0.0) tm = fmin(tm, kTwoPi * m.eta / mp);
+    if (m.kappa != 0.0 && mr > 0.0) tm = fmin(tm, kTwoPi * m.eta / (fabs(m.kappa) * mr));
+    m.stab[0] = fmax(m.stab[0], fabs(m.dt[0]) / (0.5 * tm));
+}
+
+hipError_t launch_stability(const Launch& L, double c_kin) {
+    k_stability<<<unsigned(L.count), 64, 0, L.stream>>>(L.members, L.first, c_kin);
     return hipGetLastError();
 }
 

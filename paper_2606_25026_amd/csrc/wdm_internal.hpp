@@ -60,7 +60,7 @@ struct MemberDev {
     int32_t nx, ny, nz;
     int32_t substeps;        // particle leapfrog sub-steps per step (>= 1)
     int32_t static_baryons;  // 1: particles never move and rho_b is kept between steps
-    int32_t pad0;
+    int32_t deterministic;   // 1: particles deposit through the fixed-point grid rho_fx
     double lx, ly, lz;
     double eta;        // hbar / m
     double four_pi_G;
@@ -82,6 +82,18 @@ struct MemberDev {
     // FP64 reduction staging
     double* partials;  // [kMaxPartials][kRedFields]
     double* results;   // [kRedFields]
+    // stability watch, written by every P1 launch: [0, 64) the largest |Phi|,
+    // [64, 128) the largest |psi|^2 (kicks with a self-interaction only), as
+    // FP64 bit patterns compared as unsigned integers (NaN above +inf), one
+    // slot per work-group index modulo 64; cleared by each check
+    unsigned long long* watch;
+    // [0] largest |dt| / dt_max (Sec. 3.5) over the steps checked since
+    // wdm_set_state, [1] 1 once a non-finite potential or density was seen
+    double* stab;
+    // deterministic deposit: 64-bit fixed-point accumulator grid (n cells;
+    // null unless deterministic) holding round(value * fx_scale)
+    unsigned long long* rho_fx;
+    double fx_scale, fx_inv;
 };
 
 constexpr int kRedFields = 11;
@@ -139,7 +151,7 @@ hipError_t launch_x_kinetic_energy(const Launch& L, int prec, int nx, int ny, in
 // mode 0: kick (tau) + drift (dt) + deposit; 1: kick only; 2: deposit only
 // into rho_b; 3: deposit only into scratch (as real grid).
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
-                            KickMode kick);
+                            KickMode kick, bool det = false);
 // Stable radix sort by Morton cell key of every member of a size class.
 hipError_t launch_particle_sort(const Launch& L, int64_t max_np, int nx, int ny, int nz);
 hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos_out,
@@ -185,6 +197,10 @@ hipError_t launch_set_dt(const Launch& L, double dt, int mode);
 // (all ones where absorb_alpha is 0).
 hipError_t launch_absorb_tables(const Launch& L);
 hipError_t launch_advance_time(const Launch& L, int64_t nsteps);
+// Stability check after a wdm_step call: folds the watch slots into stab
+// (|dt| / dt_max with dt_max = 0.5 min{c_kin dx^2 / eta, 2 pi eta / max|Phi|,
+// 2 pi eta / (|kappa| max|psi|^2)}, Sec. 3.5) and clears them.
+hipError_t launch_stability(const Launch& L, double c_kin);
 hipError_t launch_zero(hipStream_t s, void* p, size_t bytes);
 hipError_t launch_copy_complex(hipStream_t s, void* dst, const void* src, int64_t n,
                                int dst_prec, int src_prec);

@@ -16,6 +16,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libwdm.so"
 WDM_C64, WDM_C128 = 0, 1
 WDM_BARYON_DYNAMIC, WDM_BARYON_STATIC = 0, 1
 WDM_BOUNDARY_PERIODIC, WDM_BOUNDARY_VACUUM = 0, 1
+WDM_DETERMINISTIC_DEPOSIT, WDM_STRICT_CFL = 0x1, 0x2
 STATUS = {0: "WDM_OK", 1: "WDM_EINVAL", 2: "WDM_ENOMEM", 3: "WDM_EDEVICE", 4: "WDM_ESTATE",
           5: "WDM_EUNSTABLE", 6: "WDM_EUNSUPPORTED"}
 
@@ -42,7 +43,7 @@ class wdm_energy_t(C.Structure):
                 ("e_kin_particles", C.c_double), ("e_total", C.c_double),
                 ("momentum", C.c_double * 3), ("max_abs_phi", C.c_double), ("t", C.c_double),
                 ("dt", C.c_double), ("dt_auto", C.c_double), ("e_self", C.c_double),
-                ("max_rho", C.c_double), ("e_ext", C.c_double)]
+                ("max_rho", C.c_double), ("e_ext", C.c_double), ("cfl_ratio", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "momentum"}
@@ -111,11 +112,18 @@ _SIGS = {
 
 
 def load():
-    """Load libwdm.so; raises if the HIP build is missing."""
+    """Load libwdm.so; raises if the HIP build is missing.
+
+    torch is imported first: the library then binds to the HIP runtime torch
+    has loaded, so the process holds one runtime (loaded the other way round,
+    the library's runtime and torch's own copy would both be in the process
+    and the library's would find no device)."""
     global _lib
     if _lib is None:
         if not LIB_PATH.exists():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (see above)
+
         lib = C.CDLL(str(LIB_PATH))
         for name, (res, args) in _SIGS.items():
             f = getattr(lib, name)
@@ -159,11 +167,11 @@ def _cfg_array(configs):
 def make_config(n, L=1.0, hbar_over_m=1.0, four_pi_G=1.0, n_particles=0, particle_mass=0.0,
                 precision=WDM_C64, kappa=0.0, absorb_alpha=0.0, absorb_nb=50.0,
                 baryon_mode=0, nbody_substeps=1, boundary=0,
-                external_potential=0) -> wdm_config:
+                external_potential=0, flags=0) -> wdm_config:
     nx, ny, nz = (n, n, n) if isinstance(n, int) else n
     lx, ly, lz = (L, L, L) if isinstance(L, (int, float)) else L
     return wdm_config(nx, ny, nz, lx, ly, lz, hbar_over_m, four_pi_G, int(n_particles),
-                      float(particle_mass), precision, 0, float(kappa), float(absorb_alpha),
+                      float(particle_mass), precision, int(flags), float(kappa), float(absorb_alpha),
                       float(absorb_nb), int(baryon_mode), int(nbody_substeps), int(boundary),
                       int(external_potential))
 
