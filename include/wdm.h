@@ -260,6 +260,26 @@ wdm_status wdm_particles(wdm_plan* plan, int32_t member, float* pos_out, float* 
  * state unsynchronised: call wdm_set_state before stepping again. */
 wdm_status wdm_fft3d(wdm_plan* plan, int32_t member, int32_t inverse);
 
+/* Allocation-free variant of wdm_fft3d, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same 3D transform of a caller's buffer, with no
+ * plan and no workspace.  psi_in and psi_out (dev, [nx][ny][nz] complex64 for
+ * precision WDM_C64, complex128 for WDM_C128) may be the same buffer (in
+ * place) or must not overlap; psi_in is read, psi_out receives the forward
+ * (inverse = 0, unnormalised exp(-i k.x)) or inverse (inverse = 1, scaled by
+ * 1/N) transform; stream-ordered on hip_stream (NULL = null stream).
+ * Axis lengths as for wdm_config (at most 512 per axis).  The library's only
+ * device memory for it is a fixed 32 KB array per GPU (the descriptor and the
+ * three twiddle tables, rewritten by every call), held until the process
+ * ends; the first call on a device looks up that array's address, so make it
+ * once outside any capture.  It calls no hipMalloc or hipFree.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller.  Returns WDM_EUNSUPPORTED for other axis lengths, WDM_EINVAL
+ * for null pointers or a bad precision; nothing is launched then. */
+wdm_status wdm_fft3d_noalloc(const void* psi_in, void* psi_out, int32_t nx, int32_t ny, int32_t nz,
+                             int32_t precision, int32_t inverse, void* hip_stream);
+
 /* Replay captured HIP graphs of the merged step (default on).  Off: every
  * kernel is launched directly on the plan's stream.  Results are the same
  * either way; profiling always launches directly. */

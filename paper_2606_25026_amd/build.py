@@ -16,7 +16,7 @@ CSRC = HERE / "csrc"
 LIB = HERE / "libwdm.so"
 OBJ = HERE / "_build"
 SOURCES = ["passes_z.hip", "passes_y.hip", "passes_x.hip", "particles.hip", "reduce.hip",
-           "diag.hip", "isolated.hip", "corrector.hip", "spectral.hip", "capi.hip"]
+           "diag.hip", "isolated.hip", "corrector.hip", "spectral.hip", "fft_noalloc.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -84,6 +84,7 @@ _SIGS = {
     "wdm_set_external_potential": (C.c_int, [_vp, _i32, _vp]),
     "wdm_particles": (C.c_int, [_vp, _i32, _vp, _vp]),
     "wdm_fft3d": (C.c_int, [_vp, _i32, _i32]),
+    "wdm_fft3d_noalloc": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
     "wdm_set_sort_interval": (C.c_int, [_vp, _i32]),
     "wdm_use_graphs": (C.c_int, [_vp, _i32]),
     "wdm_autotune": (C.c_int, [_vp, _i32]),
@@ -245,6 +246,12 @@ def wdm_particles(plan, member, pos_out=None, vel_out=None):
 
 def wdm_fft3d(plan, member, inverse=False):
     _check(load().wdm_fft3d(plan, member, 1 if inverse else 0))
+
+
+def wdm_fft3d_noalloc(psi_in, psi_out, shape, precision=WDM_C64, inverse=False, stream=None):
+    nx, ny, nz = shape
+    _check(load().wdm_fft3d_noalloc(_ptr(psi_in), _ptr(psi_out), int(nx), int(ny), int(nz),
+                                    int(precision), 1 if inverse else 0, _stream(stream)))
 
 
 def wdm_set_sort_interval(plan, interval):
