@@ -82,28 +82,87 @@ def traffic_from_profiles(kernel: str, variant: int = 0):
 
 
 def cpu_baseline(wl, budget_s: float = 20.0):
+    """The FP64 oracle on the host cores over a bounded sample of the workload:
+    unmerged KDK steps with every core the process may use, then with one."""
     import oracle
 
-    cores = min(16, len(os.sched_getaffinity(0)))
-    oracle.set_threads(cores)
+    cores = len(os.sched_getaffinity(0))
     cfg = oracle.make_config((wl.n,) * 3, n_particles=wl.n_particles,
                              particle_mass=wl.particle_mass)
     pos = wl.pos.astype(np.float64)
     vel = wl.vel.astype(np.float64)
-    t = time.perf_counter()
-    oracle.kdk(cfg, wl.psi, pos, vel, nsteps=0, dt=wl.dt)   # initial potential only
-    setup = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.kdk(cfg, wl.psi, pos, vel, nsteps=1, dt=wl.dt)
-    one = time.perf_counter() - t - setup
-    steps = max(1, min(10, int(budget_s / max(one, 1e-3))))
-    t = time.perf_counter()
-    oracle.kdk(cfg, wl.psi, pos, vel, nsteps=steps, dt=wl.dt)
-    per = (time.perf_counter() - t - setup) / steps
+
+    def per_step(threads, budget):
+        oracle.set_threads(threads)
+        t = time.perf_counter()
+        oracle.kdk(cfg, wl.psi, pos, vel, nsteps=0, dt=wl.dt)   # initial potential only
+        setup = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.kdk(cfg, wl.psi, pos, vel, nsteps=1, dt=wl.dt)
+        one = time.perf_counter() - t - setup
+        steps = max(1, min(10, int(budget / max(one, 1e-3))))
+        if steps == 1:
+            return one, 1
+        t = time.perf_counter()
+        oracle.kdk(cfg, wl.psi, pos, vel, nsteps=steps, dt=wl.dt)
+        return (time.perf_counter() - t - setup) / steps, steps
+
+    per, steps = per_step(cores, budget_s)
+    per1, steps1 = per_step(1, budget_s)
     return {"value": wl.n ** 3 / per, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} unmerged FP64 KDK steps of the same {wl.n}^3 + "
                       f"{wl.n_particles}-particle halo (initial Poisson solve subtracted)",
-            "s_per_step": per}
+            "s_per_step": per,
+            "single_thread": {"value": wl.n ** 3 / per1, "unit": "cell-updates/s", "cores": 1,
+                              "s_per_step": per1,
+                              "sample": f"{steps1} unmerged FP64 KDK steps, one thread"}}
+
+
+def learned_cost(h, wl, args, dev, ms_per_step, every=8, blocks=16):
+    """Seconds per simulated time unit of the plain fine solve (this run's step
+    time over dt) and of the 2x-coarser solve with the learned corrector
+    attached (a correction every `every` coarse steps, inside the captured
+    block), from the same state restricted to the coarse grid.  The cost does
+    not depend on the weights' values: the network is randomly initialised."""
+    import torch
+
+    from paper_2606_25026_amd import wdm
+
+    nc = args.n // 2
+    coarse = wdm.Plan(wdm.make_config(nc, n_particles=wl.n_particles,
+                                      particle_mass=wl.particle_mass), device=dev)
+    net = wdm.Net(nc, device=dev)
+    rng = np.random.default_rng(0)
+    wdm.wdm_net_set_params(net.handle, (rng.standard_normal(wdm.wdm_net_param_count())
+                                        * 0.05).astype(np.float32))
+    wdm.wdm_net_set_scales(net.handle, 1.0, 1.0, 1e-3)
+    buf = torch.empty((nc,) * 3, dtype=torch.complex64, device=dev)
+    wdm.wdm_restrict(h, 0, coarse.handle, 0, buf)
+    p = v = None
+    if wl.n_particles:
+        p = torch.empty((wl.n_particles, 3), dtype=torch.float32, device=dev)
+        v = torch.empty_like(p)
+        wdm.wdm_particles(h, 0, p, v)
+    wdm.wdm_set_state(coarse.handle, 0, buf, p, v)
+    wdm.wdm_set_sort_interval(coarse.handle, args.sort_interval)
+    wdm.wdm_plan_attach_corrector(coarse.handle, net.handle, 0, every)
+    dt_c = 0.2 / nc ** 2
+    wdm.wdm_step(coarse.handle, every, dt_c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wdm.wdm_step(coarse.handle, every * blocks, dt_c)
+    torch.cuda.synchronize()
+    t_c = time.perf_counter() - t0
+    wdm.wdm_plan_attach_corrector(coarse.handle, None, 0, 0)
+    net.close()
+    coarse.close()
+    s_fine = ms_per_step * 1e-3 / wl.dt
+    s_learned = t_c / (every * blocks * dt_c)
+    return {"s_per_unit_fine": s_fine, "s_per_unit_learned": s_learned,
+            "ratio": s_fine / s_learned,
+            "sample": f"{blocks} blocks of {every} coarse {nc}^3 steps + correction (BF16 MFMA "
+                      f"3-layer conv) vs this run's {args.n}^3 step; weights random (cost does "
+                      "not depend on them)"}
 
 
 def bench_ensemble(args):
@@ -235,11 +294,13 @@ def bench_learned(args):
     """Learned coarse corrector: 128^3 coarse + corrector vs the 256^3 plain solve."""
     from paper_2606_25026_amd import learned
 
-    cfg = learned.LearnedConfig()
+    cfg = learned.LearnedConfig(horizon_checkpoints=(64, 256, 1024, 4096))
     if args.learned_small:
-        cfg = learned.LearnedConfig(n_fine=64, n_coarse=32, n_particles=10_000,
-                                    train_seeds=tuple(range(6)), windows=4,
-                                    heldout_seeds=(100, 101), epochs=30)
+        cfg = learned.LearnedConfig(n_fine=64, n_coarse=32, n_particles=2000,
+                                    train_seeds=tuple(range(6)), windows=6, pair_stride=16,
+                                    heldout_seeds=(100, 101), epochs=30, judge_steps=48,
+                                    lr=2e-3, k0_modes=4.0, rc=0.1,
+                                    horizon_checkpoints=(48, 256, 1024))
     res = learned.run(cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps({
         "metric": "seconds per simulated time unit: plain fine solve / (coarse + corrector)",
@@ -263,6 +324,8 @@ def main():
                     help="steps between particle re-sorts (the halo's fastest particles cross "
                          "about 0.1 cell in 128 steps at its dt)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the coarse + corrector timing of the learned path")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true",
@@ -405,6 +468,10 @@ def main():
     step_bytes = STEP_BYTES_PER_CELL * n3 + STEP_BYTES_PER_PARTICLE * wl.n_particles
     step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
 
+    learned_line = None
+    if args.boundary == "periodic" and not args.no_learned:
+        learned_line = learned_cost(h, wl, args, dev, ms_per_step)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("# timing the FP64 CPU oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -413,7 +480,7 @@ def main():
     base_workload = (f"coupled halo {args.n}^3 complex64 + {wl.n_particles} CIC "
                      "Plummer particles (GRF k0=16*2pi + soliton rc=0.05)")
     out = {
-        "metric": "grid cell-updates/s (KDK) at 256^3 c64 + % HBM roofline",
+        "metric": "grid cell-updates/s (KDK) at 256^3 c64 + % HBM roofline; learned vs plain s/unit-time",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -439,6 +506,7 @@ def main():
                   "roofline: HIP events around every launch over an equal profiled region",
         "profiled_region_ms_per_step": (elapsed_prof * 1e3 / args.steps) if elapsed_prof else None,
         "mass_drift": e1["mass"] / e0["mass"] - 1.0,
+        "learned": learned_line,
         "cpu_baseline": cpu,
     }
     if args.kappa != 0.0 or args.absorb_alpha != 0.0:

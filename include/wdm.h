@@ -344,6 +344,11 @@ wdm_status wdm_restrict(wdm_plan* fine, int32_t fine_member, wdm_plan* coarse,
 wdm_status wdm_power_spectrum(wdm_plan* plan, int32_t member, int32_t nbins, double* pk,
                               int64_t* counts);
 
+/* Field distance for the corrector's judge: out[0] = sum |psi - other|^2,
+ * out[1] = sum |other|^2 over the member's grid (other: dev, same shape and
+ * precision as psi), FP64 sums in a fixed order (host out; synchronises). */
+wdm_status wdm_distance(wdm_plan* plan, int32_t member, const void* other, double* out);
+
 /* ---- learned corrector ----------------------------------------------------
  * Not part of the paper's method: a network that corrects a 2x-coarser
  * split-step run toward the fine one every few coarse steps.
@@ -379,13 +384,39 @@ wdm_status wdm_net_backward(wdm_net* net, const float* dy);
 wdm_status wdm_net_mse_backward(wdm_net* net, const float* target, double* loss);
 /* One Adam step on the FP32 master parameters (bias-corrected). */
 wdm_status wdm_net_adam(wdm_net* net, double lr, double b1, double b2, double eps);
-/* Apply the corrector to a complex64 member of the same grid: inputs
- * (Re psi * s_psi, Im psi * s_psi, Phi * s_phi), psi += s_out * output, psi
- * rescaled to its previous FP64 mass, and the potential rebuilt from the
- * corrected state (particles redeposited).  The network and the plan must
- * share a stream. */
-wdm_status wdm_net_apply(wdm_net* net, wdm_plan* plan, int32_t member, double s_psi,
-                         double s_phi, double s_out);
+/* Normalisation held by the network (device scalars; all 1 at creation):
+ * inputs enter as (Re psi s_psi, Im psi s_psi, Phi s_phi), the network learns
+ * residuals divided by s_out (wdm_net_mse_backward compares its output with
+ * target / s_out) and a correction adds s_out times its output.  The forward
+ * pass scales its caller inputs x the same way. */
+wdm_status wdm_net_set_scales(wdm_net* net, double s_psi, double s_phi, double s_out);
+/* out[3] = (s_psi, s_phi, s_out) (host out; synchronises). */
+wdm_status wdm_net_get_scales(wdm_net* net, double* out);
+/* Scales from a training set of `count` pairs (host arrays of device
+ * pointers to wdm_net_pair outputs of the network's grid): s_psi = 1 / rms
+ * |psi|, s_phi = 1 / std(Phi), s_out = std of the residual's components
+ * (population moments, FP64 deterministic sums). */
+wdm_status wdm_net_fit_scales(wdm_net* net, const float* const* xs, const float* const* ys,
+                              int32_t count);
+/* A training pair from a complex64 member's synchronised state and a target
+ * field of the same grid (dev, complex64): x_out = (Re psi, Im psi, Phi) as f32
+ * [n^3][3], y_out = target - psi as f32 [n^3][2] (dev outs, channels last). */
+wdm_status wdm_net_pair(wdm_plan* plan, int32_t member, const void* target, float* x_out,
+                        float* y_out);
+/* Apply the corrector to a complex64 member of the network's grid: inputs
+ * from (psi, Phi) with the network's scales, psi += s_out * output, psi
+ * rescaled to its FP64 mass before the correction, and the potential rebuilt
+ * from the corrected state (moving particles redeposited), so the state is
+ * synchronised again.  The network and the plan must share a stream. */
+wdm_status wdm_net_apply(wdm_net* net, wdm_plan* plan, int32_t member);
+/* Attach the corrector to a plan: from now on wdm_step applies it to
+ * `member` after every `every` steps (counted across calls; 1 <= every <=
+ * 4096), as wdm_net_apply would between calls.  A run of `every` steps that
+ * starts at a correction boundary replays one captured graph holding the
+ * steps, the closing half kick and the correction.  net = NULL or every = 0
+ * detaches.  The network must stay alive while attached. */
+wdm_status wdm_plan_attach_corrector(wdm_plan* plan, wdm_net* net, int32_t member,
+                                     int32_t every);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* wdm_last_error(void);

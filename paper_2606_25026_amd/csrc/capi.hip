@@ -24,23 +24,32 @@ hipError_t conv_backward_weight(hipStream_t s, int layer, const uint16_t* dz,
                                 int n);
 int wgrad_row(int layer);
 hipError_t net_pack_input(hipStream_t s, const float* x, uint16_t* y, int64_t cells, int cin,
-                          int cp);
+                          int cp, const double* scales);
 hipError_t net_mse(hipStream_t s, const float* y, const float* t, uint16_t* dy, double* part,
-                   double* out, int64_t cells, int cout, int cp);
+                   double* out, int64_t cells, int cout, int cp, const double* s_out);
 hipError_t net_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int n, float lr,
                     float b1, float b2, float eps, float c1, float c2);
 hipError_t net_pack_weights(hipStream_t s, const float* w, uint16_t* fwd, uint16_t* bwd, int cin,
                             int cout, int cpin, int cpout);
-hipError_t net_state_inputs(hipStream_t s, const float* psi, const float* phi, float* x,
-                            int64_t cells, float s_psi, float s_phi);
-hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, float s_out,
-                           double* part, double* mass_before, double* mass_after);
+hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uint16_t* x0,
+                          int64_t cells, double* scal, double* part);
+hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
+                           double* part);
+hipError_t net_pair(hipStream_t s, const float* psi, const float* phi, const float* target,
+                    float* x, float* y, int64_t cells);
+hipError_t net_moments(hipStream_t s, const float* x, const float* y, int64_t cells, double* rows,
+                       bool first);
+hipError_t net_fit_scales(hipStream_t s, const double* rows, double count, double* scal);
+hipError_t net_set_scales(hipStream_t s, double* scal, double s_psi, double s_phi, double s_out);
+size_t net_moment_doubles();
 hipError_t net_unpack_grads(hipStream_t s, const float* sum, float* gw, float* gb, int cin,
                             int cout, int cpin, int row);
 hipError_t launch_restrict_modes(hipStream_t s, const void* fine, void* coarse, int nf, int nc,
                                  int prec);
 hipError_t launch_contrast(const Launch& L, int prec, int64_t n);
 hipError_t launch_shells(const Launch& L, int prec, int nbins, double* part, double* out);
+hipError_t launch_distance(const Launch& L, int prec, const void* other, int64_t n, double* part,
+                           double* out);
 size_t shells_partial_doubles();
 int64_t axis_tiles(int n, int64_t pencils, int prec);
 hipError_t launch_scale_complex(hipStream_t s, void* p, int64_t n, double scale, int prec);
@@ -208,7 +217,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         if (g.external_potential) m.ext = c.take(cells * rs);
         m.dt = c.take(4 * sizeof(double));
         m.results = c.take(kRedFields * sizeof(double));
-        m.watch = c.take(128 * sizeof(unsigned long long));
+        m.watch = c.take(2 * watch_slots(g.nx, g.ny) * sizeof(unsigned long long));
         m.stab = c.take(2 * sizeof(double));
         if (g.flags & WDM_DETERMINISTIC_DEPOSIT) m.rho_fx = c.take(cells * 8);
         const int64_t np = std::max<int64_t>(g.n_particles, 0);
@@ -289,6 +298,15 @@ struct wdm_plan {
     hipStream_t s_main = nullptr, s_aux = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t g_step[2] = {nullptr, nullptr};   // [0] opening half kick, [1] merged
+    // attached corrector (wdm_plan_attach_corrector): applied to member
+    // net_member after every `every` steps; corr_phase counts the steps since
+    // the last application.  g_block holds `every` steps, the closing half kick
+    // and the correction as one captured graph.
+    wdm_net* net = nullptr;
+    int32_t net_member = 0;
+    int32_t every = 0;
+    int64_t corr_phase = 0;
+    hipGraphExec_t g_block = nullptr;
 };
 
 namespace {
@@ -446,9 +464,9 @@ wdm_status check_stability(wdm_plan* p, int32_t member) {
 // Potential of a member's synchronised state (psi, particle positions): the
 // moving particles are deposited (static ones keep their deposit in rho_b)
 // and Poisson is solved, as wdm_set_state does.
-hipError_t rebuild_potential(wdm_plan* p, int32_t member) {
+hipError_t rebuild_potential(wdm_plan* p, int32_t member, hipStream_t s) {
     const wdm_config& c = p->cfg[member];
-    const Launch L = one(p, member);
+    const Launch L{s, p->table, p->dev_index[member], 1};
     if (c.n_particles > 0 && c.baryon_mode == WDM_BARYON_DYNAMIC) {
         const hipError_t e = launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det);
         if (e != hipSuccess) return e;
@@ -570,6 +588,7 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         m.partials = reinterpret_cast<double*>(ws + L.partials);
         m.results = reinterpret_cast<double*>(ws + ml.results);
         m.watch = reinterpret_cast<unsigned long long*>(ws + ml.watch);
+        m.watch_n = watch_slots(c.nx, c.ny);
         m.stab = reinterpret_cast<double*>(ws + ml.stab);
         if (c.flags & WDM_DETERMINISTIC_DEPOSIT) {
             // fixed point with round(value * 2^S): the largest possible node sum,
@@ -655,7 +674,8 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         if (launch_zero(p->stream, m.rho_b, size_t(cells) * (p->prec ? 8 : 4)) != hipSuccess ||
             launch_zero(p->stream, m.dt, 4 * sizeof(double)) != hipSuccess ||
             launch_zero(p->stream, m.results, kRedFields * sizeof(double)) != hipSuccess ||
-            launch_zero(p->stream, m.watch, 128 * sizeof(unsigned long long)) != hipSuccess ||
+            launch_zero(p->stream, m.watch, 2 * m.watch_n * sizeof(unsigned long long)) !=
+                hipSuccess ||
             launch_zero(p->stream, m.stab, 2 * sizeof(double)) != hipSuccess ||
             (m.rho_fx && launch_zero(p->stream, m.rho_fx, size_t(cells) * 8) != hipSuccess))
             return cleanup(WDM_EDEVICE, "plan initialisation failed");
@@ -688,6 +708,7 @@ wdm_status wdm_plan_destroy(wdm_plan* plan) {
     for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
     for (hipGraphExec_t g : plan->g_step)
         if (g) (void)hipGraphExecDestroy(g);
+    if (plan->g_block) (void)hipGraphExecDestroy(plan->g_block);
     for (hipEvent_t e : {plan->ev_in, plan->ev_out, plan->ev_fork, plan->ev_join})
         if (e) (void)hipEventDestroy(e);
     if (plan->s_main) (void)hipStreamDestroy(plan->s_main);
@@ -709,7 +730,7 @@ wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const flo
     HIPCHK(hipMemcpyAsync(m.psi, psi, size_t(n) * (p->prec ? 16 : 8), hipMemcpyDeviceToDevice,
                           p->stream));
     HIPCHK(launch_zero(p->stream, m.rho_b, size_t(n) * (p->prec ? 8 : 4)));
-    HIPCHK(launch_zero(p->stream, m.watch, 128 * sizeof(unsigned long long)));
+    HIPCHK(launch_zero(p->stream, m.watch, 2 * m.watch_n * sizeof(unsigned long long)));
     HIPCHK(launch_zero(p->stream, m.stab, 2 * sizeof(double)));
     if (c.n_particles > 0) {
         HIPCHK(launch_particle_upload(p->stream, m, pos, vel));
@@ -872,31 +893,67 @@ hipError_t capture_step(wdm_plan* p, int which) {
     return e;
 }
 
-}  // namespace
+hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t s);
+wdm_status check_net_for(wdm_net* net, wdm_plan* p, int32_t member);
 
-extern "C" {
+// Capture `every` steps, the closing half kick and the corrector as one graph.
+hipError_t capture_block(wdm_plan* p) {
+    if (p->g_block) return hipSuccess;
+    hipError_t e0 = ensure_streams(p);
+    if (e0 != hipSuccess) return e0;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->s_main, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int32_t i = 0; i < p->every && le == hipSuccess; ++i)
+        le = enqueue_step(p, p->s_main, p->s_aux, i == 0 ? kHalfKick : kFullKick);
+    if (le == hipSuccess) le = enqueue_close(p, p->s_main, p->every);
+    if (le == hipSuccess) le = enqueue_apply(p->net, p, p->net_member, p->s_main);
+    e = hipStreamEndCapture(p->s_main, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->g_block, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
 
-wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
-    if (!p) return fail(WDM_EINVAL, "null plan");
-    if (n < 0) return fail(WDM_EINVAL, "n must be >= 0");
-    if (!std::isfinite(dt)) return fail(WDM_EINVAL, "dt must be finite");
-    for (size_t i = 0; i < p->has_state.size(); ++i)
-        if (!p->has_state[i]) return fail(WDM_ESTATE, "wdm_set_state not called for every member");
-    if (n == 0) return WDM_OK;
+void drop_graphs(wdm_plan* p) {
+    for (hipGraphExec_t& g : p->g_step)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    if (p->g_block) {
+        (void)hipGraphExecDestroy(p->g_block);
+        p->g_block = nullptr;
+    }
+}
+
+// What follows a run of steps.
+enum After : int { kNoApply = 0, kApplyAfter = 1, kBlockGraph = 2 };
+
+// n steps: opening half kick, n - 1 merged steps, closing half kick, then the
+// corrector when `after` asks for it (kBlockGraph: the n = every steps and the
+// corrector replayed as the one block graph).
+wdm_status run_steps(wdm_plan* p, int64_t n, double dt, After after) {
     const bool graphs = p->use_graphs && !p->profiling;
     if (graphs) {
-        for (int w = 0; w < 2; ++w)
-            if (capture_step(p, w) != hipSuccess) {
-                p->use_graphs = false;   // capture unavailable: launch directly
-                (void)hipGetLastError();
-                return wdm_step(p, n, dt);
-            }
+        bool ok = true;
+        for (int w = 0; w < 2 && ok; ++w) ok = capture_step(p, w) == hipSuccess;
+        if (ok && after == kBlockGraph) ok = capture_block(p) == hipSuccess;
+        if (!ok) {
+            drop_graphs(p);
+            p->use_graphs = false;   // capture unavailable: launch directly
+            (void)hipGetLastError();
+            return run_steps(p, n, dt, after == kBlockGraph ? kApplyAfter : after);
+        }
     }
+    if (after == kBlockGraph && !graphs) after = kApplyAfter;
     // deterministic mode: each call starts from the synchronised state alone,
     // its potential rebuilt as wdm_set_state builds it, so a state saved
     // between calls and set again continues bit for bit
     if (p->det)
-        for (int32_t u = 0; u < int32_t(p->cfg.size()); ++u) HIPCHK(rebuild_potential(p, u));
+        for (int32_t u = 0; u < int32_t(p->cfg.size()); ++u)
+            HIPCHK(rebuild_potential(p, u, p->stream));
     // direct launches run on the caller's stream and fork the particle
     // kernel onto the auxiliary stream, as the captured graph does
     HIPCHK(ensure_streams(p));
@@ -910,19 +967,84 @@ wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
         HIPCHK(dt != 0.0 ? launch_set_dt(L, dt, 0) : launch_set_dt(L, 0.0, 1));
         if (c.absorb) HIPCHK(launch_absorb_tables(L));
     }
-    for (int64_t i = 0; i < n; ++i) {
-        if (resort_due(p)) HIPCHK(enqueue_sort(p, s));
-        if (graphs)
-            HIPCHK(hipGraphLaunch(p->g_step[i == 0 ? 0 : 1], s));
-        else
-            HIPCHK(enqueue_step(p, s, p->s_aux, i == 0 ? kHalfKick : kFullKick));
-        p->steps_done++;
+    if (after == kBlockGraph) {
+        // a re-sort due inside the block is done before it
+        bool due = false;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t k = p->steps_done + i;
+            due = due || (p->sort_interval > 0 && k > 0 && k % p->sort_interval == 0);
+        }
+        if (due) HIPCHK(enqueue_sort(p, s));
+        HIPCHK(hipGraphLaunch(p->g_block, s));
+        p->steps_done += n;
+    } else {
+        for (int64_t i = 0; i < n; ++i) {
+            if (resort_due(p)) HIPCHK(enqueue_sort(p, s));
+            if (graphs)
+                HIPCHK(hipGraphLaunch(p->g_step[i == 0 ? 0 : 1], s));
+            else
+                HIPCHK(enqueue_step(p, s, p->s_aux, i == 0 ? kHalfKick : kFullKick));
+            p->steps_done++;
+        }
+        HIPCHK(enqueue_close(p, s, n));
+        if (after == kApplyAfter) HIPCHK(enqueue_apply(p->net, p, p->net_member, s));
     }
-    HIPCHK(enqueue_close(p, s, n));
     if (graphs) {
         HIPCHK(hipEventRecord(p->ev_out, s));
         HIPCHK(hipStreamWaitEvent(p->stream, p->ev_out, 0));
     }
+    return WDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wdm_status wdm_step(wdm_plan* p, int64_t n, double dt) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    if (n < 0) return fail(WDM_EINVAL, "n must be >= 0");
+    if (!std::isfinite(dt)) return fail(WDM_EINVAL, "dt must be finite");
+    for (size_t i = 0; i < p->has_state.size(); ++i)
+        if (!p->has_state[i]) return fail(WDM_ESTATE, "wdm_set_state not called for every member");
+    if (n == 0) return WDM_OK;
+    if (!p->net) return run_steps(p, n, dt, kNoApply);
+    // with a corrector: runs of steps that end where a correction falls due
+    for (int64_t left = n; left > 0;) {
+        const int64_t k = std::min<int64_t>(left, p->every - p->corr_phase);
+        const bool due = p->corr_phase + k == p->every;
+        const After a = !due ? kNoApply : (p->corr_phase == 0 ? kBlockGraph : kApplyAfter);
+        if (wdm_status st = run_steps(p, k, dt, a)) return st;
+        p->corr_phase = due ? 0 : p->corr_phase + k;
+        left -= k;
+    }
+    return WDM_OK;
+}
+
+wdm_status wdm_plan_attach_corrector(wdm_plan* p, wdm_net* net, int32_t member, int32_t every) {
+    if (!p) return fail(WDM_EINVAL, "null plan");
+    if (!net || every == 0) {   // detach
+        if (p->g_block) {
+            (void)hipStreamSynchronize(p->stream);
+            (void)hipGraphExecDestroy(p->g_block);
+            p->g_block = nullptr;
+        }
+        p->net = nullptr;
+        p->every = 0;
+        p->corr_phase = 0;
+        return WDM_OK;
+    }
+    if (wdm_status st = check_member(p, member)) return st;
+    if (every < 1 || every > 4096) return fail(WDM_EINVAL, "every must be in [1, 4096]");
+    if (wdm_status st = check_net_for(net, p, member)) return st;
+    if (p->g_block) {
+        (void)hipStreamSynchronize(p->stream);
+        (void)hipGraphExecDestroy(p->g_block);
+        p->g_block = nullptr;
+    }
+    p->net = net;
+    p->net_member = member;
+    p->every = every;
+    p->corr_phase = 0;
     return WDM_OK;
 }
 
@@ -967,13 +1089,6 @@ hipError_t tune_launch(wdm_plan* p, const Launch& L, const SizeClass& c, int slo
     }
 }
 
-void drop_graphs(wdm_plan* p) {
-    for (hipGraphExec_t& g : p->g_step)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
-}
 
 }  // namespace
 
@@ -1347,8 +1462,8 @@ int net_params() {
 int net_kpad(int cp) { return (27 * cp + 15) / 16 * 16; }
 
 struct NetLayout {
-    size_t params, grads, am, av, wf[3], wb[3], x0, a1, a2, y, dy, d2, d1, xin, wpart, wsum[3],
-        dpart, scal, total;
+    size_t params, grads, am, av, wf[3], wb[3], x0, a1, a2, y, dy, d2, d1, wpart, wsum[3], dpart,
+        mom, scal, total;
 };
 
 NetLayout net_layout(int n) {
@@ -1371,10 +1486,10 @@ NetLayout net_layout(int n) {
     L.dy = c.take(cells * 4 * 2);
     L.d2 = c.take(cells * 16 * 2);
     L.d1 = c.take(cells * 16 * 2);
-    L.xin = c.take(cells * 3 * 4);
     L.wpart = c.take(size_t(kNetWgradBlocks) * 16 * wgrad_row(1) * 4);
     for (int l = 0; l < kNetLayers; ++l) L.wsum[l] = c.take(16 * wgrad_row(l) * 4);
     L.dpart = c.take(1024 * 8);
+    L.mom = c.take(net_moment_doubles() * 8);
     L.scal = c.take(8 * 8);
     L.total = (c.off + kAlign - 1) / kAlign * kAlign;
     return L;
@@ -1410,11 +1525,9 @@ hipError_t net_repack(wdm_net* net) {
     return e;
 }
 
-hipError_t net_run_forward(wdm_net* net, const float* x, float* y) {
-    hipStream_t s = net->stream;
-    hipError_t e;
-    if ((e = net_pack_input(s, x, net->at<uint16_t>(net->L.x0), net->cells, 3, 4)) != hipSuccess)
-        return e;
+// The three layers from the packed input x0 (bf16 [cells][4]) on stream s.
+hipError_t net_run_layers(wdm_net* net, hipStream_t s) {
+    hipError_t e = hipSuccess;
     const uint16_t* in[3] = {net->at<uint16_t>(net->L.x0), net->at<uint16_t>(net->L.a1),
                              net->at<uint16_t>(net->L.a2)};
     void* out[3] = {net->at<uint16_t>(net->L.a1), net->at<uint16_t>(net->L.a2),
@@ -1426,6 +1539,18 @@ hipError_t net_run_forward(wdm_net* net, const float* x, float* y) {
                                     net->n)) != hipSuccess)
             return e;
     }
+    return e;
+}
+
+// Forward pass of caller inputs x (f32 [cells][3], scaled by the network's
+// input scales while packed); y (optional) receives the output.
+hipError_t net_run_forward(wdm_net* net, const float* x, float* y) {
+    hipStream_t s = net->stream;
+    hipError_t e;
+    if ((e = net_pack_input(s, x, net->at<uint16_t>(net->L.x0), net->cells, 3, 4,
+                            net->at<double>(net->L.scal) + 3)) != hipSuccess)
+        return e;
+    if ((e = net_run_layers(net, s)) != hipSuccess) return e;
     if (y && y != net->at<float>(net->L.y))
         e = hipMemcpyAsync(y, net->at<float>(net->L.y), size_t(net->cells) * 2 * 4,
                            hipMemcpyDeviceToDevice, s);
@@ -1494,6 +1619,7 @@ wdm_status wdm_net_create(int32_t n, void* workspace, size_t bytes, void* hip_st
     for (size_t off : {L.params, L.grads, L.am, L.av})   // separately aligned sections
         if (e == hipSuccess) e = launch_zero(net->stream, net->ws + off, size_t(P) * 4);
     if (e == hipSuccess) e = net_repack(net);
+    if (e == hipSuccess) e = net_set_scales(net->stream, net->at<double>(L.scal), 1.0, 1.0, 1.0);
     if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
     if (e != hipSuccess) {
         delete net;
@@ -1547,7 +1673,8 @@ wdm_status wdm_net_forward(wdm_net* net, const float* x, float* y) {
 wdm_status wdm_net_backward(wdm_net* net, const float* dy) {
     if (!net || !dy) return fail(WDM_EINVAL, "null argument");
     if (!net->have_forward) return fail(WDM_ESTATE, "backward needs a forward pass first");
-    HIPCHK(net_pack_input(net->stream, dy, net->at<uint16_t>(net->L.dy), net->cells, 2, 4));
+    HIPCHK(net_pack_input(net->stream, dy, net->at<uint16_t>(net->L.dy), net->cells, 2, 4,
+                          nullptr));
     HIPCHK(net_run_backward(net));
     return WDM_OK;
 }
@@ -1557,7 +1684,7 @@ wdm_status wdm_net_mse_backward(wdm_net* net, const float* target, double* loss)
     if (!net->have_forward) return fail(WDM_ESTATE, "backward needs a forward pass first");
     double* scal = net->at<double>(net->L.scal);
     HIPCHK(net_mse(net->stream, net->at<float>(net->L.y), target, net->at<uint16_t>(net->L.dy),
-                   net->at<double>(net->L.dpart), scal, net->cells, 2, 4));
+                   net->at<double>(net->L.dpart), scal, net->cells, 2, 4, scal + 5));
     HIPCHK(net_run_backward(net));
     if (loss) {
         HIPCHK(hipMemcpyAsync(loss, scal, sizeof(double), hipMemcpyDeviceToHost, net->stream));
@@ -1580,28 +1707,93 @@ wdm_status wdm_net_adam(wdm_net* net, double lr, double b1, double b2, double ep
     return WDM_OK;
 }
 
-wdm_status wdm_net_apply(wdm_net* net, wdm_plan* p, int32_t member, double s_psi, double s_phi,
-                         double s_out) {
+wdm_status wdm_net_set_scales(wdm_net* net, double s_psi, double s_phi, double s_out) {
     if (!net) return fail(WDM_EINVAL, "null network");
-    if (wdm_status st = check_member(p, member)) return st;
+    if (!(std::isfinite(s_psi) && std::isfinite(s_phi) && std::isfinite(s_out)))
+        return fail(WDM_EINVAL, "scales must be finite");
+    HIPCHK(net_set_scales(net->stream, net->at<double>(net->L.scal), s_psi, s_phi, s_out));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_get_scales(wdm_net* net, double* out) {
+    if (!net || !out) return fail(WDM_EINVAL, "null argument");
+    double sc[8];
+    HIPCHK(hipMemcpyAsync(sc, net->at<double>(net->L.scal), sizeof(sc), hipMemcpyDeviceToHost,
+                          net->stream));
+    HIPCHK(hipStreamSynchronize(net->stream));
+    for (int i = 0; i < 3; ++i) out[i] = sc[3 + i];
+    return WDM_OK;
+}
+
+wdm_status wdm_net_fit_scales(wdm_net* net, const float* const* xs, const float* const* ys,
+                              int32_t count) {
+    if (!net || !xs || !ys || count < 1) return fail(WDM_EINVAL, "need count >= 1 pairs");
+    for (int32_t i = 0; i < count; ++i)
+        if (!xs[i] || !ys[i]) return fail(WDM_EINVAL, "null pair buffer");
+    double* rows = net->at<double>(net->L.mom);
+    for (int32_t i = 0; i < count; ++i)
+        HIPCHK(net_moments(net->stream, xs[i], ys[i], net->cells, rows, i == 0));
+    HIPCHK(net_fit_scales(net->stream, rows, double(count) * double(net->cells),
+                          net->at<double>(net->L.scal)));
+    return WDM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The corrector on a member's synchronised state, on stream s: network inputs
+// from (psi, Phi) with the network's scales, the three layers, psi += s_out y,
+// psi rescaled to its FP64 mass before the correction, and the potential
+// rebuilt from the corrected state (moving particles redeposited).
+hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t s) {
+    const MemberDev& m = p->host[p->dev_index[member]];
+    float* psi = static_cast<float*>(m.psi);
+    double* scal = net->at<double>(net->L.scal);
+    double* part = net->at<double>(net->L.dpart);
+    hipError_t e;
+    if ((e = net_state_pack(s, psi, static_cast<const float*>(m.phi),
+                            net->at<uint16_t>(net->L.x0), net->cells, scal, part)) != hipSuccess)
+        return e;
+    if ((e = net_run_layers(net, s)) != hipSuccess) return e;
+    if ((e = net_apply_delta(s, psi, net->at<float>(net->L.y), net->cells, scal, part)) !=
+        hipSuccess)
+        return e;
+    return rebuild_potential(p, member, s);
+}
+
+// Checks shared by wdm_net_apply and wdm_plan_attach_corrector.
+wdm_status check_net_for(wdm_net* net, wdm_plan* p, int32_t member) {
     const wdm_config& c = p->cfg[member];
     if (p->prec != WDM_C64) return fail(WDM_EUNSUPPORTED, "corrector needs a complex64 plan");
     if (c.nx != net->n || c.ny != net->n || c.nz != net->n)
         return fail(WDM_EINVAL, "network grid differs from the member's grid");
-    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
     if (net->stream != p->stream) return fail(WDM_EINVAL, "network and plan must share a stream");
+    return WDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wdm_status wdm_net_apply(wdm_net* net, wdm_plan* p, int32_t member) {
+    if (!net) return fail(WDM_EINVAL, "null network");
+    if (wdm_status st = check_member(p, member)) return st;
+    if (wdm_status st = check_net_for(net, p, member)) return st;
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    HIPCHK(enqueue_apply(net, p, member, p->stream));
+    return WDM_OK;
+}
+
+wdm_status wdm_net_pair(wdm_plan* p, int32_t member, const void* target, float* x_out,
+                        float* y_out) {
+    if (wdm_status st = check_member(p, member)) return st;
+    if (!target || !x_out || !y_out) return fail(WDM_EINVAL, "null argument");
+    if (p->prec != WDM_C64) return fail(WDM_EUNSUPPORTED, "training pairs need a complex64 plan");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
     const MemberDev& m = p->host[p->dev_index[member]];
-    const Launch L = one(p, member);
-    float* psi = static_cast<float*>(m.psi);
-    HIPCHK(net_state_inputs(p->stream, psi, static_cast<const float*>(m.phi),
-                            net->at<float>(net->L.xin), net->cells, float(s_psi), float(s_phi)));
-    HIPCHK(net_run_forward(net, net->at<float>(net->L.xin), nullptr));
-    double* scal = net->at<double>(net->L.scal);
-    HIPCHK(net_apply_delta(p->stream, psi, net->at<float>(net->L.y), net->cells, float(s_out),
-                           net->at<double>(net->L.dpart), scal + 1, scal + 2));
-    // the corrected psi needs its own potential: redeposit the particles and
-    // re-solve Poisson so the state is synchronised again
-    HIPCHK(rebuild_potential(p, member));
+    HIPCHK(net_pair(p->stream, static_cast<const float*>(m.psi), static_cast<const float*>(m.phi),
+                    static_cast<const float*>(target), x_out, y_out, cells_of(p->cfg[member])));
     return WDM_OK;
 }
 
@@ -1639,6 +1831,23 @@ wdm_status wdm_restrict(wdm_plan* fine, int32_t fmember, wdm_plan* coarse, int32
         HIPCHK(launch_axis_fft(LC, prec, c.nx, c.ny, c.nz, ax, true, 1));
     HIPCHK(hipMemcpyAsync(psi_out, mc.scratch, size_t(cells_of(c)) * cs, hipMemcpyDeviceToDevice,
                           coarse->stream));
+    return WDM_OK;
+}
+
+wdm_status wdm_distance(wdm_plan* p, int32_t member, const void* other, double* out) {
+    if (wdm_status st = check_member(p, member)) return st;
+    if (!other || !out) return fail(WDM_EINVAL, "null argument");
+    if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
+    const MemberDev& m = p->host[p->dev_index[member]];
+    // 2 x 1024 partials and the two sums at the end of the reduction staging
+    double* part = m.partials;
+    double* res = m.partials + 2 * 1024;
+    HIPCHK(launch_distance(one(p, member), p->prec, other, cells_of(p->cfg[member]), part, res));
+    double host[2];
+    HIPCHK(hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    out[0] = host[0];
+    out[1] = host[1];
     return WDM_OK;
 }
 

@@ -20,6 +20,7 @@
 namespace wdm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bf16, round to nearest even (NaN kept quiet)
@@ -59,64 +60,140 @@ enum ConvEpi : int {
     kEpiMaskBf16 = 2,       // out = bf16(acc * (mask > 0)), CPOUT channels (backward data)
 };
 
+// Convolution tile: 4 x 4 x 16 output cells (x, y, z) per work-group pass.
+// The input brick with its one-cell periodic halo, 6 x 6 x 18 cells, is staged
+// in LDS once and read by all 27 taps; each wavefront owns the four 16-cell z
+// segments of one x row (N = 16 cells per MFMA) and keeps its A operand (the
+// layer's weights, all K chunks) in registers for the whole launch.
+constexpr int kCTX = 4, kCTY = 4, kCTZ = 16;
+constexpr int kCBX = kCTX + 2, kCBY = kCTY + 2, kCBZ = kCTZ + 2;
+constexpr int kCBrick = kCBX * kCBY * kCBZ;
+
+// v in [-1, n + kCTZ]: periodic index in [0, n)
+__device__ __forceinline__ int wrap_edge(int v, int n) { return (v + n) % n; }
+
 // in: bf16 [cells][CPIN]; wmat: bf16 [16][KC*16] (rows >= COUT zero);
 // out: see ConvEpi.  COUT real output channels (<= 16), CPOUT padded store width.
+// Persistent: work-group b handles tiles b, b + gridDim.x, ...
 template <int CPIN, int COUT, int CPOUT, int EPI>
-__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in,
+__global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in,
                                               const uint16_t* __restrict__ wmat,
                                               const float* __restrict__ bias,
                                               const uint16_t* __restrict__ mask, void* out,
                                               int n) {
     constexpr int KC = (27 * CPIN + 15) / 16;
-    const Grid3 g{n};
-    const int lane = int(threadIdx.x) & 63;
-    const int wave = int(threadIdx.x) >> 6;
-    const int64_t seg = int64_t(blockIdx.x) * 4 + wave;      // 16-cell segment along z
-    const int64_t base = seg * 16;
-    if (base >= g.cells()) return;                            // uniform per wavefront
-    const int col = lane & 15;                                // output cell within segment
-    const int kq = lane >> 4;                                 // which 4-wide k group
-    const int64_t cell = base + col;
-    const bool valid = cell < g.cells();   // the last segment may be partial
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-    for (int ch = 0; ch < KC; ++ch) {
-        const int k0 = ch * 16 + 4 * kq;
-        // A: 4 consecutive weights of row (lane % 16)
-        const bf16x4 a = ld_bf16x4(wmat, int64_t(col) * (KC * 16) + k0);
-        bf16x4 b = {0, 0, 0, 0};
-        if (valid && k0 < 27 * CPIN) {
-            const int tap = k0 / CPIN, c = k0 % CPIN;
-            b = ld_bf16x4(in, g.shift(cell, tap) * CPIN + c);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    if (!valid) return;
-    // lane holds out[cell][4*kq + q]
-    const int m0 = 4 * kq;
-    if constexpr (EPI == kEpiBiasF32) {
-        float* o = static_cast<float*>(out);
+    constexpr int W8 = CPIN / 4;                 // 8-byte words per brick cell
+    __shared__ __align__(16) uint64_t brick[kCBrick * W8];
+    const int tid = int(threadIdx.x);
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 15;                   // z within the segment; A row
+    const int kq = lane >> 4;                    // which 4-wide k group
+    bf16x4 a[KC];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (m0 + q < COUT) gstr(o, cell * COUT + m0 + q, acc[q] + gldr(bias, m0 + q));
-    } else {
-        if (m0 >= CPOUT) return;
-        uint16_t* o = static_cast<uint16_t*>(out);
-        uint16_t r[4];
+    for (int ch = 0; ch < KC; ++ch) a[ch] = ld_bf16x4(wmat, int64_t(col) * (KC * 16) + ch * 16 + 4 * kq);
+    const int tx = (n + kCTX - 1) / kCTX, ty = (n + kCTY - 1) / kCTY, tz = (n + kCTZ - 1) / kCTZ;
+    const int64_t ntiles = int64_t(tx) * ty * tz;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int iz = int(t % tz);
+        const int64_t r = t / tz;
+        const int x0 = int(r / ty) * kCTX, y0 = int(r % ty) * kCTY, z0 = iz * kCTZ;
+        // stage the brick: every load issued before the LDS stores
+        if constexpr (W8 == 4) {
+            constexpr int kChunks = kCBrick * 2;  // 16-byte halves of 32-byte cells
+            constexpr int kIt = (kChunks + 255) / 256;
+            u32x4 v[kIt];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float v = acc[q];
-            if constexpr (EPI == kEpiBiasReluBf16) {
-                v = m0 + q < COUT ? fmaxf(v + gldr(bias, m0 + q), 0.0f) : 0.0f;
-            } else {
-                const float mk = bf2f(gldr(mask, cell * CPOUT + m0 + q));
-                v = (m0 + q < COUT && mk > 0.0f) ? v : 0.0f;
+            for (int k = 0; k < kIt; ++k) {
+                const int i = tid + k * 256;
+                v[k] = u32x4{0u, 0u, 0u, 0u};
+                if (i < kChunks) {
+                    const int c = i >> 1, bz = c % kCBZ, rr = c / kCBZ, by = rr % kCBY,
+                              bx = rr / kCBY;
+                    const int64_t g = (int64_t(wrap_edge(x0 + bx - 1, n)) * n +
+                                       wrap_edge(y0 + by - 1, n)) * n + wrap_edge(z0 + bz - 1, n);
+                    v[k] = *(const WDM_GAS u32x4*)(in + g * 16 + (i & 1) * 8);
+                }
             }
-            r[q] = f2bf(v);
+#pragma unroll
+            for (int k = 0; k < kIt; ++k) {
+                const int i = tid + k * 256;
+                if (i < kChunks) reinterpret_cast<u32x4*>(brick)[i] = v[k];
+            }
+        } else {
+            constexpr int kIt = (kCBrick * W8 + 255) / 256;
+            uint64_t v[kIt];
+#pragma unroll
+            for (int k = 0; k < kIt; ++k) {
+                const int i = tid + k * 256;
+                v[k] = 0ull;
+                if (i < kCBrick * W8) {
+                    const int c = i / W8, bz = c % kCBZ, rr = c / kCBZ, by = rr % kCBY,
+                              bx = rr / kCBY;
+                    const int64_t g = (int64_t(wrap_edge(x0 + bx - 1, n)) * n +
+                                       wrap_edge(y0 + by - 1, n)) * n + wrap_edge(z0 + bz - 1, n);
+                    v[k] = *(const WDM_GAS uint64_t*)(in + g * CPIN + (i % W8) * 4);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kIt; ++k) {
+                const int i = tid + k * 256;
+                if (i < kCBrick * W8) brick[i] = v[k];
+            }
         }
-        const uint64_t packed = uint64_t(r[0]) | (uint64_t(r[1]) << 16) |
-                                (uint64_t(r[2]) << 32) | (uint64_t(r[3]) << 48);
-        gstr(reinterpret_cast<uint64_t*>(o), (cell * CPOUT + m0) / 4, packed);
+        __syncthreads();
+        // wavefront `wave` owns x = x0 + wave, y = y0 + s (s < 4), z = z0 + col
+        f32x4 acc[kCTY];
+#pragma unroll
+        for (int s2 = 0; s2 < kCTY; ++s2) acc[s2] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < KC; ++ch) {
+            const int k0 = ch * 16 + 4 * kq;
+            const int tap = k0 / CPIN, c = k0 % CPIN;
+            const bool live = k0 < 27 * CPIN;
+            const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
+            const int cell0 = ((wave + dx) * kCBY + dy) * kCBZ + col + dz;
+#pragma unroll
+            for (int s2 = 0; s2 < kCTY; ++s2) {
+                const uint64_t bw = live ? brick[(cell0 + s2 * kCBZ) * W8 + c / 4] : 0ull;
+                bf16x4 b;
+                __builtin_memcpy(&b, &bw, sizeof(b));
+                acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ch], b, acc[s2], 0, 0, 0);
+            }
+        }
+        // epilogue: lane holds out[cell][4*kq + q] of each segment
+        const int x = x0 + wave, z = z0 + col, m0 = 4 * kq;
+#pragma unroll
+        for (int s2 = 0; s2 < kCTY; ++s2) {
+            const int y = y0 + s2;
+            if (x >= n || y >= n || z >= n) continue;
+            const int64_t cell = (int64_t(x) * n + y) * n + z;
+            if constexpr (EPI == kEpiBiasF32) {
+                float* o = static_cast<float*>(out);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (m0 + q < COUT) gstr(o, cell * COUT + m0 + q, acc[s2][q] + gldr(bias, m0 + q));
+            } else {
+                if (m0 >= CPOUT) continue;
+                uint16_t rq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v = acc[s2][q];
+                    if constexpr (EPI == kEpiBiasReluBf16) {
+                        v = m0 + q < COUT ? fmaxf(v + gldr(bias, m0 + q), 0.0f) : 0.0f;
+                    } else {
+                        const float mk = bf2f(gldr(mask, cell * CPOUT + m0 + q));
+                        v = (m0 + q < COUT && mk > 0.0f) ? v : 0.0f;
+                    }
+                    rq[q] = f2bf(v);
+                }
+                const uint64_t packed = uint64_t(rq[0]) | (uint64_t(rq[1]) << 16) |
+                                        (uint64_t(rq[2]) << 32) | (uint64_t(rq[3]) << 48);
+                gstr(reinterpret_cast<uint64_t*>(static_cast<uint16_t*>(out)),
+                     (cell * CPOUT + m0) / 4, packed);
+            }
+        }
+        __syncthreads();   // the next tile reuses the brick
     }
 }
 
@@ -204,23 +281,33 @@ __global__ void k_sum_partials(const float* __restrict__ part, float* __restrict
 
 // ---- packing, loss, Adam ---------------------------------------------------
 
-// f32 [cells][cin] -> bf16 [cells][CP] (zero padded)
+// f32 [cells][cin] -> bf16 [cells][CP] (zero padded), channel c scaled by
+// sc[sidx[c]] (the network's input scales, device doubles) when sc is given.
 __global__ void k_pack_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t cells,
-                            int cin, int cp) {
+                            int cin, int cp, const double* __restrict__ sc) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= cells * cp) return;
     const int64_t p = i / cp;
     const int c = int(i % cp);
-    gstr(y, i, c < cin ? f2bf(gldr(x, p * cin + c)) : uint16_t(0));
+    float v = 0.0f;
+    if (c < cin) {
+        v = gldr(x, p * cin + c);
+        if (sc) v *= float(gldr(sc, c < 2 ? 0 : 1));
+    }
+    gstr(y, i, f2bf(v));
 }
 
 // loss = sum (y - t)^2 / count in FP64 partials; dy = bf16(2 (y - t) / count)
 // stored with CP channels.
+// The target t is in the network's output units divided by s_out (read
+// from *s_out when given): the network learns t / s_out.
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t,
                                              uint16_t* __restrict__ dy, double* __restrict__ part,
-                                             int64_t cells, int cout, int cp) {
+                                             int64_t cells, int cout, int cp,
+                                             const double* __restrict__ s_out) {
     __shared__ double red[256];
     const int64_t count = cells * cout;
+    const float inv = s_out ? float(1.0 / gldr(s_out, 0)) : 1.0f;
     double s = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < cells * cp;
          i += int64_t(gridDim.x) * 256) {
@@ -228,7 +315,7 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
         const int c = int(i % cp);
         float g = 0.0f;
         if (c < cout) {
-            const float d = gldr(y, p * cout + c) - gldr(t, p * cout + c);
+            const float d = gldr(y, p * cout + c) - gldr(t, p * cout + c) * inv;
             s += double(d) * double(d);
             g = float(2.0 * double(d) / double(count));
         }
@@ -289,53 +376,149 @@ __global__ void k_pack_weights(const float* __restrict__ w, uint16_t* __restrict
     }
 }
 
-// Corrector inputs from a member's state: x[p] = (Re psi * s_psi, Im psi * s_psi,
-// Phi * s_phi) as f32 [cells][3].
-__global__ void k_state_inputs(const float* __restrict__ psi, const float* __restrict__ phi,
-                               float* __restrict__ x, int64_t cells, float s_psi, float s_phi) {
-    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (p >= cells) return;
-    gstr(x, 3 * p + 0, gldr(psi, 2 * p) * s_psi);
-    gstr(x, 3 * p + 1, gldr(psi, 2 * p + 1) * s_psi);
-    gstr(x, 3 * p + 2, gldr(phi, p) * s_phi);
-}
+// ---- the corrector applied to a member's state -------------------------------
+// scal (device doubles): [1] mass before, [2] mass after, [3] s_psi, [4] s_phi,
+// [5] s_out.  Reductions: a fixed grid of kMassBlocks work-groups, each
+// summing a fixed range into its own FP64 partial (deterministic).
+constexpr int kMassBlocks = 1024;
 
-// psi += s_out * dpsi (dpsi f32 [cells][2])
-__global__ void k_apply_delta(float* __restrict__ psi, const float* __restrict__ d, int64_t cells,
-                              float s_out) {
-    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (p >= cells) return;
-    gstr(psi, 2 * p, gldr(psi, 2 * p) + s_out * gldr(d, 2 * p));
-    gstr(psi, 2 * p + 1, gldr(psi, 2 * p + 1) + s_out * gldr(d, 2 * p + 1));
-}
-
-// psi *= sqrt(target / current) with both masses in FP64 (device scalars)
-__global__ void k_rescale(float* __restrict__ psi, int64_t cells, const double* __restrict__ before,
-                          const double* __restrict__ after) {
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= 2 * cells) return;
-    const double a = gldr(after, 0);
-    const float s = a > 0.0 ? float(sqrt(gldr(before, 0) / a)) : 1.0f;
-    gstr(psi, i, gldr(psi, i) * s);
-}
-
-// FP64 sum of |psi|^2 (partials per block).
-__global__ __launch_bounds__(256) void k_mass_partials(const float* __restrict__ psi,
-                                                       double* __restrict__ part, int64_t cells) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < cells;
-         p += int64_t(gridDim.x) * 256) {
-        const double re = gldr(psi, 2 * p), im = gldr(psi, 2 * p + 1);
-        s += re * re + im * im;
-    }
-    red[threadIdx.x] = s;
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), red[0]);
+    return red[0];
+}
+
+// Network inputs from the state, x0[p] = bf16(Re psi s_psi, Im psi s_psi,
+// Phi s_phi, 0), and the FP64 partials of |psi|^2 (mass before the correction).
+__global__ __launch_bounds__(256) void k_state_pack(const float* __restrict__ psi,
+                                                    const float* __restrict__ phi,
+                                                    uint16_t* __restrict__ x0, int64_t cells,
+                                                    const double* __restrict__ scal,
+                                                    double* __restrict__ part) {
+    __shared__ double red[256];
+    const float sp = float(gldr(scal, 3)), sf = float(gldr(scal, 4));
+    double m = 0.0;
+    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < cells;
+         p += int64_t(gridDim.x) * 256) {
+        const float re = gldr(psi, 2 * p), im = gldr(psi, 2 * p + 1);
+        m += double(re) * double(re) + double(im) * double(im);
+        const uint64_t packed = uint64_t(f2bf(re * sp)) | (uint64_t(f2bf(im * sp)) << 16) |
+                                (uint64_t(f2bf(gldr(phi, p) * sf)) << 32);
+        gstr(reinterpret_cast<uint64_t*>(x0), p, packed);
+    }
+    const double t = block_sum(m, red);
+    if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), t);
+}
+
+// psi += s_out * d (d f32 [cells][2], the network output) and the FP64
+// partials of the corrected |psi|^2.
+__global__ __launch_bounds__(256) void k_apply_delta(float* __restrict__ psi,
+                                                     const float* __restrict__ d, int64_t cells,
+                                                     const double* __restrict__ scal,
+                                                     double* __restrict__ part) {
+    __shared__ double red[256];
+    const float so = float(gldr(scal, 5));
+    double m = 0.0;
+    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < cells;
+         p += int64_t(gridDim.x) * 256) {
+        const float re = gldr(psi, 2 * p) + so * gldr(d, 2 * p);
+        const float im = gldr(psi, 2 * p + 1) + so * gldr(d, 2 * p + 1);
+        gstr(psi, 2 * p, re);
+        gstr(psi, 2 * p + 1, im);
+        m += double(re) * double(re) + double(im) * double(im);
+    }
+    const double t = block_sum(m, red);
+    if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), t);
+}
+
+// scal[slot] = sum of the kMassBlocks partials, in order.
+__global__ void k_sum_mass(const double* __restrict__ part, double* __restrict__ scal, int slot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < kMassBlocks; ++i) s += gldr(part, i);
+    gstr(scal, slot, s);
+}
+
+// psi *= sqrt(mass before / mass after), the factor formed in FP64.
+__global__ void k_rescale(float* __restrict__ psi, int64_t cells, const double* __restrict__ scal) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= 2 * cells) return;
+    const double a = gldr(scal, 2);
+    const float f = a > 0.0 ? float(sqrt(gldr(scal, 1) / a)) : 1.0f;
+    gstr(psi, i, gldr(psi, i) * f);
+}
+
+// ---- training data --------------------------------------------------------
+// A training pair from a member's state and a target field: x[p] = (Re psi,
+// Im psi, Phi), y[p] = (Re, Im)(target - psi), both f32 channels last.
+__global__ void k_pair(const float* __restrict__ psi, const float* __restrict__ phi,
+                       const float* __restrict__ target, float* __restrict__ x,
+                       float* __restrict__ y, int64_t cells) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= cells) return;
+    const float re = gldr(psi, 2 * p), im = gldr(psi, 2 * p + 1);
+    gstr(x, 3 * p + 0, re);
+    gstr(x, 3 * p + 1, im);
+    gstr(x, 3 * p + 2, gldr(phi, p));
+    gstr(y, 2 * p + 0, gldr(target, 2 * p) - re);
+    gstr(y, 2 * p + 1, gldr(target, 2 * p + 1) - im);
+}
+
+// Moments of a training set, accumulated pair by pair into per-work-group
+// FP64 rows (first pair: overwrite): [0] sum x0^2 + x1^2, [1] sum x2,
+// [2] sum x2^2, [3] sum y0^2 + y1^2, [4] sum y0 + y1.
+constexpr int kMoments = 5;
+__global__ __launch_bounds__(256) void k_moments(const float* __restrict__ x,
+                                                 const float* __restrict__ y, int64_t cells,
+                                                 double* __restrict__ rows, int first) {
+    __shared__ double red[256];
+    double a[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < cells;
+         p += int64_t(gridDim.x) * 256) {
+        const double x0 = gldr(x, 3 * p), x1 = gldr(x, 3 * p + 1), x2 = gldr(x, 3 * p + 2);
+        const double y0 = gldr(y, 2 * p), y1 = gldr(y, 2 * p + 1);
+        a[0] += x0 * x0 + x1 * x1;
+        a[1] += x2;
+        a[2] += x2 * x2;
+        a[3] += y0 * y0 + y1 * y1;
+        a[4] += y0 + y1;
+    }
+    for (int f = 0; f < kMoments; ++f) {
+        const double t = block_sum(a[f], red);
+        if (threadIdx.x == 0) {
+            double* r = rows + int64_t(blockIdx.x) * kMoments + f;
+            gstr(r, 0, first ? t : gldr(r, 0) + t);
+        }
+        __syncthreads();
+    }
+}
+
+// Scales from the moments of `count` cells (count = pairs x cells per pair):
+// s_psi = 1 / rms|psi|, s_phi = 1 / std(Phi), s_out = std of the residual's
+// components (population moments); written to scal[3..5].
+__global__ void k_fit_scales(const double* __restrict__ rows, double count,
+                             double* __restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double m[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < kMassBlocks; ++b)
+        for (int f = 0; f < kMoments; ++f) m[f] += gldr(rows, int64_t(b) * kMoments + f);
+    const double ms = m[0] / count;
+    const double mean_phi = m[1] / count, var_phi = m[2] / count - mean_phi * mean_phi;
+    const double mean_y = m[4] / (2.0 * count), var_y = m[3] / (2.0 * count) - mean_y * mean_y;
+    gstr(scal, 3, ms > 0.0 ? 1.0 / sqrt(ms) : 1.0);
+    gstr(scal, 4, var_phi > 0.0 ? 1.0 / sqrt(var_phi) : 1.0);
+    gstr(scal, 5, var_y > 0.0 ? sqrt(var_y) : 1e-30);
+}
+
+__global__ void k_set_scales(double* __restrict__ scal, double s_psi, double s_phi, double s_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    gstr(scal, 3, s_psi);
+    gstr(scal, 4, s_phi);
+    gstr(scal, 5, s_out);
 }
 
 // Gradient sums [16][ROW] (k = tap * CPIN + c, bias at column KC*16) to the
@@ -363,9 +546,20 @@ hipError_t net_unpack_grads(hipStream_t s, const float* sum, float* gw, float* g
     return hipGetLastError();
 }
 
+// Persistent grid of the convolution: one work-group per tile up to eight per
+// compute unit.
 static unsigned conv_blocks(int n) {
-    const int64_t segs = (int64_t(n) * n * n + 15) / 16;
-    return unsigned((segs + 3) / 4);
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, c = 0;
+        cus = (hipGetDevice(&dev) == hipSuccess &&
+               hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+               c > 0) ? c : 256;
+    }
+    const int64_t tiles = int64_t((n + kCTX - 1) / kCTX) * ((n + kCTY - 1) / kCTY) *
+                          ((n + kCTZ - 1) / kCTZ);
+    const int64_t cap = int64_t(8) * cus;
+    return unsigned(tiles < cap ? tiles : cap);
 }
 
 hipError_t conv_forward_layer(hipStream_t s, int layer, const uint16_t* in, const uint16_t* w,
@@ -410,15 +604,15 @@ hipError_t conv_backward_weight(hipStream_t s, int layer, const uint16_t* dz,
 }
 
 hipError_t net_pack_input(hipStream_t s, const float* x, uint16_t* y, int64_t cells, int cin,
-                          int cp) {
-    k_pack_bf16<<<unsigned((cells * cp + 255) / 256), 256, 0, s>>>(x, y, cells, cin, cp);
+                          int cp, const double* scales) {
+    k_pack_bf16<<<unsigned((cells * cp + 255) / 256), 256, 0, s>>>(x, y, cells, cin, cp, scales);
     return hipGetLastError();
 }
 
 hipError_t net_mse(hipStream_t s, const float* y, const float* t, uint16_t* dy, double* part,
-                   double* out, int64_t cells, int cout, int cp) {
+                   double* out, int64_t cells, int cout, int cp, const double* s_out) {
     constexpr int kBlocks = 1024;
-    k_mse<<<kBlocks, 256, 0, s>>>(y, t, dy, part, cells, cout, cp);
+    k_mse<<<kBlocks, 256, 0, s>>>(y, t, dy, part, cells, cout, cp, s_out);
     k_sum_f64<<<1, 64, 0, s>>>(part, out, kBlocks);
     return hipGetLastError();
 }
@@ -436,23 +630,43 @@ hipError_t net_pack_weights(hipStream_t s, const float* w, uint16_t* fwd, uint16
     return hipGetLastError();
 }
 
-hipError_t net_state_inputs(hipStream_t s, const float* psi, const float* phi, float* x,
-                            int64_t cells, float s_psi, float s_phi) {
-    k_state_inputs<<<unsigned((cells + 255) / 256), 256, 0, s>>>(psi, phi, x, cells, s_psi, s_phi);
+hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uint16_t* x0,
+                          int64_t cells, double* scal, double* part) {
+    k_state_pack<<<kMassBlocks, 256, 0, s>>>(psi, phi, x0, cells, scal, part);
+    k_sum_mass<<<1, 64, 0, s>>>(part, scal, 1);
     return hipGetLastError();
 }
 
-hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, float s_out,
-                           double* part, double* mass_before, double* mass_after) {
-    constexpr int kBlocks = 1024;
-    k_mass_partials<<<kBlocks, 256, 0, s>>>(psi, part, cells);
-    k_sum_f64<<<1, 64, 0, s>>>(part, mass_before, kBlocks);
-    k_apply_delta<<<unsigned((cells + 255) / 256), 256, 0, s>>>(psi, d, cells, s_out);
-    k_mass_partials<<<kBlocks, 256, 0, s>>>(psi, part, cells);
-    k_sum_f64<<<1, 64, 0, s>>>(part, mass_after, kBlocks);
-    k_rescale<<<unsigned((2 * cells + 255) / 256), 256, 0, s>>>(psi, cells, mass_before,
-                                                                mass_after);
+hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
+                           double* part) {
+    k_apply_delta<<<kMassBlocks, 256, 0, s>>>(psi, d, cells, scal, part);
+    k_sum_mass<<<1, 64, 0, s>>>(part, scal, 2);
+    k_rescale<<<unsigned((2 * cells + 255) / 256), 256, 0, s>>>(psi, cells, scal);
     return hipGetLastError();
 }
+
+hipError_t net_pair(hipStream_t s, const float* psi, const float* phi, const float* target,
+                    float* x, float* y, int64_t cells) {
+    k_pair<<<unsigned((cells + 255) / 256), 256, 0, s>>>(psi, phi, target, x, y, cells);
+    return hipGetLastError();
+}
+
+hipError_t net_moments(hipStream_t s, const float* x, const float* y, int64_t cells, double* rows,
+                       bool first) {
+    k_moments<<<kMassBlocks, 256, 0, s>>>(x, y, cells, rows, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t net_fit_scales(hipStream_t s, const double* rows, double count, double* scal) {
+    k_fit_scales<<<1, 64, 0, s>>>(rows, count, scal);
+    return hipGetLastError();
+}
+
+hipError_t net_set_scales(hipStream_t s, double* scal, double s_psi, double s_phi, double s_out) {
+    k_set_scales<<<1, 64, 0, s>>>(scal, s_psi, s_phi, s_out);
+    return hipGetLastError();
+}
+
+size_t net_moment_doubles() { return size_t(kMassBlocks) * kMoments; }
 
 }  // namespace wdm

@@ -299,30 +299,36 @@ __device__ __forceinline__ void transform_tile(cplx<T>* data, const Strides& sd,
 
 // ---------------------------------------------------------------------------
 // Stability watch (Sec. 3.5): the largest |x| over a lane's E values, reduced
-// over the wavefront and folded into slots[blockIdx.x % 64] by an unsigned
-// 64-bit atomic maximum of the FP64 bit pattern (the sign bit cleared, so a
-// NaN orders above +inf and is kept).  All lanes of the wavefront must call it.
+// over the wavefront (DPP) and folded into the wavefront's own slot of the
+// member's watch array by an unsigned 64-bit atomic maximum of the FP64 bit
+// pattern (the sign bit cleared, so a NaN orders above +inf and is kept).  No
+// two wavefronts of a launch share a slot, so the atomics never contend.  All
+// lanes of the wavefront must call it.
 // ---------------------------------------------------------------------------
-template <int E>
-__device__ __forceinline__ void watch_max(unsigned long long* slots, const float* x) {
-    int u = 0;
-#pragma unroll
-    for (int s = 0; s < E; ++s) u = max(u, int(__float_as_uint(x[s]) & 0x7fffffffu));
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) u = max(u, __shfl_xor(u, off));
-    if (__lane_id() == 0)
-        atomicMax(slots + (blockIdx.x & 63u),
-                  (unsigned long long)__double_as_longlong(double(__uint_as_float(unsigned(u)))));
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_max_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(
+    unsigned long long);
+
+__device__ __forceinline__ void watch_store(unsigned long long* slots, int64_t n,
+                                            unsigned long long bits) {
+    const int64_t w = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (__lane_id() == 0 && w < n) atomicMax(slots + w, bits);
 }
 template <int E>
-__device__ __forceinline__ void watch_max(unsigned long long* slots, const double* x) {
-    long long u = 0;
+__device__ __forceinline__ void watch_max(unsigned long long* slots, int64_t n, const float* x) {
+    unsigned int u = 0;
+#pragma unroll
+    for (int s = 0; s < E; ++s) u = max(u, __float_as_uint(x[s]) & 0x7fffffffu);
+    u = __ockl_wfred_max_u32(u);
+    watch_store(slots, n, (unsigned long long)__double_as_longlong(double(__uint_as_float(u))));
+}
+template <int E>
+__device__ __forceinline__ void watch_max(unsigned long long* slots, int64_t n, const double* x) {
+    unsigned long long u = 0;
 #pragma unroll
     for (int s = 0; s < E; ++s)
-        u = max(u, (long long)(__double_as_longlong(x[s]) & 0x7fffffffffffffffll));
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) u = max(u, __shfl_xor(u, off));
-    if (__lane_id() == 0) atomicMax(slots + (blockIdx.x & 63u), (unsigned long long)u);
+        u = max(u, (unsigned long long)__double_as_longlong(x[s]) & 0x7fffffffffffffffull);
+    watch_store(slots, n, __ockl_wfred_max_u64(u));
 }
 
 // ---------------------------------------------------------------------------

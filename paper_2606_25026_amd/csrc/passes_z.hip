@@ -156,7 +156,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     for (int s = 0; s < FP::E; ++s)
         if (ok) gstr(gphi, slot_elem<FP, FP::first()>(ln.t, s), phi[s]);
     // lanes past the last pencil hold zeros here
-    watch_max<FP::E>(m.watch, phi);
+    watch_max<FP::E>(m.watch, m.watch_n, phi);
     if constexpr (OP == kZPhiOnly) return;
     const double dt = gldr(m.dt, 0);
     const double tau = (KICK == kFullKick) ? dt : 0.5 * dt;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
             T r2[FP::E];
 #pragma unroll
             for (int s = 0; s < FP::E; ++s) r2[s] = ok ? w[s].re * w[s].re + w[s].im * w[s].im : T(0);
-            watch_max<FP::E>(m.watch + 64, r2);
+            watch_max<FP::E>(m.watch + m.watch_n, m.watch_n, r2);
         }
         kick_general<FP, T, MASK, KICK == kFullKick>(v, w, phi, m, bxy, bz, c, ln);
     } else {

@@ -164,22 +164,33 @@ hipError_t launch_dt_auto(const Launch& L, double zeta, double c_kin) {
 // |psi|^2) the call's P1 launches saw give dt_max = 0.5 min{c_kin dx_min^2 /
 // eta, 2 pi eta / max|Phi|, 2 pi eta / (|kappa| max|psi|^2)}; stab[0] keeps
 // the largest |dt| / dt_max since wdm_set_state, stab[1] is set once a
-// non-finite value was seen.  One wavefront per member; the watch slots are
+// non-finite value was seen.  One work-group per member; the watch slots are
 // cleared for the next call.
-__global__ __launch_bounds__(64) void k_stability(const MemberDev* __restrict__ mems, int first,
-                                                  double c_kin) {
+__global__ __launch_bounds__(256) void k_stability(const MemberDev* __restrict__ mems, int first,
+                                                   double c_kin) {
+    __shared__ unsigned long long red[2][256];
     const MemberDev& m = mems[first + blockIdx.x];
     const int t = int(threadIdx.x);
-    long long a = (long long)m.watch[t], b = (long long)m.watch[64 + t];
-    m.watch[t] = 0ull;
-    m.watch[64 + t] = 0ull;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        a = max(a, __shfl_xor(a, off));
-        b = max(b, __shfl_xor(b, off));
+    unsigned long long a = 0ull, b = 0ull;
+    for (int64_t i = t; i < m.watch_n; i += 256) {
+        a = max(a, m.watch[i]);
+        b = max(b, m.watch[m.watch_n + i]);
+        m.watch[i] = 0ull;
+        m.watch[m.watch_n + i] = 0ull;
+    }
+    red[0][t] = a;
+    red[1][t] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] = max(red[0][t], red[0][t + w]);
+            red[1][t] = max(red[1][t], red[1][t + w]);
+        }
+        __syncthreads();
     }
     if (t != 0) return;
-    const double mp = __longlong_as_double(a), mr = __longlong_as_double(b);
+    const double mp = __longlong_as_double((long long)red[0][0]);
+    const double mr = __longlong_as_double((long long)red[1][0]);
     if (!(mp <= DBL_MAX) || !(mr <= DBL_MAX)) {
         m.stab[1] = 1.0;
         return;
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(64) void k_stability(const MemberDev* __restrict__ 
 }
 
 hipError_t launch_stability(const Launch& L, double c_kin) {
-    k_stability<<<unsigned(L.count), 64, 0, L.stream>>>(L.members, L.first, c_kin);
+    k_stability<<<unsigned(L.count), 256, 0, L.stream>>>(L.members, L.first, c_kin);
     return hipGetLastError();
 }
 

@@ -129,4 +129,63 @@ hipError_t launch_shells(const Launch& L, int prec, int nbins, double* part, dou
 
 size_t shells_partial_doubles() { return size_t(kPkBlocks) * 2 * kPkMaxBins + 2 * kPkMaxBins; }
 
+// FP64 partials of sum |psi - other|^2 and sum |other|^2 (the judge's field
+// distance) into part[2 b], part[2 b + 1] over a fixed grid of work-groups,
+// then their ordered sums into out[0], out[1].
+constexpr int kDistBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_distance(const MemberDev* __restrict__ mems, int first,
+                                                  const cplx<T>* __restrict__ other, int64_t n,
+                                                  double* __restrict__ part) {
+    __shared__ double red[2][256];
+    const MemberDev& m = mems[first];
+    const cplx<T>* psi = static_cast<const cplx<T>*>(m.psi);
+    double d = 0.0, o = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        const cplx<T> a = gld(psi, i), b = gld(other, i);
+        const double dr = double(a.re) - double(b.re), di = double(a.im) - double(b.im);
+        d += dr * dr + di * di;
+        o += double(b.re) * double(b.re) + double(b.im) * double(b.im);
+    }
+    red[0][threadIdx.x] = d;
+    red[1][threadIdx.x] = o;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        gstr(part, 2 * int64_t(blockIdx.x), red[0][0]);
+        gstr(part, 2 * int64_t(blockIdx.x) + 1, red[1][0]);
+    }
+}
+
+__global__ void k_distance_finish(const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double d = 0.0, o = 0.0;
+    for (int b = 0; b < kDistBlocks; ++b) {
+        d += gldr(part, 2 * b);
+        o += gldr(part, 2 * b + 1);
+    }
+    gstr(out, 0, d);
+    gstr(out, 1, o);
+}
+
+hipError_t launch_distance(const Launch& L, int prec, const void* other, int64_t n, double* part,
+                           double* out) {
+    if (prec)
+        k_distance<double><<<kDistBlocks, 256, 0, L.stream>>>(
+            L.members, L.first, static_cast<const cplx<double>*>(other), n, part);
+    else
+        k_distance<float><<<kDistBlocks, 256, 0, L.stream>>>(
+            L.members, L.first, static_cast<const cplx<float>*>(other), n, part);
+    k_distance_finish<<<1, 64, 0, L.stream>>>(part, out);
+    return hipGetLastError();
+}
+
 }  // namespace wdm

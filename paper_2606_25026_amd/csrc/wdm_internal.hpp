@@ -82,11 +82,13 @@ struct MemberDev {
     // FP64 reduction staging
     double* partials;  // [kMaxPartials][kRedFields]
     double* results;   // [kRedFields]
-    // stability watch, written by every P1 launch: [0, 64) the largest |Phi|,
-    // [64, 128) the largest |psi|^2 (kicks with a self-interaction only), as
-    // FP64 bit patterns compared as unsigned integers (NaN above +inf), one
-    // slot per work-group index modulo 64; cleared by each check
+    // stability watch, written by every P1 launch: [0, watch_n) the largest
+    // |Phi|, [watch_n, 2 watch_n) the largest |psi|^2 (kicks with a
+    // self-interaction only), as FP64 bit patterns compared as unsigned
+    // integers (NaN above +inf), one slot per wavefront of the launch (no two
+    // wavefronts share a slot); cleared by each check
     unsigned long long* watch;
+    int64_t watch_n;
     // [0] largest |dt| / dt_max (Sec. 3.5) over the steps checked since
     // wdm_set_state, [1] 1 once a non-finite potential or density was seen
     double* stab;
@@ -197,6 +199,9 @@ hipError_t launch_set_dt(const Launch& L, double dt, int mode);
 // (all ones where absorb_alpha is 0).
 hipError_t launch_absorb_tables(const Launch& L);
 hipError_t launch_advance_time(const Launch& L, int64_t nsteps);
+// Slots of the stability watch per member: at least the wavefronts of any P1
+// launch (one pencil or more per wavefront).
+inline int64_t watch_slots(int nx, int ny) { return int64_t(nx) * ny + 1024; }
 // Stability check after a wdm_step call: folds the watch slots into stab
 // (|dt| / dt_max with dt_max = 0.5 min{c_kin dx^2 / eta, 2 pi eta / max|Phi|,
 // 2 pi eta / (|kappa| max|psi|^2)}, Sec. 3.5) and clears them.

@@ -216,14 +216,15 @@ def plane_wave_box(n: int = 32, seed: int = 0, steps: int = 100) -> Workload:
 
 def coupled_halo(n: int = 256, n_particles: int = 1_000_000, seed: int = 0, rc: float = 0.05,
                  rho_c: float = 50.0, L: float = 1.0, plummer_a: float = 0.03,
-                 mass_fraction: float = 0.1, steps: int = 1000) -> Workload:
-    """GRF (k0 = 16 * 2 pi / L) + soliton halo with a Plummer sphere of baryons.
+                 mass_fraction: float = 0.1, steps: int = 1000, k0_modes: float = 16.0) -> Workload:
+    """GRF (k0 = k0_modes * 2 pi / L, 16 in the workloads) + soliton halo with a
+    Plummer sphere of baryons.
 
     The particles' total mass is ``mass_fraction`` of the wave mass; one
     generator stream feeds the field first and the particles second.
     """
     rng = np.random.default_rng(seed)
-    psi = grf_soliton(n, L=L, k0=16.0 * TWO_PI / L, rc=rc, rho_c=rho_c, rng=rng)
+    psi = grf_soliton(n, L=L, k0=k0_modes * TWO_PI / L, rc=rc, rho_c=rho_c, rng=rng)
     mw = wave_mass(psi, L)
     pos = vel = None
     mp = 0.0

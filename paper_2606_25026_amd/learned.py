@@ -1,18 +1,22 @@
-"""Learned coarse-grid corrector workload: data generation, training and the
-P(k) judge with fallback, sequenced over libwdm entry points.
+"""Learned coarse-grid corrector workload: training-pair generation, training,
+the P(k) judge and the fine-solve fallback, sequenced over libwdm entry points.
 
 Every computation runs in the library's kernels (fine and coarse KDK steps,
-spectral restriction, network forward/backward/Adam, correction, shell power
-spectra); this module only orders the calls and keeps tensors alive.
+spectral restriction, training pairs and their normalisation, network
+forward/backward/Adam, the correction inside the coarse plan's captured step,
+shell power spectra); this module orders the calls, keeps tensors alive and
+compares scalars.
 
 Workload (the defaults): fine 256^3 and coarse 128^3 periodic boxes of the
 coupled-halo generator (GRF k0 = 16 * 2 pi + soliton, Plummer baryons carrying
 0.1 of the wave mass, particles in both runs), dt_f = 0.2 dx_f^2 and
 dt_c = 0.2 dx_c^2 = 4 dt_f.  A training pair is (restricted fine state at t0,
-advanced 8 coarse steps) -> (restricted fine state at t0 + 8 dt_c); the
-network learns the residual.  The judge runs 64 coarse steps (8 corrections)
-and compares the shell power spectrum of the density contrast with the plain
-fine solve over shells 1..nc/2-1.
+advanced `every` coarse steps) -> (restricted fine state at t0 + every dt_c);
+the network learns the residual.  Window starts are spread along the judged
+horizon.  The judge runs `judge_steps` coarse steps (a correction every
+`every` steps) and compares the shell power spectrum of the density contrast
+with the plain fine solve over shells 1..nc/2-1; above `threshold` the fine
+solve is used instead (fallback).
 """
 from __future__ import annotations
 
@@ -32,6 +36,7 @@ class LearnedConfig:
     n_particles: int = 1_000_000
     train_seeds: tuple = tuple(range(20))
     windows: int = 10
+    pair_stride: int = 8          # coarse steps between training-window starts
     heldout_seeds: tuple = tuple(range(100, 110))
     every: int = 8                # coarse steps between corrections
     judge_steps: int = 64         # coarse steps in the judged run
@@ -39,6 +44,9 @@ class LearnedConfig:
     lr: float = 1e-3
     threshold: float = 0.02       # P(k) error above which the fine solve is used
     init_scale: float = 0.05
+    horizon_checkpoints: tuple = ()   # coarse steps at which to report the no-net error
+    k0_modes: float = 16.0        # generator: GRF scale k0 = k0_modes * 2 pi / L
+    rc: float = 0.05              # generator: soliton core radius
     seed: int = 0
     extra: dict = field(default_factory=dict)
 
@@ -49,6 +57,12 @@ def _torch():
     return torch
 
 
+def halo(cfg, seed):
+    """The coupled-halo field and particles of one seed on the fine grid."""
+    return inputs.coupled_halo(n=cfg.n_fine, n_particles=cfg.n_particles, seed=seed, rc=cfg.rc,
+                               k0_modes=cfg.k0_modes)
+
+
 def _state(wl, device):
     torch = _torch()
     psi = torch.from_numpy(wl.psi.astype(np.complex64)).to(device)
@@ -57,8 +71,16 @@ def _state(wl, device):
     return psi, pos, vel
 
 
+def pk_error(pk_c, pk_f, nbins):
+    """Relative L2 distance of two shell spectra over shells 1 .. nbins-1."""
+    b = slice(1, nbins)
+    d = pk_c[b] - pk_f[b]
+    return float(math.sqrt(np.sum(d * d) / np.sum(pk_f[b] ** 2)))
+
+
 class Pipeline:
-    """A fine and a coarse single-member plan on one stream, plus buffers."""
+    """A fine and a coarse single-member plan and the corrector network, on
+    one stream, plus buffers."""
 
     def __init__(self, cfg: LearnedConfig, particle_mass: float, device="cuda"):
         torch = _torch()
@@ -69,14 +91,16 @@ class Pipeline:
                              device=device)
         self.coarse = wdm.Plan(wdm.make_config(nc, n_particles=npart,
                                                particle_mass=particle_mass), device=device)
+        self.net = wdm.Net(nc, device=device)
         self.dt_f = 0.2 / nf ** 2
         self.dt_c = 0.2 / nc ** 2
         self.ratio = int(round(self.dt_c / self.dt_f))
         self.buf_c = torch.empty((nc,) * 3, dtype=torch.complex64, device=device)
-        self.phi_c = torch.empty((nc,) * 3, dtype=torch.float32, device=device)
         self.pos = torch.empty((max(npart, 1), 3), dtype=torch.float32, device=device)
         self.vel = torch.empty_like(self.pos)
+        self.fallback = False
 
+    # -- state hand-over --------------------------------------------------
     def particles_of(self, plan):
         if self.cfg.n_particles:
             wdm.wdm_particles(plan.handle, 0, self.pos, self.vel)
@@ -89,164 +113,213 @@ class Pipeline:
         p, v = self.particles_of(self.fine)
         wdm.wdm_set_state(self.coarse.handle, 0, self.buf_c, p, v)
 
-    def coarse_psi_phi(self):
+    def attach(self, on: bool):
+        wdm.wdm_plan_attach_corrector(self.coarse.handle, self.net.handle if on else None, 0,
+                                      self.cfg.every if on else 0)
+
+    def coarse_pk(self):
+        return wdm.wdm_power_spectrum(self.coarse.handle, 0, self.cfg.n_coarse // 2)[0]
+
+    def fine_pk(self):
+        return wdm.wdm_power_spectrum(self.fine.handle, 0, self.cfg.n_coarse // 2)[0]
+
+    # -- training ------------------------------------------------------------
+    def make_pairs(self, seeds, log=print):
+        """Training pairs (x, y) as device tensors: x = (Re psi, Im psi, Phi)
+        of the coarse state after `every` steps from the restricted fine state,
+        y = restricted fine state at the same time minus the coarse psi."""
         torch = _torch()
-        psi = torch.empty_like(self.buf_c)
-        wdm.wdm_get_psi(self.coarse.handle, 0, psi)
-        phi = torch.empty_like(self.phi_c)
-        wdm.wdm_potential(self.coarse.handle, 0, phi)
-        return psi, phi
+        cfg, nc = self.cfg, self.cfg.n_coarse
+        xs, ys = [], []
+        for s in seeds:
+            wl = halo(cfg, s)
+            psi, pos, vel = _state(wl, self.device)
+            wdm.wdm_set_state(self.fine.handle, 0, psi, pos, vel)
+            self.attach(False)
+            for w in range(cfg.windows):
+                if w:
+                    gap = cfg.pair_stride - cfg.every
+                    if gap > 0:
+                        wdm.wdm_step(self.fine.handle, gap * self.ratio, self.dt_f)
+                self.coarse_from_fine()
+                wdm.wdm_step(self.coarse.handle, cfg.every, self.dt_c)
+                wdm.wdm_step(self.fine.handle, cfg.every * self.ratio, self.dt_f)
+                tgt = torch.empty_like(self.buf_c)
+                wdm.wdm_restrict(self.fine.handle, 0, self.coarse.handle, 0, tgt)
+                x = torch.empty((nc ** 3, 3), dtype=torch.float32, device=self.device)
+                y = torch.empty((nc ** 3, 2), dtype=torch.float32, device=self.device)
+                wdm.wdm_net_pair(self.coarse.handle, 0, tgt, x, y)
+                xs.append(x)
+                ys.append(y)
+            log(f"# pairs: seed {s} done ({len(xs)} pairs)")
+        return xs, ys
 
-    def close(self):
-        self.fine.close()
-        self.coarse.close()
+    def train(self, xs, ys, log=print):
+        cfg = self.cfg
+        wdm.wdm_net_fit_scales(self.net.handle, xs, ys)
+        rng = np.random.default_rng(cfg.seed)
+        wdm.wdm_net_set_params(self.net.handle,
+                               (rng.standard_normal(wdm.wdm_net_param_count())
+                                * cfg.init_scale).astype(np.float32))
+        losses = []
+        for ep in range(cfg.epochs):
+            order = rng.permutation(len(xs))
+            tot = 0.0
+            for i in order:
+                wdm.wdm_net_forward(self.net.handle, xs[i])
+                tot += wdm.wdm_net_mse_backward(self.net.handle, ys[i])
+                wdm.wdm_net_adam(self.net.handle, cfg.lr)
+            losses.append(tot / len(order))
+            log(f"# epoch {ep}: mean loss {losses[-1]:.4e}")
+        return losses
 
+    # -- judge and fallback ----------------------------------------------------
+    def judge_seed(self, seed):
+        """P(k) errors after judge_steps coarse steps, with and without the
+        corrector, against the plain fine solve over the same time."""
+        cfg = self.cfg
+        wl = halo(cfg, seed)
+        psi, pos, vel = _state(wl, self.device)
+        torch = _torch()
+        res, fields = {}, {}
+        for use_net in (False, True):
+            wdm.wdm_set_state(self.fine.handle, 0, psi, pos, vel)
+            self.coarse_from_fine()
+            self.attach(use_net)
+            wdm.wdm_step(self.coarse.handle, cfg.judge_steps, self.dt_c)
+            res[use_net] = self.coarse_pk()
+            fields[use_net] = torch.empty_like(self.buf_c)
+            wdm.wdm_get_psi(self.coarse.handle, 0, fields[use_net])
+        self.attach(False)
+        wdm.wdm_set_state(self.fine.handle, 0, psi, pos, vel)
+        wdm.wdm_step(self.fine.handle, cfg.judge_steps * self.ratio, self.dt_f)
+        pk_f = self.fine_pk()
+        nb = cfg.n_coarse // 2
+        # field error: the coarse field against the restricted fine field
+        target = torch.empty_like(self.buf_c)
+        wdm.wdm_restrict(self.fine.handle, 0, self.coarse.handle, 0, target)
+        ferr = {}
+        for use_net in (False, True):
+            wdm.wdm_set_state(self.coarse.handle, 0, fields[use_net], *self.particles_of(self.fine))
+            d, o = wdm.wdm_distance(self.coarse.handle, 0, target)
+            ferr[use_net] = math.sqrt(d / o)
+        return {"err_without_net": pk_error(res[False], pk_f, nb),
+                "err_with_net": pk_error(res[True], pk_f, nb),
+                "field_err_without_net": ferr[False], "field_err_with_net": ferr[True]}
 
-def make_pairs(cfg: LearnedConfig, seeds, device="cuda", log=print):
-    """(input psi/phi after 8 coarse steps, restricted fine target) per window."""
-    torch = _torch()
-    pipe = None
-    xs, ys = [], []
-    for s in seeds:
-        wl = inputs.coupled_halo(n=cfg.n_fine, n_particles=cfg.n_particles, seed=s)
-        if pipe is None:
-            pipe = Pipeline(cfg, wl.particle_mass, device)
-        psi, pos, vel = _state(wl, device)
-        wdm.wdm_set_state(pipe.fine.handle, 0, psi, pos, vel)
-        for w in range(cfg.windows):
-            pipe.coarse_from_fine()
-            wdm.wdm_step(pipe.coarse.handle, cfg.every, pipe.dt_c)
-            cpsi, cphi = pipe.coarse_psi_phi()
-            wdm.wdm_step(pipe.fine.handle, cfg.every * pipe.ratio, pipe.dt_f)
-            tgt = torch.empty_like(pipe.buf_c)
-            wdm.wdm_restrict(pipe.fine.handle, 0, pipe.coarse.handle, 0, tgt)
-            xs.append(torch.stack([cpsi.real, cpsi.imag, cphi], dim=-1).reshape(-1, 3).contiguous())
-            ys.append(torch.stack([(tgt - cpsi).real, (tgt - cpsi).imag], dim=-1)
-                      .reshape(-1, 2).contiguous())
-        log(f"# pairs: seed {s} done ({len(xs)} pairs)")
-    return xs, ys, pipe
+    def judge(self, seeds, log=print):
+        """Judge on held-out seeds; the fallback is taken when the mean error
+        with the corrector exceeds the threshold."""
+        judged = []
+        for s in seeds:
+            judged.append(self.judge_seed(s))
+            log(f"# judge: seed {s}: {judged[-1]}")
+        mean = {k: float(np.mean([j[k] for j in judged])) for k in judged[0]}
+        self.fallback = mean["err_with_net"] > self.cfg.threshold
+        return {"pk_err_with_net": mean["err_with_net"],
+                "pk_err_without_net": mean["err_without_net"],
+                "gain": mean["err_without_net"] - mean["err_with_net"],
+                "field_err_with_net": mean["field_err_with_net"],
+                "field_err_without_net": mean["field_err_without_net"],
+                "per_seed": judged, "fallback_to_fine": self.fallback}
 
+    def advance(self, psi, pos, vel, coarse_steps):
+        """Advance an initial state by coarse_steps * dt_c of simulated time on
+        the path the judge chose: the coarse plan with the corrector attached
+        (restricted state), or, after a fallback, the plain fine plan.  Returns
+        (plan name, field as a device tensor)."""
+        torch = _torch()
+        wdm.wdm_set_state(self.fine.handle, 0, psi, pos, vel)
+        if self.fallback:
+            wdm.wdm_step(self.fine.handle, coarse_steps * self.ratio, self.dt_f)
+            out = torch.empty_like(psi)
+            wdm.wdm_get_psi(self.fine.handle, 0, out)
+            return "fine", out
+        self.coarse_from_fine()
+        self.attach(True)
+        wdm.wdm_step(self.coarse.handle, coarse_steps, self.dt_c)
+        self.attach(False)
+        out = torch.empty_like(self.buf_c)
+        wdm.wdm_get_psi(self.coarse.handle, 0, out)
+        return "coarse", out
 
-def normalisation(xs, ys):
-    """Input and output scales from the training set (host scalars)."""
-    torch = _torch()
-    x = torch.stack(xs)
-    y = torch.stack(ys)
-    s_psi = 1.0 / float(torch.sqrt(torch.mean(x[..., 0] ** 2 + x[..., 1] ** 2)))
-    s_phi = 1.0 / float(torch.std(x[..., 2]))
-    s_out = float(torch.std(y))
-    return s_psi, s_phi, max(s_out, 1e-30)
+    # -- cost ------------------------------------------------------------------
+    def seconds_per_unit_time(self, reps=3, blocks=4):
+        """Wall time per simulated time unit of the plain fine solve and of the
+        coarse solve with the corrector attached (its correction inside the
+        captured block), each over `blocks` correction intervals."""
+        torch = _torch()
+        cfg = self.cfg
 
-
-def train(cfg: LearnedConfig, net, xs, ys, scales, log=print):
-    torch = _torch()
-    s_psi, s_phi, s_out = scales
-    sc_in = torch.tensor([s_psi, s_psi, s_phi], device=xs[0].device)
-    xin = [x * sc_in for x in xs]
-    tgt = [y / s_out for y in ys]
-    rng = np.random.default_rng(cfg.seed)
-    losses = []
-    for ep in range(cfg.epochs):
-        order = rng.permutation(len(xin))
-        tot = 0.0
-        for i in order:
-            wdm.wdm_net_forward(net.handle, xin[i])
-            tot += wdm.wdm_net_mse_backward(net.handle, tgt[i])
-            wdm.wdm_net_adam(net.handle, cfg.lr)
-        losses.append(tot / len(order))
-        log(f"# epoch {ep}: mean loss {losses[-1]:.4e}")
-    return losses
-
-
-def pk_error(pk_c, pk_f, nbins):
-    b = slice(1, nbins)
-    d = pk_c[b] - pk_f[b]
-    return float(math.sqrt(np.sum(d * d) / np.sum(pk_f[b] ** 2)))
-
-
-def judge(cfg: LearnedConfig, pipe: Pipeline, net, scales, seed, device="cuda"):
-    """P(k) error of coarse runs with and without the corrector vs the fine run."""
-    wl = inputs.coupled_halo(n=cfg.n_fine, n_particles=cfg.n_particles, seed=seed)
-    psi, pos, vel = _state(wl, device)
-    nb = cfg.n_coarse // 2
-    s_psi, s_phi, s_out = scales
-    res = {}
-    for use_net in (False, True):
-        wdm.wdm_set_state(pipe.fine.handle, 0, psi, pos, vel)
-        pipe.coarse_from_fine()
-        for _ in range(cfg.judge_steps // cfg.every):
-            wdm.wdm_step(pipe.coarse.handle, cfg.every, pipe.dt_c)
-            if use_net:
-                wdm.wdm_net_apply(net.handle, pipe.coarse.handle, 0, s_psi, s_phi, s_out)
-        pk_c, _ = wdm.wdm_power_spectrum(pipe.coarse.handle, 0, nb)
-        res["with_net" if use_net else "without_net"] = pk_c
-    wdm.wdm_set_state(pipe.fine.handle, 0, psi, pos, vel)
-    wdm.wdm_step(pipe.fine.handle, cfg.judge_steps * pipe.ratio, pipe.dt_f)
-    pk_f, _ = wdm.wdm_power_spectrum(pipe.fine.handle, 0, nb)
-    return {"err_without_net": pk_error(res["without_net"], pk_f, nb),
-            "err_with_net": pk_error(res["with_net"], pk_f, nb)}
-
-
-def seconds_per_unit_time(cfg: LearnedConfig, pipe: Pipeline, net, scales, reps=3):
-    """Wall time per simulated time unit: fine plain solve vs coarse + corrector."""
-    torch = _torch()
-    s_psi, s_phi, s_out = scales
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        best = 1e30
-        for _ in range(reps):
-            t0 = time.perf_counter()
+        def timed(fn):
             fn()
             torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
-        return best
+            best = 1e30
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            return best
 
-    def fine_block():
-        wdm.wdm_step(pipe.fine.handle, cfg.every * pipe.ratio, pipe.dt_f)
+        nfine = blocks * cfg.every * self.ratio
+        ncoarse = blocks * cfg.every
+        t_f = timed(lambda: wdm.wdm_step(self.fine.handle, nfine, self.dt_f)) / (nfine * self.dt_f)
+        self.attach(True)
+        t_c = timed(lambda: wdm.wdm_step(self.coarse.handle, ncoarse, self.dt_c)) / (
+            ncoarse * self.dt_c)
+        self.attach(False)
+        return t_f, t_c
 
-    def coarse_block():
-        wdm.wdm_step(pipe.coarse.handle, cfg.every, pipe.dt_c)
-        wdm.wdm_net_apply(net.handle, pipe.coarse.handle, 0, s_psi, s_phi, s_out)
+    def error_horizon(self, seed, checkpoints):
+        """P(k) error of the coarse solve without the corrector against the
+        fine solve at each checkpoint (coarse steps, increasing)."""
+        cfg = self.cfg
+        wl = halo(cfg, seed)
+        psi, pos, vel = _state(wl, self.device)
+        wdm.wdm_set_state(self.fine.handle, 0, psi, pos, vel)
+        self.coarse_from_fine()
+        self.attach(False)
+        out, done = [], 0
+        for c in checkpoints:
+            wdm.wdm_step(self.coarse.handle, c - done, self.dt_c)
+            wdm.wdm_step(self.fine.handle, (c - done) * self.ratio, self.dt_f)
+            done = c
+            out.append((c, pk_error(self.coarse_pk(), self.fine_pk(), cfg.n_coarse // 2)))
+        return out
 
-    t_f = timed(fine_block) / (cfg.every * pipe.ratio * pipe.dt_f)
-    t_c = timed(coarse_block) / (cfg.every * pipe.dt_c)
-    return t_f, t_c
+    def close(self):
+        self.net.close()
+        self.fine.close()
+        self.coarse.close()
 
 
 def run(cfg: LearnedConfig, device="cuda", log=print) -> dict:
     """Generate pairs, train, judge on held-out seeds, time both paths."""
     torch = _torch()
+    wl0 = halo(cfg, cfg.train_seeds[0])
+    pipe = Pipeline(cfg, wl0.particle_mass, device)
+    del wl0
     t0 = time.perf_counter()
-    xs, ys, pipe = make_pairs(cfg, [s for s in cfg.train_seeds], device, log)
+    xs, ys = pipe.make_pairs(cfg.train_seeds, log)
     t_pairs = time.perf_counter() - t0
-    scales = normalisation(xs, ys)
-    net = wdm.Net(cfg.n_coarse, device=device)
-    rng = np.random.default_rng(cfg.seed)
-    wdm.wdm_net_set_params(net.handle, (rng.standard_normal(wdm.wdm_net_param_count())
-                                        * cfg.init_scale).astype(np.float32))
-    # untrained baseline loss (identity residual = 0 target scale)
     t1 = time.perf_counter()
-    losses = train(cfg, net, xs, ys, scales, log)
+    losses = pipe.train(xs, ys, log)
     t_train = time.perf_counter() - t1
+    scales = wdm.wdm_net_get_scales(pipe.net.handle)
     del xs, ys
     torch.cuda.empty_cache()
-    judged = []
-    for s in cfg.heldout_seeds:
-        judged.append(judge(cfg, pipe, net, scales, s, device))
-        log(f"# judge: seed {s}: {judged[-1]}")
-    err_with = float(np.mean([j["err_with_net"] for j in judged]))
-    err_without = float(np.mean([j["err_without_net"] for j in judged]))
-    t_f, t_c = seconds_per_unit_time(cfg, pipe, net, scales)
-    fallback = err_with > cfg.threshold
-    out = {"pk_err_with_net": err_with, "pk_err_without_net": err_without,
-           "gain": err_without - err_with, "per_seed": judged,
-           "s_per_unit_time_fine": t_f, "s_per_unit_time_learned": t_c,
-           "speedup": t_f / t_c, "fallback_to_fine": fallback,
-           "effective_speedup": 1.0 if fallback else t_f / t_c,
-           "train_losses": losses, "scales": scales, "pairs": len(cfg.train_seeds) * cfg.windows,
-           "seconds_pairs": t_pairs, "seconds_train": t_train}
-    net.close()
+    res = pipe.judge(cfg.heldout_seeds, log)
+    if cfg.horizon_checkpoints:
+        res["horizon_without_net"] = pipe.error_horizon(cfg.heldout_seeds[0],
+                                                        cfg.horizon_checkpoints)
+        log(f"# horizon: {res['horizon_without_net']}")
+    t_f, t_c = pipe.seconds_per_unit_time()
+    res.update({"s_per_unit_time_fine": t_f, "s_per_unit_time_learned": t_c,
+                "speedup": t_f / t_c,
+                "effective_speedup": 1.0 if res["fallback_to_fine"] else t_f / t_c,
+                "train_losses": losses, "scales": scales,
+                "pairs": len(cfg.train_seeds) * cfg.windows,
+                "seconds_pairs": t_pairs, "seconds_train": t_train})
     pipe.close()
-    return out
+    return res

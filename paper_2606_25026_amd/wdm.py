@@ -96,6 +96,7 @@ _SIGS = {
     "wdm_copy_bandwidth": (C.c_int, [_vp, _vp, C.c_size_t, _i32, _vp, C.POINTER(_f64)]),
     "wdm_restrict": (C.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "wdm_power_spectrum": (C.c_int, [_vp, _i32, _i32, C.POINTER(_f64), C.POINTER(_i64)]),
+    "wdm_distance": (C.c_int, [_vp, _i32, _vp, C.POINTER(_f64)]),
     "wdm_net_param_count": (_i32, []),
     "wdm_net_workspace_bytes": (C.c_size_t, [_i32]),
     "wdm_net_create": (C.c_int, [_i32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -107,7 +108,12 @@ _SIGS = {
     "wdm_net_backward": (C.c_int, [_vp, _vp]),
     "wdm_net_mse_backward": (C.c_int, [_vp, _vp, C.POINTER(_f64)]),
     "wdm_net_adam": (C.c_int, [_vp, _f64, _f64, _f64, _f64]),
-    "wdm_net_apply": (C.c_int, [_vp, _vp, _i32, _f64, _f64, _f64]),
+    "wdm_net_apply": (C.c_int, [_vp, _vp, _i32]),
+    "wdm_net_set_scales": (C.c_int, [_vp, _f64, _f64, _f64]),
+    "wdm_net_get_scales": (C.c_int, [_vp, C.POINTER(_f64)]),
+    "wdm_net_fit_scales": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), _i32]),
+    "wdm_net_pair": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "wdm_plan_attach_corrector": (C.c_int, [_vp, _vp, _i32, _i32]),
     "wdm_last_error": (C.c_char_p, []),
 }
 
@@ -348,6 +354,13 @@ def wdm_power_spectrum(plan, member, nbins):
     return pk, cnt
 
 
+def wdm_distance(plan, member, other):
+    """(sum |psi - other|^2, sum |other|^2) of a member's field."""
+    out = (_f64 * 2)()
+    _check(load().wdm_distance(plan, int(member), _ptr(other), out))
+    return out[0], out[1]
+
+
 def wdm_net_param_count() -> int:
     return int(load().wdm_net_param_count())
 
@@ -413,8 +426,33 @@ def wdm_net_adam(net, lr, b1=0.9, b2=0.999, eps=1e-8):
     _check(load().wdm_net_adam(net, float(lr), float(b1), float(b2), float(eps)))
 
 
-def wdm_net_apply(net, plan, member, s_psi, s_phi, s_out):
-    _check(load().wdm_net_apply(net, plan, int(member), float(s_psi), float(s_phi), float(s_out)))
+def wdm_net_apply(net, plan, member=0):
+    _check(load().wdm_net_apply(net, plan, int(member)))
+
+
+def wdm_net_set_scales(net, s_psi, s_phi, s_out):
+    _check(load().wdm_net_set_scales(net, float(s_psi), float(s_phi), float(s_out)))
+
+
+def wdm_net_get_scales(net):
+    out = (_f64 * 3)()
+    _check(load().wdm_net_get_scales(net, out))
+    return tuple(out)
+
+
+def wdm_net_fit_scales(net, xs, ys):
+    n = len(xs)
+    xa = (_vp * n)(*[_ptr(x) for x in xs])
+    ya = (_vp * n)(*[_ptr(y) for y in ys])
+    _check(load().wdm_net_fit_scales(net, xa, ya, n))
+
+
+def wdm_net_pair(plan, member, target, x_out, y_out):
+    _check(load().wdm_net_pair(plan, int(member), _ptr(target), _ptr(x_out), _ptr(y_out)))
+
+
+def wdm_plan_attach_corrector(plan, net, member=0, every=8):
+    _check(load().wdm_plan_attach_corrector(plan, net, int(member), int(every)))
 
 
 class Net:

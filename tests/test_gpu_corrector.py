@@ -102,6 +102,37 @@ def test_conv_forward_and_backward_match_oracle(wdm, orc):
     net.close()
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n", [64, 128])
+def test_conv_parity_at_production_size(wdm, orc, n):
+    """Forward output and every layer's weight and bias gradients at 64^3 and
+    at the corrector's 128^3 grid, where each weight-gradient work-group sums
+    8192 cells in FP32 on the matrix cores.  The lower layers' gradients depend
+    on the data gradients of the layers above (dx of layers 2 and 1), so their
+    parity covers those too."""
+    rng = np.random.default_rng(n)
+    net = wdm.Net(n)
+    params = random_params(wdm, rng)
+    wdm.wdm_net_set_params(net.handle, params)
+    x = rng.standard_normal((n ** 3, 3)).astype(np.float32)
+    y = torch.empty((n ** 3, 2), dtype=torch.float32, device="cuda")
+    wdm.wdm_net_forward(net.handle, torch.from_numpy(x).cuda(), y)
+    dy = rng.standard_normal((n ** 3, 2)).astype(np.float32) * 1e-3
+    wdm.wdm_net_backward(net.handle, torch.from_numpy(dy).cuda())
+    g = split_params(wdm.wdm_net_get_grads(net.handle))
+    torch.cuda.synchronize()
+    y_ref, acts = oracle_forward(orc, params, x, n)
+    err = rel_l2(to_cf(y.cpu().numpy(), n), y_ref)
+    print(f"{n}^3 conv3d forward vs oracle: rel L2 {err:.2e}")
+    assert err < 1e-3
+    ref = oracle_backward(orc, params, acts, to_cf(dy, n))
+    for l in range(3):
+        ew, eb = rel_l2(g[l][0], ref[l][0]), rel_l2(g[l][1], ref[l][1])
+        print(f"{n}^3 layer {l}: dW rel L2 {ew:.2e}, db rel L2 {eb:.2e}")
+        assert ew < 1e-3 and eb < 1e-3
+    net.close()
+
+
 def test_mse_backward_and_adam(wdm):
     n = 8
     rng = np.random.default_rng(1)
@@ -162,7 +193,8 @@ def test_apply_keeps_mass_and_rebuilds_potential(wdm, orc):
     net = wdm.Net(n)
     wdm.wdm_net_set_params(net.handle, random_params(wdm, np.random.default_rng(3), 0.05))
     e0 = wdm.wdm_energy(plan.handle, 0)
-    wdm.wdm_net_apply(net.handle, plan.handle, 0, 1.0, 1.0, 0.05)
+    wdm.wdm_net_set_scales(net.handle, 1.0, 1.0, 0.05)
+    wdm.wdm_net_apply(net.handle, plan.handle, 0)
     e1 = wdm.wdm_energy(plan.handle, 0)
     out = torch.empty_like(psi)
     wdm.wdm_get_psi(plan.handle, 0, out)
@@ -177,3 +209,137 @@ def test_apply_keeps_mass_and_rebuilds_potential(wdm, orc):
     assert rel_l2(phi.cpu().numpy(), phi_ref) < 1e-5
     net.close()
     plan.close()
+
+
+def oracle_apply(orc, params, scales, psi, phi, n):
+    """The correction written out from its definition: inputs (Re psi s_psi,
+    Im psi s_psi, Phi s_phi) rounded to BF16, the network (BF16 weights and
+    activations, FP64 accumulation), psi + s_out y, rescaled to the FP64 mass
+    of psi before the correction."""
+    s_psi, s_phi, s_out = scales
+    x = np.stack([psi.real * s_psi, psi.imag * s_psi, phi * s_phi], axis=-1).reshape(-1, 3)
+    y, _ = oracle_forward(orc, params, x.astype(np.float32), n)
+    new = psi + s_out * (y[0] + 1j * y[1])
+    m0 = np.sum(np.abs(psi) ** 2)
+    return new * np.sqrt(m0 / np.sum(np.abs(new) ** 2))
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_apply_matches_oracle_composition(wdm, orc, n):
+    wl = inputs.coupled_halo(n=n, n_particles=2000, seed=6, steps=0)
+    plan = wdm.Plan(wdm.make_config(n, n_particles=2000, particle_mass=wl.particle_mass))
+    psi = torch.from_numpy(wl.psi.astype(np.complex64)).cuda()
+    wdm.wdm_set_state(plan.handle, 0, psi, torch.from_numpy(wl.pos).cuda(),
+                      torch.from_numpy(wl.vel).cuda())
+    net = wdm.Net(n)
+    params = random_params(wdm, np.random.default_rng(n + 1), 0.1)
+    wdm.wdm_net_set_params(net.handle, params)
+    scales = (0.9, 2.5, 0.03)
+    wdm.wdm_net_set_scales(net.handle, *scales)
+    assert wdm.wdm_net_get_scales(net.handle) == pytest.approx(scales, rel=1e-15)
+    phi = torch.empty((n,) * 3, dtype=torch.float32, device="cuda")
+    wdm.wdm_potential(plan.handle, 0, phi)
+    before = phi.cpu().numpy().astype(np.float64)
+    wdm.wdm_net_apply(net.handle, plan.handle, 0)
+    out = torch.empty_like(psi)
+    wdm.wdm_get_psi(plan.handle, 0, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.complex128)
+    ref = oracle_apply(orc, params, scales, wl.psi.astype(np.complex64).astype(np.complex128),
+                       before, n)
+    err = rel_l2(got, ref)
+    change = rel_l2(ref, wl.psi)
+    print(f"apply {n}^3: rel L2 vs oracle {err:.2e} (the correction moves psi by {change:.2e})")
+    assert change > 1e-3
+    # the network output carries the forward pass's bar (1e-3 relative), scaled
+    # by the size of the correction, plus the complex64 rounding of psi
+    assert err < 1e-3 * change + 1e-6
+    # the potential was rebuilt from the corrected state
+    wdm.wdm_potential(plan.handle, 0, phi)
+    cfg = orc.make_config((n,) * 3, n_particles=2000, particle_mass=wl.particle_mass)
+    phi_ref = orc.potential(cfg, got, wl.pos.astype(np.float64))
+    assert rel_l2(phi.cpu().numpy(), phi_ref) < 1e-5
+    net.close()
+    plan.close()
+
+
+def test_training_pair_and_scales(wdm):
+    n = 32
+    wl = inputs.coupled_halo(n=n, n_particles=500, seed=8, steps=0)
+    plan = wdm.Plan(wdm.make_config(n, n_particles=500, particle_mass=wl.particle_mass))
+    psi = torch.from_numpy(wl.psi.astype(np.complex64)).cuda()
+    wdm.wdm_set_state(plan.handle, 0, psi, torch.from_numpy(wl.pos).cuda(),
+                      torch.from_numpy(wl.vel).cuda())
+    rng = np.random.default_rng(9)
+    xs, ys, hx, hy = [], [], [], []
+    phi = torch.empty((n,) * 3, dtype=torch.float32, device="cuda")
+    wdm.wdm_potential(plan.handle, 0, phi)
+    for k in range(3):
+        tgt = (wl.psi + 0.01 * (k + 1) * (rng.standard_normal(wl.psi.shape)
+                                         + 1j * rng.standard_normal(wl.psi.shape)))
+        tgt = tgt.astype(np.complex64)
+        x = torch.empty((n ** 3, 3), dtype=torch.float32, device="cuda")
+        y = torch.empty((n ** 3, 2), dtype=torch.float32, device="cuda")
+        wdm.wdm_net_pair(plan.handle, 0, torch.from_numpy(tgt).cuda(), x, y)
+        xs.append(x)
+        ys.append(y)
+        p32 = wl.psi.astype(np.complex64)
+        ex = np.stack([p32.real, p32.imag, phi.cpu().numpy()], -1).reshape(-1, 3)
+        d = (tgt - p32).reshape(-1)
+        ey = np.stack([d.real, d.imag], -1)
+        assert np.array_equal(x.cpu().numpy(), ex)
+        assert np.array_equal(y.cpu().numpy(), ey)
+        hx.append(ex.astype(np.float64))
+        hy.append(ey.astype(np.float64))
+    net = wdm.Net(n)
+    assert wdm.wdm_net_get_scales(net.handle) == (1.0, 1.0, 1.0)
+    wdm.wdm_net_fit_scales(net.handle, xs, ys)
+    X, Y = np.concatenate(hx), np.concatenate(hy)
+    expect = (1 / np.sqrt(np.mean(X[:, 0] ** 2 + X[:, 1] ** 2)), 1 / np.std(X[:, 2]), np.std(Y))
+    assert wdm.wdm_net_get_scales(net.handle) == pytest.approx(expect, rel=1e-10)
+    net.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("pattern", [(12,), (6, 6), (3, 9, 4)])
+def test_attached_corrector_equals_applies_between_calls(wdm, pattern):
+    """A corrector attached to the plan (every 4 steps; a run of 4 steps from a
+    correction boundary replays one captured graph holding the correction)
+    gives the same state, bit for bit in deterministic mode, as the same calls
+    split where a correction falls due with wdm_net_apply called there."""
+    n, every = 32, 4
+    wl = inputs.coupled_halo(n=n, n_particles=1500, seed=10, steps=0)
+    cfg = wdm.make_config(n, n_particles=1500, particle_mass=wl.particle_mass,
+                          flags=wdm.WDM_DETERMINISTIC_DEPOSIT)
+    net = wdm.Net(n)
+    wdm.wdm_net_set_params(net.handle, random_params(wdm, np.random.default_rng(11), 0.1))
+    wdm.wdm_net_set_scales(net.handle, 1.0, 1.0, 1e-3)
+    plans = [wdm.Plan(cfg), wdm.Plan(cfg)]
+    for p in plans:
+        wdm.wdm_set_state(p.handle, 0, torch.from_numpy(wl.psi.astype(np.complex64)).cuda(),
+                          torch.from_numpy(wl.pos).cuda(), torch.from_numpy(wl.vel).cuda())
+    a, b = plans
+    wdm.wdm_plan_attach_corrector(a.handle, net.handle, 0, every)
+    for k in pattern:
+        wdm.wdm_step(a.handle, k, wl.dt)
+    # the same calls, split where a correction falls due, with wdm_net_apply there
+    phase = 0
+    for k in pattern:
+        while k:
+            run = min(k, every - phase)
+            wdm.wdm_step(b.handle, run, wl.dt)
+            phase, k = (phase + run) % every, k - run
+            if phase == 0:
+                wdm.wdm_net_apply(net.handle, b.handle, 0)
+    outs = []
+    for p in plans:
+        o = torch.empty((n,) * 3, dtype=torch.complex64, device="cuda")
+        wdm.wdm_get_psi(p.handle, 0, o)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    assert rel_l2(outs[0], wl.psi) > 1e-4
+    wdm.wdm_plan_attach_corrector(a.handle, None, 0, 0)
+    net.close()
+    for p in plans:
+        p.close()
