@@ -179,7 +179,7 @@ def bench_ensemble(args):
             for m in members]
     plan = wdm.Plan(cfgs)
     h = plan.handle
-    tuning = wdm.autotune(h, cfgs, reps=10) if not args.no_tune else wdm.wdm_get_tuning(h)
+    tuning = wdm.autotune(h, cfgs, reps=20) if not args.no_tune else wdm.wdm_get_tuning(h)
     keep = []
     for i, m in enumerate(members):
         psi = torch.from_numpy(m.psi.astype(np.complex64)).cuda()
@@ -387,7 +387,7 @@ def main():
         wdm.wdm_set_tuning(h, [1] * wdm.wdm_tuning_entries(h))
         tuning = wdm.wdm_get_tuning(h)
     else:
-        tuning = wdm.autotune(h, cfg, reps=10)
+        tuning = wdm.autotune(h, cfg, reps=20)
     if args.tidal != 0.0:
         x = torch.arange(args.n, dtype=torch.float32, device=dev) / args.n - 0.5
         X, Y, Z = torch.meshgrid(x, x, x, indexing="ij")

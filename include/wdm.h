@@ -293,8 +293,10 @@ wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);
  * P6/P8, P7) of each size class has two FFT plans where its axis length allows
  * (32, 64, 128, 256, 384, 512): the default, and one with twice the lanes per
  * pencil and half the values per lane.  wdm_autotune times both on the plan's
- * stream (one warm-up and `reps` timed launches each, reps in [1, 1000], on
- * zeroed fields) and keeps the faster.  It overwrites the members' states:
+ * stream (a warm-up launch each, then `reps` rounds, reps in [1, 1000], timing
+ * each plan once per round in alternating order, each launch between its own
+ * events, on zeroed fields) and takes the second plan only when its median is
+ * at least 2 % below the default's.  It overwrites the members' states:
  * call it before wdm_set_state, or set every state again afterwards
  * (wdm_step returns WDM_ESTATE until then).  Synchronises.  Both plans give
  * the same results up to rounding.

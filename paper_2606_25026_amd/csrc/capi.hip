@@ -1058,6 +1058,11 @@ wdm_status wdm_use_graphs(wdm_plan* p, int32_t enable) {
 
 namespace {
 
+// The second plan replaces the default only when its median launch time is
+// this fraction faster: the plans of one pass are usually within a few per
+// cent, and a choice made on noise would change from run to run.
+constexpr float kTuneMargin = 0.02f;
+
 // Axis length that decides each tunable pass's plan.
 int tune_axis(const SizeClass& c, int slot) {
     switch (slot) {
@@ -1124,13 +1129,19 @@ wdm_status wdm_autotune(wdm_plan* p, int32_t reps) {
     if (!p) return fail(WDM_EINVAL, "null plan");
     if (reps < 1 || reps > 1000) return fail(WDM_EINVAL, "reps must be in [1, 1000]");
     if (p->profiling) return fail(WDM_ESTATE, "switch profiling off before tuning");
-    hipEvent_t a = nullptr, b = nullptr;
-    HIPCHK(hipEventCreate(&a));
-    if (hipEventCreate(&b) != hipSuccess) {
-        (void)hipEventDestroy(a);
+    // one event pair per timed launch: reps launches of each of two plans
+    std::vector<hipEvent_t> ev(4 * size_t(reps), nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    auto release = [&] {
+        for (auto x : ev)
+            if (x) (void)hipEventDestroy(x);
+    };
+    if (e != hipSuccess) {
+        release();
         return fail(WDM_EDEVICE, "hipEventCreate failed");
     }
-    hipError_t e = hipSuccess;
     // the timings run on zeroed fields (FFT timing does not depend on the
     // values); the members' states are overwritten
     for (size_t k = 0; k < p->classes.size() && e == hipSuccess; ++k) {
@@ -1149,29 +1160,40 @@ wdm_status wdm_autotune(wdm_plan* p, int32_t reps) {
             if (e == hipSuccess) e = launch_zero(p->stream, m.dt, 4 * sizeof(double));
         }
         for (int j = 0; j < kTuneSlots && e == hipSuccess; ++j) {
-            const int nv = axis_has_variant(tune_axis(c, j)) ? 2 : 1;
-            float best = 0.0f;
-            int pick = 0;
-            for (int v = 0; v < nv && e == hipSuccess; ++v) {
-                // one warm-up launch, then reps timed launches
-                if ((e = tune_launch(p, L, c, j, v)) != hipSuccess) break;
-                if ((e = hipEventRecord(a, p->stream)) != hipSuccess) break;
-                for (int r = 0; r < reps && e == hipSuccess; ++r) e = tune_launch(p, L, c, j, v);
-                if (e != hipSuccess) break;
-                if ((e = hipEventRecord(b, p->stream)) != hipSuccess) break;
-                if ((e = hipEventSynchronize(b)) != hipSuccess) break;
-                float ms = 0.0f;
-                if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
-                if (v == 0 || ms < best) {
-                    best = ms;
-                    pick = v;
+            c.var[j] = 0;
+            if (!axis_has_variant(tune_axis(c, j))) continue;
+            // a warm-up launch of each plan, then reps rounds timing each plan
+            // once per round, in alternating order, every launch on its own
+            for (int v = 0; v < 2 && e == hipSuccess; ++v) e = tune_launch(p, L, c, j, v);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+                    const int v = (r + q) & 1;
+                    hipEvent_t a = ev[4 * size_t(r) + 2 * v], b = ev[4 * size_t(r) + 2 * v + 1];
+                    if ((e = hipEventRecord(a, p->stream)) != hipSuccess) break;
+                    if ((e = tune_launch(p, L, c, j, v)) != hipSuccess) break;
+                    e = hipEventRecord(b, p->stream);
                 }
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            std::vector<float> t[2];
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+                    float ms = 0.0f;
+                    e = hipEventElapsedTime(&ms, ev[4 * size_t(r) + 2 * v],
+                                            ev[4 * size_t(r) + 2 * v + 1]);
+                    t[v].push_back(ms);
+                }
+            if (e != hipSuccess) break;
+            // medians; the second plan must win by kTuneMargin to replace the default
+            float med[2];
+            for (int v = 0; v < 2; ++v) {
+                std::sort(t[v].begin(), t[v].end());
+                const size_t h = t[v].size() / 2;
+                med[v] = t[v].size() % 2 ? t[v][h] : 0.5f * (t[v][h - 1] + t[v][h]);
             }
-            c.var[j] = pick;
+            c.var[j] = med[1] < (1.0f - kTuneMargin) * med[0] ? 1 : 0;
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    release();
     drop_graphs(p);
     std::fill(p->has_state.begin(), p->has_state.end(), false);
     if (e != hipSuccess) return fail(WDM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));

@@ -268,7 +268,7 @@ def wdm_use_graphs(plan, enable=True):
     _check(load().wdm_use_graphs(plan, 1 if enable else 0))
 
 
-def wdm_autotune(plan, reps=10):
+def wdm_autotune(plan, reps=20):
     _check(load().wdm_autotune(plan, int(reps)))
 
 
@@ -298,7 +298,7 @@ def tuning_key(configs) -> str:
         f"{a}x{b}x{c}" for a, b, c in shapes)
 
 
-def autotune(plan, configs, cache=None, reps=10):
+def autotune(plan, configs, cache=None, reps=20):
     """Choose the step passes' FFT plans: from the JSON file `cache` when it
     holds this plan's key, else by wdm_autotune (and store the result there).
     Overwrites the members' states (set them afterwards).  Returns the table."""
