@@ -154,12 +154,45 @@ def learned_cost(h, wl, args, dev, ms_per_step, every=8, blocks=16):
     torch.cuda.synchronize()
     t_c = time.perf_counter() - t0
     wdm.wdm_plan_attach_corrector(coarse.handle, None, 0, 0)
+    # the corrector alone: one correction (inputs, three convolutions, update,
+    # potential rebuilt) and the network's forward pass, HIP events on the
+    # stream they run on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 20
+    wdm.wdm_net_apply(net.handle, coarse.handle, 0)
+    ev[0].record()
+    for _ in range(reps):
+        wdm.wdm_net_apply(net.handle, coarse.handle, 0)
+    ev[1].record()
+    x = torch.randn((nc ** 3, 3), dtype=torch.float32, device=dev)
+    wdm.wdm_net_forward(net.handle, x)
+    ev[2].record()
+    for _ in range(reps):
+        wdm.wdm_net_forward(net.handle, x)
+    ev[3].record()
+    torch.cuda.synchronize()
+    apply_us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    fwd_us = ev[2].elapsed_time(ev[3]) * 1e3 / reps
     net.close()
     coarse.close()
+    cells = nc ** 3
+    # forward pass: bf16 activations in and out of the three 3x3x3 layers
+    # (3 -> 16 -> 16 -> 2 channels, inputs packed from f32): 12 + 8 (pack) +
+    # 32 + 32 + 32 + 32 + 8 = 156 B and 2 * 27 * (3*16 + 16*16 + 16*2) flop per cell
+    fwd_bytes = 156 * cells
+    fwd_flop = 2 * 27 * (3 * 16 + 16 * 16 + 16 * 2) * cells
     s_fine = ms_per_step * 1e-3 / wl.dt
     s_learned = t_c / (every * blocks * dt_c)
     return {"s_per_unit_fine": s_fine, "s_per_unit_learned": s_learned,
             "ratio": s_fine / s_learned,
+            "apply_us": apply_us,
+            "corrector_roofline": {
+                "kernel": "k_conv x3 + input pack (network forward pass)", "bound": "hbm",
+                "achieved": fwd_bytes / (fwd_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": fwd_bytes / (fwd_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                "avg_launch_us": fwd_us, "alg_bytes_per_launch": fwd_bytes,
+                "mfma_tflops": fwd_flop / (fwd_us * 1e-6) / 1e12,
+                "mfma_peak_tflops_bf16": 2500.0},
             "sample": f"{blocks} blocks of {every} coarse {nc}^3 steps + correction (BF16 MFMA "
                       f"3-layer conv) vs this run's {args.n}^3 step; weights random (cost does "
                       "not depend on them)"}

@@ -965,6 +965,7 @@ wdm_status run_steps(wdm_plan* p, int64_t n, double dt, After after) {
     for (const auto& c : p->classes) {
         const Launch L{s, p->table, c.first, c.count};
         HIPCHK(dt != 0.0 ? launch_set_dt(L, dt, 0) : launch_set_dt(L, 0.0, 1));
+        HIPCHK(launch_kinetic_tables(L, p->prec, int64_t(c.nx) + int64_t(c.ny) * c.nz));
         if (c.absorb) HIPCHK(launch_absorb_tables(L));
     }
     if (after == kBlockGraph) {

@@ -146,6 +146,30 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
         f32x4 acc[kCTY];
 #pragma unroll
         for (int s2 = 0; s2 < kCTY; ++s2) acc[s2] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (CPIN == 16) {
+            // one K chunk per tap (16 channels).  For fixed (dx, dz) the four
+            // segments and three dy offsets read only six brick rows (segment
+            // s at offset dy is row s + dy): each B operand read from LDS
+            // serves two MFMAs on average.
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz) {
+                    uint64_t braw[kCTY + 2];
+#pragma unroll
+                    for (int r = 0; r < kCTY + 2; ++r)
+                        braw[r] = brick[(((wave + dx) * kCBY + r) * kCBZ + col + dz) * W8 + kq];
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int s2 = 0; s2 < kCTY; ++s2) {
+                            bf16x4 b;
+                            __builtin_memcpy(&b, &braw[s2 + dy], sizeof(b));
+                            acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                                a[dx * 9 + dy * 3 + dz], b, acc[s2], 0, 0, 0);
+                        }
+                }
+        } else {
 #pragma unroll
         for (int ch = 0; ch < KC; ++ch) {
             const int k0 = ch * 16 + 4 * kq;
@@ -160,6 +184,7 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
                 __builtin_memcpy(&b, &bw, sizeof(b));
                 acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ch], b, acc[s2], 0, 0, 0);
             }
+        }
         }
         // epilogue: lane holds out[cell][4*kq + q] of each segment
         const int x = x0 + wave, z = z0 + col, m0 = 4 * kq;

@@ -11,6 +11,9 @@
 // and each non-zero node costs one global atomic add per work-group.
 #include "wdm_internal.hpp"
 
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_min_i32(int);
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);
+
 #include <algorithm>
 #include <type_traits>
 
@@ -95,8 +98,11 @@ __device__ __forceinline__ void cic_accel(const T* __restrict__ phi, const Membe
         // from the z faces each row is one vector load.
         if (c.k >= 1 && c.k + 2 < nz) {
             float v[4][4][4];
+            // 32-bit row offsets (cells < 2^27 for axes <= 512): the loads
+            // take the scalar base plus a 32-bit vector offset
             auto row = [&](int a, int b) {
-                return phi + (int64_t(ix[a]) * ny + iy[b]) * nz;
+                return phi + uint32_t((uint32_t(ix[a]) * uint32_t(ny) + uint32_t(iy[b])) *
+                                      uint32_t(nz));
             };
 #pragma unroll
             for (int a = 1; a < 3; ++a)
@@ -221,16 +227,9 @@ constexpr int tile_nodes() {
 }
 constexpr int kParticleWG = 256;
 
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return v;
-}
+// wavefront minimum / maximum (DPP reductions)
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
 // Work-group deposit.  The particles of a work-group are consecutive in
 // Morton order, so their cells usually fill a small box: if that box (plus the
@@ -289,15 +288,28 @@ __device__ __forceinline__ void deposit_group(A* __restrict__ grid, const Member
     __syncthreads();
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int eyz = ey * ez;
+    // (ti, tj, tk) of node t = tid, advanced by the stride kParticleWG with
+    // carries: two divisions per chunk instead of two per node
+    int ti = tid / eyz, tj = (tid - ti * eyz) / ez, tk = tid - ti * eyz - tj * ez;
+    const int si = kParticleWG / eyz, sj = (kParticleWG - si * eyz) / ez,
+              sk = kParticleWG - si * eyz - sj * ez;
     for (int t = tid; t < vol; t += kParticleWG) {
         const A v = tile[t];
+        const int ci = ti, cj = tj, ck = tk;
+        tk += sk;
+        tj += sj;
+        ti += si;
+        if (tk >= ez) {
+            tk -= ez;
+            ++tj;
+        }
+        if (tj >= ey) {
+            tj -= ey;
+            ++ti;
+        }
         if (v == A(0)) continue;
-        const int ti = t / eyz;
-        const int r = t - ti * eyz;
-        const int tj = r / ez;
-        const int tk = r - tj * ez;
-        // i0 + ti <= max cell + 1 <= n: one wrap at most
-        int gi = i0 + ti, gj = j0 + tj, gk = k0 + tk;
+        // i0 + ci <= max cell + 1 <= n: one wrap at most
+        int gi = i0 + ci, gj = j0 + cj, gk = k0 + ck;
         if (gi >= nx) gi -= nx;
         if (gj >= ny) gj -= ny;
         if (gk >= nz) gk -= nz;

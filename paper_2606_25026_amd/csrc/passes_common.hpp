@@ -237,8 +237,8 @@ __device__ __forceinline__ void store_slots(const cplx<T>* v, cplx<T>* g, int64_
 // factored as e_x(k_x) e_yz(k_y, k_z) and formed in FP64: each mode gets the
 // same factor every step, so a factor rounded to single precision would add up
 // coherently over a run.  complex64 keeps each factor as an unevaluated sum
-// hi + lo of two complex64 numbers.  Written by the threads of P1's merged
-// variant (grid-stride over nx + ny nz entries), read by P3 of the same step.
+// hi + lo of two complex64 numbers.  Written once per wdm_step call, after the
+// call's dt is set (grid-stride over nx + ny nz entries), read by P3.
 template <typename T>
 __device__ __forceinline__ void write_kinetic_table(const MemberDev& m, double dt, int64_t nthr,
                                                     int64_t gtid) {

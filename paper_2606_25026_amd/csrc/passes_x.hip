@@ -288,6 +288,27 @@ hipError_t launch_x_mul_green(const Launch& L, int prec, int nx, int ny, int nz)
     return dispatch_n<XMulGreen>(nx, L, prec, ny, nz);
 }
 
+// The kinetic factor tables of the dt in use, for every member of the class
+// (grid-stride over nx + ny nz entries per member).
+template <typename T>
+__global__ __launch_bounds__(256) void k_kinetic_tables(const MemberDev* __restrict__ mems,
+                                                        int first) {
+    const MemberDev& m = mems[first + blockIdx.y];
+    write_kinetic_table<T>(m, gldr(m.dt, 0), int64_t(gridDim.x) * blockDim.x,
+                           int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_kinetic_tables(const Launch& L, int prec, int64_t max_entries) {
+    int64_t g = (max_entries + 255) / 256;
+    if (g > 1024) g = 1024;
+    const dim3 grid(unsigned(g), unsigned(L.count));
+    if (prec)
+        k_kinetic_tables<double><<<grid, 256, 0, L.stream>>>(L.members, L.first);
+    else
+        k_kinetic_tables<float><<<grid, 256, 0, L.stream>>>(L.members, L.first);
+    return hipGetLastError();
+}
+
 hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz, int variant) {
     return dispatch_n<XKin>(nx, L, prec, ny, nz, variant);
 }

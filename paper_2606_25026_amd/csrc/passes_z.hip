@@ -181,8 +181,6 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     __syncthreads();
     pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
     store_slots<FP, FP::last()>(v, psi, q * NZ, 1, ok, ln);
-    write_kinetic_table<T>(m, dt, int64_t(gridDim.x) * blockDim.x,
-                           int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 

@@ -41,7 +41,7 @@ struct MemberDev {
     void* spec;       // complex half spectrum [nx][ny][nz/2] (kz = 0 .. nz/2-1)
     void* spec_nyq;   // complex Nyquist plane [nx][ny] (kz = nz/2)
     void* scratch;    // complex, n cells (diagnostics only)
-    // kinetic factors of the step's dt, written by P1 and read by P3:
+    // kinetic factors of the call's dt, written once per wdm_step call and read by P3:
     // [0, nx) e_x(k_x); [nx, nx + ny nz) e_yz(k_y, k_z) / N at q = iy nz + iz.
     // 16 bytes per entry: (hi, lo) complex64 pair, or one complex128.
     void* kin;
@@ -134,6 +134,9 @@ hipError_t launch_y_fft_psi(const Launch& L, int prec, int nx, int ny, int nz, b
                             int variant = 0);
 hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, bool inverse,
                              int variant = 0);
+// Kinetic factor tables e_x, e_yz / N of the dt in use (dt[0]) for every member
+// of the class; max_entries = the largest nx + ny nz of the class.
+hipError_t launch_kinetic_tables(const Launch& L, int prec, int64_t max_entries);
 // P3: x forward, kinetic phase exp(-i eta |k|^2 dt/2)/N, x inverse.
 hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz, int variant = 0);
 // P5: z inverse of psi (optional), rho = |psi|^2 + rho_b (rho_b cleared), R2C along z.
