@@ -72,76 +72,103 @@ constexpr int kCBrick = kCBX * kCBY * kCBZ;
 // v in [-1, n + kCTZ]: periodic index in [0, n)
 __device__ __forceinline__ int wrap_edge(int v, int n) { return (v + n) % n; }
 
+// The input brick of tile t: every 8-byte word of its cells (one 16-byte half
+// cell per thread and slot for 16 channels, one 8-byte cell for 4), loaded into
+// registers; stored to LDS by brick_store.
+template <int W8>
+struct BrickRegs {
+    static constexpr int kWords = kCBrick * W8;              // 8-byte words
+    static constexpr int kPer = W8 == 4 ? 2 : 1;             // words per load
+    static constexpr int kLoads = kWords / kPer;
+    static constexpr int kIt = (kLoads + 255) / 256;
+    u32x4 v[W8 == 4 ? kIt : 1];
+    uint64_t w[W8 == 4 ? 1 : kIt];
+};
+
+template <int CPIN, int W8>
+__device__ __forceinline__ void brick_load(BrickRegs<W8>& R, const uint16_t* __restrict__ in,
+                                           int64_t t, int n, int tz, int ty) {
+    using B = BrickRegs<W8>;
+    const int tid = int(threadIdx.x);
+    const int iz = int(t % tz);
+    const int64_t r = t / tz;
+    const int x0 = int(r / ty) * kCTX, y0 = int(r % ty) * kCTY, z0 = iz * kCTZ;
+#pragma unroll
+    for (int k = 0; k < B::kIt; ++k) {
+        const int i = tid + k * 256;
+        if (i < B::kLoads) {
+            const int c = i / (W8 / B::kPer), bz = c % kCBZ, rr = c / kCBZ, by = rr % kCBY,
+                      bx = rr / kCBY;
+            const int64_t g = (int64_t(wrap_edge(x0 + bx - 1, n)) * n +
+                               wrap_edge(y0 + by - 1, n)) * n + wrap_edge(z0 + bz - 1, n);
+            if constexpr (W8 == 4)
+                R.v[k] = *(const WDM_GAS u32x4*)(in + g * CPIN + (i & 1) * 8);
+            else
+                R.w[k] = *(const WDM_GAS uint64_t*)(in + g * CPIN);
+        }
+    }
+}
+
+template <int W8>
+__device__ __forceinline__ void brick_store(const BrickRegs<W8>& R, uint64_t* brick) {
+    using B = BrickRegs<W8>;
+    const int tid = int(threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < B::kIt; ++k) {
+        const int i = tid + k * 256;
+        if (i < B::kLoads) {
+            if constexpr (W8 == 4)
+                reinterpret_cast<u32x4*>(brick)[i] = R.v[k];
+            else
+                brick[i] = R.w[k];
+        }
+    }
+}
+
 // in: bf16 [cells][CPIN]; wmat: bf16 [16][KC*16] (rows >= COUT zero);
 // out: see ConvEpi.  COUT real output channels (<= 16), CPOUT padded store width.
-// Persistent: work-group b handles tiles b, b + gridDim.x, ...
+// Persistent: work-group b handles tiles b, b + gridDim.x, ...; the next
+// tile's brick is loaded into registers while the current one is computed.
+// The layer's weights (the MFMA A operand) sit in LDS, rows padded by four
+// entries so the sixteen rows a wavefront reads fall on different banks.
 template <int CPIN, int COUT, int CPOUT, int EPI>
 __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in,
-                                              const uint16_t* __restrict__ wmat,
-                                              const float* __restrict__ bias,
-                                              const uint16_t* __restrict__ mask, void* out,
-                                              int n) {
+                                                 const uint16_t* __restrict__ wmat,
+                                                 const float* __restrict__ bias,
+                                                 const uint16_t* __restrict__ mask, void* out,
+                                                 int n) {
     constexpr int KC = (27 * CPIN + 15) / 16;
+    constexpr int KW = KC * 16 + 4;              // LDS row of the weights (bf16 entries)
     constexpr int W8 = CPIN / 4;                 // 8-byte words per brick cell
     __shared__ __align__(16) uint64_t brick[kCBrick * W8];
+    __shared__ __align__(16) uint16_t wl[16 * KW];
     const int tid = int(threadIdx.x);
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int col = lane & 15;                   // z within the segment; A row
     const int kq = lane >> 4;                    // which 4-wide k group
-    bf16x4 a[KC];
-#pragma unroll
-    for (int ch = 0; ch < KC; ++ch) a[ch] = ld_bf16x4(wmat, int64_t(col) * (KC * 16) + ch * 16 + 4 * kq);
+    for (int i = tid; i < 16 * KC * 4; i += 256) {
+        const int row = i / (KC * 4), q = i - row * (KC * 4);
+        *reinterpret_cast<uint64_t*>(&wl[row * KW + 4 * q]) =
+            *(const WDM_GAS uint64_t*)(wmat + int64_t(row) * (KC * 16) + 4 * q);
+    }
+    auto a_op = [&](int ch) {
+        bf16x4 a;
+        const uint64_t w = *reinterpret_cast<const uint64_t*>(&wl[col * KW + ch * 16 + 4 * kq]);
+        __builtin_memcpy(&a, &w, sizeof(a));
+        return a;
+    };
     const int tx = (n + kCTX - 1) / kCTX, ty = (n + kCTY - 1) / kCTY, tz = (n + kCTZ - 1) / kCTZ;
     const int64_t ntiles = int64_t(tx) * ty * tz;
+    BrickRegs<W8> R;
+    if (int64_t(blockIdx.x) < ntiles) brick_load<CPIN, W8>(R, in, blockIdx.x, n, tz, ty);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int iz = int(t % tz);
         const int64_t r = t / tz;
         const int x0 = int(r / ty) * kCTX, y0 = int(r % ty) * kCTY, z0 = iz * kCTZ;
-        // stage the brick: every load issued before the LDS stores
-        if constexpr (W8 == 4) {
-            constexpr int kChunks = kCBrick * 2;  // 16-byte halves of 32-byte cells
-            constexpr int kIt = (kChunks + 255) / 256;
-            u32x4 v[kIt];
-#pragma unroll
-            for (int k = 0; k < kIt; ++k) {
-                const int i = tid + k * 256;
-                v[k] = u32x4{0u, 0u, 0u, 0u};
-                if (i < kChunks) {
-                    const int c = i >> 1, bz = c % kCBZ, rr = c / kCBZ, by = rr % kCBY,
-                              bx = rr / kCBY;
-                    const int64_t g = (int64_t(wrap_edge(x0 + bx - 1, n)) * n +
-                                       wrap_edge(y0 + by - 1, n)) * n + wrap_edge(z0 + bz - 1, n);
-                    v[k] = *(const WDM_GAS u32x4*)(in + g * 16 + (i & 1) * 8);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kIt; ++k) {
-                const int i = tid + k * 256;
-                if (i < kChunks) reinterpret_cast<u32x4*>(brick)[i] = v[k];
-            }
-        } else {
-            constexpr int kIt = (kCBrick * W8 + 255) / 256;
-            uint64_t v[kIt];
-#pragma unroll
-            for (int k = 0; k < kIt; ++k) {
-                const int i = tid + k * 256;
-                v[k] = 0ull;
-                if (i < kCBrick * W8) {
-                    const int c = i / W8, bz = c % kCBZ, rr = c / kCBZ, by = rr % kCBY,
-                              bx = rr / kCBY;
-                    const int64_t g = (int64_t(wrap_edge(x0 + bx - 1, n)) * n +
-                                       wrap_edge(y0 + by - 1, n)) * n + wrap_edge(z0 + bz - 1, n);
-                    v[k] = *(const WDM_GAS uint64_t*)(in + g * CPIN + (i % W8) * 4);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kIt; ++k) {
-                const int i = tid + k * 256;
-                if (i < kCBrick * W8) brick[i] = v[k];
-            }
-        }
+        brick_store<W8>(R, brick);
         __syncthreads();
+        if (t + gridDim.x < ntiles) brick_load<CPIN, W8>(R, in, t + gridDim.x, n, tz, ty);
         // wavefront `wave` owns x = x0 + wave, y = y0 + s (s < 4), z = z0 + col
         f32x4 acc[kCTY];
 #pragma unroll
@@ -157,34 +184,37 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
                 for (int dz = 0; dz < 3; ++dz) {
                     uint64_t braw[kCTY + 2];
 #pragma unroll
-                    for (int r = 0; r < kCTY + 2; ++r)
-                        braw[r] = brick[(((wave + dx) * kCBY + r) * kCBZ + col + dz) * W8 + kq];
+                    for (int rr = 0; rr < kCTY + 2; ++rr)
+                        braw[rr] = brick[(((wave + dx) * kCBY + rr) * kCBZ + col + dz) * W8 + kq];
 #pragma unroll
-                    for (int dy = 0; dy < 3; ++dy)
+                    for (int dy = 0; dy < 3; ++dy) {
+                        const bf16x4 a = a_op(dx * 9 + dy * 3 + dz);
 #pragma unroll
                         for (int s2 = 0; s2 < kCTY; ++s2) {
                             bf16x4 b;
                             __builtin_memcpy(&b, &braw[s2 + dy], sizeof(b));
-                            acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                                a[dx * 9 + dy * 3 + dz], b, acc[s2], 0, 0, 0);
+                            acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s2], 0,
+                                                                                0, 0);
                         }
+                    }
                 }
         } else {
 #pragma unroll
-        for (int ch = 0; ch < KC; ++ch) {
-            const int k0 = ch * 16 + 4 * kq;
-            const int tap = k0 / CPIN, c = k0 % CPIN;
-            const bool live = k0 < 27 * CPIN;
-            const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
-            const int cell0 = ((wave + dx) * kCBY + dy) * kCBZ + col + dz;
+            for (int ch = 0; ch < KC; ++ch) {
+                const int k0 = ch * 16 + 4 * kq;
+                const int tap = k0 / CPIN, c = k0 % CPIN;
+                const bool live = k0 < 27 * CPIN;
+                const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
+                const int cell0 = ((wave + dx) * kCBY + dy) * kCBZ + col + dz;
+                const bf16x4 a = a_op(ch);
 #pragma unroll
-            for (int s2 = 0; s2 < kCTY; ++s2) {
-                const uint64_t bw = live ? brick[(cell0 + s2 * kCBZ) * W8 + c / 4] : 0ull;
-                bf16x4 b;
-                __builtin_memcpy(&b, &bw, sizeof(b));
-                acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ch], b, acc[s2], 0, 0, 0);
+                for (int s2 = 0; s2 < kCTY; ++s2) {
+                    const uint64_t bw = live ? brick[(cell0 + s2 * kCBZ) * W8 + c / 4] : 0ull;
+                    bf16x4 b;
+                    __builtin_memcpy(&b, &bw, sizeof(b));
+                    acc[s2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s2], 0, 0, 0);
+                }
             }
-        }
         }
         // epilogue: lane holds out[cell][4*kq + q] of each segment
         const int x = x0 + wave, z = z0 + col, m0 = 4 * kq;
@@ -218,7 +248,7 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
                      (cell * CPOUT + m0) / 4, packed);
             }
         }
-        __syncthreads();   // the next tile reuses the brick
+        __syncthreads();   // the next tile's brick overwrites this one
     }
 }
 
@@ -571,9 +601,10 @@ hipError_t net_unpack_grads(hipStream_t s, const float* sum, float* gw, float* g
     return hipGetLastError();
 }
 
-// Persistent grid of the convolution: one work-group per tile up to eight per
-// compute unit.
-static unsigned conv_blocks(int n) {
+// Persistent grid of the convolution: one work-group per tile up to `per_cu`
+// per compute unit (the kernel's resident work-groups: three at 16 input
+// channels, set by registers; eight at 4).
+static unsigned conv_blocks(int n, int per_cu) {
     static int cus = 0;
     if (cus == 0) {
         int dev = 0, c = 0;
@@ -583,30 +614,32 @@ static unsigned conv_blocks(int n) {
     }
     const int64_t tiles = int64_t((n + kCTX - 1) / kCTX) * ((n + kCTY - 1) / kCTY) *
                           ((n + kCTZ - 1) / kCTZ);
-    const int64_t cap = int64_t(8) * cus;
+    const int64_t cap = int64_t(per_cu) * cus;
     return unsigned(tiles < cap ? tiles : cap);
 }
 
 hipError_t conv_forward_layer(hipStream_t s, int layer, const uint16_t* in, const uint16_t* w,
                               const float* b, void* out, int n) {
-    const unsigned g = conv_blocks(n);
     if (layer == 0)
-        k_conv<4, 16, 16, kEpiBiasReluBf16><<<g, 256, 0, s>>>(in, w, b, nullptr, out, n);
+        k_conv<4, 16, 16, kEpiBiasReluBf16><<<conv_blocks(n, 8), 256, 0, s>>>(in, w, b, nullptr,
+                                                                             out, n);
     else if (layer == 1)
-        k_conv<16, 16, 16, kEpiBiasReluBf16><<<g, 256, 0, s>>>(in, w, b, nullptr, out, n);
+        k_conv<16, 16, 16, kEpiBiasReluBf16><<<conv_blocks(n, 3), 256, 0, s>>>(in, w, b, nullptr,
+                                                                              out, n);
     else
-        k_conv<16, 2, 4, kEpiBiasF32><<<g, 256, 0, s>>>(in, w, b, nullptr, out, n);
+        k_conv<16, 2, 4, kEpiBiasF32><<<conv_blocks(n, 3), 256, 0, s>>>(in, w, b, nullptr, out, n);
     return hipGetLastError();
 }
 
 // Gradient wrt the input of layer `layer` (1 or 2), masked by that input's ReLU.
 hipError_t conv_backward_data(hipStream_t s, int layer, const uint16_t* dz, const uint16_t* wbwd,
                               const uint16_t* act_in, uint16_t* dact, int n) {
-    const unsigned g = conv_blocks(n);
     if (layer == 2)
-        k_conv<4, 16, 16, kEpiMaskBf16><<<g, 256, 0, s>>>(dz, wbwd, nullptr, act_in, dact, n);
+        k_conv<4, 16, 16, kEpiMaskBf16><<<conv_blocks(n, 8), 256, 0, s>>>(dz, wbwd, nullptr,
+                                                                         act_in, dact, n);
     else
-        k_conv<16, 16, 16, kEpiMaskBf16><<<g, 256, 0, s>>>(dz, wbwd, nullptr, act_in, dact, n);
+        k_conv<16, 16, 16, kEpiMaskBf16><<<conv_blocks(n, 3), 256, 0, s>>>(dz, wbwd, nullptr,
+                                                                          act_in, dact, n);
     return hipGetLastError();
 }
 
