@@ -370,19 +370,19 @@ hipError_t enqueue_vacuum_poisson(wdm_plan* p, hipStream_t s, int first, int cou
     hipError_t e = timed_on(p, s, kKZDens,
                             [&] { return launch_z_density(L, prec, nx, ny, nz, op); });
     if (e != hipSuccess) return e;
-    // Only the x < nx half of the padded grid is ever written: the forward z
-    // and y transforms would see zeros in every pencil with x >= nx, and the
-    // inverse y and z results there are not needed, so those four passes
-    // cover the lower half; the x pass reads and writes that half only, with
-    // the zeros of the other half implied (it stays zero from plan creation).
+    // The padded density is zero outside the x < nx, y < ny corner: the forward
+    // z pass reads the density rows and fills only those padded rows, the y
+    // passes treat the y >= ny half of each x < nx pencil as zeros (forward) or
+    // leave it unstored (inverse), the x pass reads and writes the x < nx half
+    // with the other half implied zero, and the inverse z pass writes the
+    // corner's real part to Phi.  No other part of the padded grid is read.
     e = timed_on(p, s, kKVacuum, [&] {
-        hipError_t r = launch_pad_density(L, prec, nx, ny);
-        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 2, false, 0, true);
-        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 1, false, 0, true);
-        if (r == hipSuccess) r = launch_x_mul_green(LP, prec, 2 * nx, 2 * ny, 2 * nz);
-        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 1, true, 0, true);
-        if (r == hipSuccess) r = launch_axis_fft(LP, prec, 2 * nx, 2 * ny, 2 * nz, 2, true, 0, true);
-        if (r == hipSuccess) r = launch_unpad(L, prec, nx, ny);
+        const int px = 2 * nx, py = 2 * ny, pz = 2 * nz;
+        hipError_t r = launch_vac_fft(LP, prec, px, py, pz, 0);
+        if (r == hipSuccess) r = launch_vac_fft(LP, prec, px, py, pz, 1);
+        if (r == hipSuccess) r = launch_x_mul_green(LP, prec, px, py, pz);
+        if (r == hipSuccess) r = launch_vac_fft(LP, prec, px, py, pz, 2);
+        if (r == hipSuccess) r = launch_vac_fft(LP, prec, px, py, pz, 3);
         return r;
     });
     if (e != hipSuccess) return e;
@@ -404,11 +404,6 @@ hipError_t compute_green(wdm_plan* p) {
                 hipSuccess)
                 return e;
         if ((e = launch_green_extract(L, p->prec, cells)) != hipSuccess) return e;
-        // the solves never write the x >= nx half of the padded grid again
-        for (int d = c.first; d < c.first + c.count; ++d)
-            if ((e = launch_zero(p->stream, p->host[d].pad,
-                                 size_t(8 * cells) * (p->prec ? 16 : 8))) != hipSuccess)
-                return e;
     }
     return e;
 }

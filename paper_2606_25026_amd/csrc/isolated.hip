@@ -3,12 +3,14 @@
 //
 // The isolated potential is the linear convolution of the density with the
 // free-space Green's function, done as a circular convolution on the grid
-// zero-padded to (2 nx, 2 ny, 2 nz): the density is copied into the padded
-// grid's corner, transformed, multiplied by the transform of the padded Green's
-// function (real and even, computed once per plan) and transformed back; the
-// corner is the potential.  The axis transforms run on the padded grid through
-// a second member table whose entries describe it; the x pass multiplies by
-// the Green's function between its forward and inverse transforms.
+// zero-padded to (2 nx, 2 ny, 2 nz): the density, in the padded grid's corner,
+// is transformed, multiplied by the transform of the padded Green's function
+// (real and even, computed once per plan) and transformed back; the corner is
+// the potential.  The transforms (passes_y.hip, launch_vac_fft, and the x pass
+// here, which multiplies by the Green's function between its forward and
+// inverse transforms) run on the padded grid through a second member table
+// whose entries describe it, and touch only the parts of it that can be
+// non-zero.
 #include "wdm_internal.hpp"
 #include "fft_device.hpp"
 
@@ -20,40 +22,6 @@ typedef float wdm_f4v __attribute__((ext_vector_type(4)));
 static unsigned iso_grid(int64_t count) {
     int64_t g = (count + kIsoThreads - 1) / kIsoThreads;
     return unsigned(g < 8192 ? g : 8192);
-}
-
-// The x < nx half of the padded grid from the density held in Phi (zeros
-// outside the nx ny nz corner); the other half stays zero from plan creation.
-// One work-group per padded z row (x < nx), its threads along z.
-template <typename T>
-__global__ __launch_bounds__(kIsoThreads) void k_pad_density(const MemberDev* __restrict__ mems,
-                                                             int first) {
-    const MemberDev& m = mems[first + blockIdx.y];
-    const int pny = 2 * m.ny, pnz = 2 * m.nz;
-    const int rows = m.nx * pny;
-    cplx<T>* pad = static_cast<cplx<T>*>(m.pad);
-    const T* rho = static_cast<const T*>(m.phi);
-    for (int r = int(blockIdx.x); r < rows; r += int(gridDim.x)) {
-        const int i = r / pny, j = r - i * pny;
-        cplx<T>* row = pad + int64_t(r) * pnz;
-        const bool inside = j < m.ny;
-        const T* src = rho + (int64_t(i) * m.ny + (inside ? j : 0)) * m.nz;
-        // two neighbouring values per thread (every length is even); complex64
-        // pairs go out as one 16-byte store
-        for (int k = 2 * int(threadIdx.x); k < pnz; k += 2 * kIsoThreads) {
-            T v0 = T(0), v1 = T(0);
-            if (inside && k < m.nz) {
-                v0 = gldr(src, k);
-                v1 = gldr(src, k + 1);
-            }
-            if constexpr (std::is_same_v<T, float>) {
-                ((WDM_GAS wdm_f4v*)(row + k))[0] = wdm_f4v{v0, 0.0f, v1, 0.0f};
-            } else {
-                gst(row, k, cplx<T>{v0, T(0)});
-                gst(row, k + 1, cplx<T>{v1, T(0)});
-            }
-        }
-    }
 }
 
 // g = -G dV / |r| between nodes, -G h^2 C for the node itself (cubic cells of
@@ -111,30 +79,6 @@ __global__ __launch_bounds__(kIsoThreads) void k_green_extract(const MemberDev* 
     }
 }
 
-// Phi / nz from the corner of the padded grid; one work-group per z row.
-template <typename T>
-__global__ __launch_bounds__(kIsoThreads) void k_unpad(const MemberDev* __restrict__ mems,
-                                                       int first) {
-    const MemberDev& m = mems[first + blockIdx.y];
-    const int rows = m.nx * m.ny;
-    const int pny = 2 * m.ny, pnz = 2 * m.nz;
-    const cplx<T>* pad = static_cast<const cplx<T>*>(m.pad);
-    T* phi = static_cast<T*>(m.phi);
-    for (int r = int(blockIdx.x); r < rows; r += int(gridDim.x)) {
-        const int i = r / m.ny, j = r - i * m.ny;
-        const cplx<T>* src = pad + (int64_t(i) * pny + j) * pnz;
-        T* dst = phi + int64_t(r) * m.nz;
-        if constexpr (std::is_same_v<T, float>) {
-            // two neighbouring nodes per thread: one 16-byte load, one 8-byte store
-            for (int k = 2 * int(threadIdx.x); k < m.nz; k += 2 * kIsoThreads) {
-                const wdm_f4v a = ((const WDM_GAS wdm_f4v*)(src + k))[0];
-                ((WDM_GAS wdm_f2v*)(dst + k))[0] = wdm_f2v{a.x, a.z};
-            }
-        } else {
-            for (int k = int(threadIdx.x); k < m.nz; k += kIsoThreads) gstr(dst, k, gld(src, k).re);
-        }
-    }
-}
 
 // Mean gradient of ext along each axis over the nodes symmetric about the
 // centre node: sums of (ext[n-1] - ext[1]) over the other two axes, per
@@ -203,34 +147,11 @@ __global__ __launch_bounds__(kIsoThreads) void k_tidal_apply(const MemberDev* __
         return hipGetLastError();                                                          \
     } while (0)
 
-// one work-group per z row: padded rows of the lower half, or corner rows
-static hipError_t launch_rows(const Launch& L, int prec, int64_t rows, bool pad) {
-    const dim3 grid(unsigned(rows < 65536 ? rows : 65536), unsigned(L.count));
-    if (pad) {
-        if (prec)
-            k_pad_density<double><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
-        else
-            k_pad_density<float><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
-    } else {
-        if (prec)
-            k_unpad<double><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
-        else
-            k_unpad<float><<<grid, kIsoThreads, 0, L.stream>>>(L.members, L.first);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_pad_density(const Launch& L, int prec, int nx, int ny) {
-    return launch_rows(L, prec, int64_t(nx) * 2 * ny, true);
-}
 hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_green_fill, 8 * max_cells);
 }
 hipError_t launch_green_extract(const Launch& L, int prec, int64_t max_cells) {
     WDM_ISO_LAUNCH(k_green_extract, 8 * max_cells);
-}
-hipError_t launch_unpad(const Launch& L, int prec, int nx, int ny) {
-    return launch_rows(L, prec, int64_t(nx) * ny, false);
 }
 #undef WDM_ISO_LAUNCH
 

@@ -70,6 +70,106 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<N>::type, T>())) void k_a
     }
 }
 
+// Transforms of the vacuum solve's zero-padded grid (Sec. 3.2.1), run on the
+// padded member table (doubled lengths, psi = the padded grid).  Only the
+// quarter of the padded grid that can be non-zero before the x pass (x < nx,
+// y < ny) is read or written along z, and the y passes see the y >= ny half of
+// each pencil as zeros (forward) or do not store it (inverse), so the padded
+// grid's y >= ny rows are never touched:
+//   kVacZFwd  the density rows (real, nz values, held in Phi) zero-extended to
+//             2 nz, forward z transform into the padded rows (x < nx, y < ny);
+//   kVacYFwd  forward y transform of the x < nx pencils, inputs y >= ny zero;
+//   kVacYInv  inverse y transform of the x < nx pencils, outputs y < ny stored;
+//   kVacZInv  inverse z transform of the padded rows (x < nx, y < ny), the real
+//             part of the first nz values written to Phi.
+enum VacMode : int { kVacZFwd = 0, kVacYFwd = 1, kVacYInv = 2, kVacZInv = 3 };
+
+template <int N, typename T, int MODE>
+__global__ __launch_bounds__((wg_size<typename PlanFor<N>::type, T>())) void k_vac_fft(
+    const MemberDev* __restrict__ mems, int first) {
+    using FP = typename PlanFor<N>::type;
+    constexpr bool STRIDED = MODE == kVacYFwd || MODE == kVacYInv;
+    constexpr bool INV = MODE == kVacYInv || MODE == kVacZInv;
+    constexpr int H = N / 2;   // the unpadded length along the transformed axis
+    using LN = Lanes<FP, T, STRIDED>;
+    __shared__ T lds[lds_entries<FP, T, false>()];
+    __shared__ cplx<T> tw[tw_entries<T>(N)];
+    const MemberDev& m = mems[first + blockIdx.y];
+    load_twiddles<N, wg_size<FP, T>()>(tw, STRIDED ? m.tw_y : m.tw_z);
+    __syncthreads();
+    const LN ln;
+    const int64_t q = int64_t(blockIdx.x) * LN::PP + ln.p;
+    cplx<T>* pad = static_cast<cplx<T>*>(m.psi);
+    cplx<T> v[FP::E];
+    if constexpr (STRIDED) {
+        // y pencils of the padded [2nx][2ny][2nz] grid with x < nx: q = x 2nz + z
+        const int64_t pny = m.ny, pnz = m.nz;
+        const int64_t count = int64_t(m.nx / 2) * pnz;
+        const bool ok = q < count;
+        const int64_t b = ok ? (q / pnz) * (pny * pnz) + (q % pnz) : 0;
+        cplx<T>* lane = pad + (b + int64_t(ln.t) * pnz);
+#pragma unroll
+        for (int s = 0; s < FP::E; ++s) {
+            constexpr int R0 = FP::first();
+            const int e = ln.t + slot_const<FP, R0>(s);
+            v[s] = (ok && (MODE == kVacYInv || e < H)) ? gld(lane, int64_t(slot_const<FP, R0>(s)) * pnz)
+                                                       : cplx<T>{T(0), T(0)};
+        }
+        pencil_fft<FP, INV, T>(v, lds, tw, ln.t, ln);
+        if (!ok) return;
+#pragma unroll
+        for (int s = 0; s < FP::E; ++s) {
+            constexpr int R1 = FP::last();
+            const int e = ln.t + slot_const<FP, R1>(s);
+            if (MODE == kVacYFwd || e < H) gst(lane, int64_t(slot_const<FP, R1>(s)) * pnz, v[s]);
+        }
+    } else {
+        // rows (x, y), x < nx, y < ny: q = x ny + y
+        const int rnx = m.nx / 2, rny = m.ny / 2;
+        const bool ok = q < int64_t(rnx) * rny;
+        const int64_t x = ok ? q / rny : 0, y = ok ? q - x * rny : 0;
+        const int64_t pb = (x * m.ny + y) * m.nz;      // padded row
+        T* phi = static_cast<T*>(m.phi) + (ok ? q : 0) * H;
+        if constexpr (MODE == kVacZFwd) {
+#pragma unroll
+            for (int s = 0; s < FP::E; ++s) {
+                const int e = ln.t + slot_const<FP, FP::first()>(s);
+                v[s] = cplx<T>{(ok && e < H) ? gldr(phi, e) : T(0), T(0)};
+            }
+            pencil_fft<FP, false, T>(v, lds, tw, ln.t, ln);
+            store_slots<FP, FP::last()>(v, pad, pb, 1, ok, ln);
+        } else {
+            load_slots<FP, FP::first()>(v, pad, pb, 1, ok, ln);
+            pencil_fft<FP, true, T>(v, lds, tw, ln.t, ln);
+            if (!ok) return;
+#pragma unroll
+            for (int s = 0; s < FP::E; ++s) {
+                const int e = ln.t + slot_const<FP, FP::last()>(s);
+                if (e < H) gstr(phi, e, v[s].re);
+            }
+        }
+    }
+}
+
+template <int N>
+struct VacFft {
+    template <typename T>
+    static hipError_t go(const Launch& L, int64_t pencils, int mode) {
+        dim3 grid(unsigned(tiles<N, T>(pencils)), unsigned(L.count));
+        const auto b = block<N, T>();
+        switch (mode) {
+            case kVacZFwd: k_vac_fft<N, T, kVacZFwd><<<grid, b, 0, L.stream>>>(L.members, L.first); break;
+            case kVacYFwd: k_vac_fft<N, T, kVacYFwd><<<grid, b, 0, L.stream>>>(L.members, L.first); break;
+            case kVacYInv: k_vac_fft<N, T, kVacYInv><<<grid, b, 0, L.stream>>>(L.members, L.first); break;
+            default: k_vac_fft<N, T, kVacZInv><<<grid, b, 0, L.stream>>>(L.members, L.first); break;
+        }
+        return hipGetLastError();
+    }
+    static hipError_t run(const Launch& L, int prec, int64_t pencils, int mode) {
+        return prec ? go<double>(L, pencils, mode) : go<float>(L, pencils, mode);
+    }
+};
+
 // Spectral kinetic energy: x forward FFT of scratch (already z and y
 // transformed) and FP64 partial sums of |k|^2 |psi_k|^2 per work-group.
 
@@ -143,14 +243,18 @@ hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, 
     return dispatch_n<YFft>(ny, L, prec, nx, nz, inverse, true, variant);
 }
 hipError_t launch_axis_fft(const Launch& L, int prec, int nx, int ny, int nz, int axis,
-                           bool inverse, int which, bool lower_x_half) {
+                           bool inverse, int which) {
     const int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
-    int64_t pencils = axis == 0 ? int64_t(ny) * nz
-                                : (axis == 1 ? int64_t(nx) * nz : int64_t(nx) * ny);
-    // y and z pencils are numbered with x outermost: the first half are those
-    // with x < nx / 2 (launching fewer tiles; each tile checks the full count)
-    if (lower_x_half && axis != 0) pencils /= 2;
+    const int64_t pencils = axis == 0 ? int64_t(ny) * nz
+                                      : (axis == 1 ? int64_t(nx) * nz : int64_t(nx) * ny);
     return dispatch_n<AxisFft>(n, L, prec, pencils, axis, inverse, which);
+}
+
+hipError_t launch_vac_fft(const Launch& L, int prec, int nx, int ny, int nz, int mode) {
+    // nx, ny, nz: the padded lengths
+    if (mode == kVacZFwd || mode == kVacZInv)
+        return dispatch_n<VacFft>(nz, L, prec, int64_t(nx / 2) * (ny / 2), mode);
+    return dispatch_n<VacFft>(ny, L, prec, int64_t(nx / 2) * nz, mode);
 }
 
 int64_t axis_tiles(int n, int64_t pencils, int prec) {

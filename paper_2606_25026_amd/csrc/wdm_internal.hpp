@@ -145,10 +145,15 @@ hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, D
 // P7: x forward, Green's function -4 pi G / |k|^2 / N, x inverse (+ Nyquist plane).
 hipError_t launch_x_green(const Launch& L, int prec, int nx, int ny, int nz, int variant = 0);
 // Plain 3D transforms between psi-shaped buffers: axis 0 = x, 1 = y, 2 = z.
-// `which` selects the member field: 0 = psi, 1 = scratch.  With lower_x_half
-// a y or z transform covers only the pencils with x < nx / 2 (at least).
+// `which` selects the member field: 0 = psi, 1 = scratch.
 hipError_t launch_axis_fft(const Launch& L, int prec, int nx, int ny, int nz, int axis,
-                           bool inverse, int which, bool lower_x_half = false);
+                           bool inverse, int which);
+// Transforms of the vacuum solve on the padded member table (nx, ny, nz the
+// padded lengths): mode 0 density rows of Phi -> padded rows, forward z;
+// 1 forward y (inputs y >= ny/2 zero); 2 inverse y (outputs y < ny/2 stored);
+// 3 inverse z, real part of the first nz/2 values -> Phi.  Rows and pencils
+// with x >= nx/2 are not touched.
+hipError_t launch_vac_fft(const Launch& L, int prec, int nx, int ny, int nz, int mode);
 // FP64 spectral kinetic-energy partials from scratch holding F_z F_y psi.
 hipError_t launch_x_kinetic_energy(const Launch& L, int prec, int nx, int ny, int nz);
 
@@ -165,9 +170,6 @@ hipError_t launch_particle_upload(hipStream_t s, const MemberDev& m, const float
                                   const float* vel);
 
 // ---- vacuum boundary and external potential (isolated.hip) ----
-// The x < nx half of the padded grid from the density held in Phi (zero
-// outside the nx ny nz corner); the x >= nx half must hold zeros.
-hipError_t launch_pad_density(const Launch& L, int prec, int nx, int ny);
 // Green's function on the padded grid (into pad), then its transform's real
 // part into green (after the caller's forward transform of pad).
 hipError_t launch_green_fill(const Launch& L, int prec, int64_t max_cells);
@@ -175,9 +177,6 @@ hipError_t launch_green_extract(const Launch& L, int prec, int64_t max_cells);
 // x forward, times green, x inverse on the padded grid (L over the padded
 // member table; nx, ny, nz the padded lengths).
 hipError_t launch_x_mul_green(const Launch& L, int prec, int nx, int ny, int nz);
-// Phi / nz = real part of the padded grid's nx ny nz corner (the z round trip
-// into P1 restores the factor).
-hipError_t launch_unpad(const Launch& L, int prec, int nx, int ny);
 // Remove the mean acceleration of the member's ext (one member).
 hipError_t launch_tidal_correct(const Launch& L, int prec, int64_t ncells);
 
