@@ -217,7 +217,7 @@ bool make_layout(const wdm_config* mem, int n, Layout& L, std::string& why) {
         if (g.external_potential) m.ext = c.take(cells * rs);
         m.dt = c.take(4 * sizeof(double));
         m.results = c.take(kRedFields * sizeof(double));
-        m.watch = c.take(2 * watch_slots(g.nx, g.ny) * sizeof(unsigned long long));
+        m.watch = c.take(watch_words(g.nx, g.ny) * sizeof(unsigned long long));
         m.stab = c.take(2 * sizeof(double));
         if (g.flags & WDM_DETERMINISTIC_DEPOSIT) m.rho_fx = c.take(cells * 8);
         const int64_t np = std::max<int64_t>(g.n_particles, 0);
@@ -669,7 +669,7 @@ wdm_status wdm_plan_create(const wdm_config* members, int32_t n_members, void* w
         if (launch_zero(p->stream, m.rho_b, size_t(cells) * (p->prec ? 8 : 4)) != hipSuccess ||
             launch_zero(p->stream, m.dt, 4 * sizeof(double)) != hipSuccess ||
             launch_zero(p->stream, m.results, kRedFields * sizeof(double)) != hipSuccess ||
-            launch_zero(p->stream, m.watch, 2 * m.watch_n * sizeof(unsigned long long)) !=
+            launch_zero(p->stream, m.watch, (2 * m.watch_n + 2) * sizeof(unsigned long long)) !=
                 hipSuccess ||
             launch_zero(p->stream, m.stab, 2 * sizeof(double)) != hipSuccess ||
             (m.rho_fx && launch_zero(p->stream, m.rho_fx, size_t(cells) * 8) != hipSuccess))
@@ -725,7 +725,7 @@ wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const flo
     HIPCHK(hipMemcpyAsync(m.psi, psi, size_t(n) * (p->prec ? 16 : 8), hipMemcpyDeviceToDevice,
                           p->stream));
     HIPCHK(launch_zero(p->stream, m.rho_b, size_t(n) * (p->prec ? 8 : 4)));
-    HIPCHK(launch_zero(p->stream, m.watch, 2 * m.watch_n * sizeof(unsigned long long)));
+    HIPCHK(launch_zero(p->stream, m.watch, (2 * m.watch_n + 2) * sizeof(unsigned long long)));
     HIPCHK(launch_zero(p->stream, m.stab, 2 * sizeof(double)));
     if (c.n_particles > 0) {
         HIPCHK(launch_particle_upload(p->stream, m, pos, vel));
@@ -851,7 +851,7 @@ hipError_t enqueue_close(wdm_plan* p, hipStream_t s, int64_t n) {
                 return launch_particles(L, p->prec, c.moving_np, 1, kHalfKick, p->det);
             });
         if (e == hipSuccess) e = launch_advance_time(L, n);
-        if (e == hipSuccess) e = launch_stability(L, kCKin);
+        if (e == hipSuccess) e = launch_stability(L, watch_slots(c.nx, c.ny), kCKin);
         if (e != hipSuccess) return e;
     }
     return e;

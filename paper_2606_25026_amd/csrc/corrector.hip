@@ -385,13 +385,6 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
     if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), red[0] / double(count));
 }
 
-__global__ void k_sum_f64(const double* __restrict__ part, double* __restrict__ out, int n) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += gldr(part, i);
-    gstr(out, 0, s);
-}
-
 // Adam on FP32 master parameters (bias-corrected step count t).
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ mo,
                        float* __restrict__ ve, int n, float lr, float b1, float b2, float eps,
@@ -490,12 +483,15 @@ __global__ __launch_bounds__(256) void k_apply_delta(float* __restrict__ psi,
     if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), t);
 }
 
-// scal[slot] = sum of the kMassBlocks partials, in order.
-__global__ void k_sum_mass(const double* __restrict__ part, double* __restrict__ scal, int slot) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[slot] = sum of n partials in a fixed order (thread t adds t, t + 256,
+// ..., then the work-group tree), one 256-thread work-group.
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int n,
+                                                   double* __restrict__ out, int slot) {
+    __shared__ double red[256];
     double s = 0.0;
-    for (int i = 0; i < kMassBlocks; ++i) s += gldr(part, i);
-    gstr(scal, slot, s);
+    for (int i = int(threadIdx.x); i < n; i += 256) s += gldr(part, i);
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) gstr(out, slot, t);
 }
 
 // psi *= sqrt(mass before / mass after), the factor formed in FP64.
@@ -555,12 +551,18 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ x,
 // Scales from the moments of `count` cells (count = pairs x cells per pair):
 // s_psi = 1 / rms|psi|, s_phi = 1 / std(Phi), s_out = std of the residual's
 // components (population moments); written to scal[3..5].
-__global__ void k_fit_scales(const double* __restrict__ rows, double count,
-                             double* __restrict__ scal) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double m[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < kMassBlocks; ++b)
-        for (int f = 0; f < kMoments; ++f) m[f] += gldr(rows, int64_t(b) * kMoments + f);
+__global__ __launch_bounds__(256) void k_fit_scales(const double* __restrict__ rows, double count,
+                                                    double* __restrict__ scal) {
+    __shared__ double red[256];
+    double m[kMoments];
+    for (int f = 0; f < kMoments; ++f) {
+        double s = 0.0;
+        for (int b = int(threadIdx.x); b < kMassBlocks; b += 256)
+            s += gldr(rows, int64_t(b) * kMoments + f);
+        m[f] = block_sum(s, red);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     const double ms = m[0] / count;
     const double mean_phi = m[1] / count, var_phi = m[2] / count - mean_phi * mean_phi;
     const double mean_y = m[4] / (2.0 * count), var_y = m[3] / (2.0 * count) - mean_y * mean_y;
@@ -671,7 +673,7 @@ hipError_t net_mse(hipStream_t s, const float* y, const float* t, uint16_t* dy, 
                    double* out, int64_t cells, int cout, int cp, const double* s_out) {
     constexpr int kBlocks = 1024;
     k_mse<<<kBlocks, 256, 0, s>>>(y, t, dy, part, cells, cout, cp, s_out);
-    k_sum_f64<<<1, 64, 0, s>>>(part, out, kBlocks);
+    k_sum_parts<<<1, 256, 0, s>>>(part, kBlocks, out, 0);
     return hipGetLastError();
 }
 
@@ -691,14 +693,14 @@ hipError_t net_pack_weights(hipStream_t s, const float* w, uint16_t* fwd, uint16
 hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uint16_t* x0,
                           int64_t cells, double* scal, double* part) {
     k_state_pack<<<kMassBlocks, 256, 0, s>>>(psi, phi, x0, cells, scal, part);
-    k_sum_mass<<<1, 64, 0, s>>>(part, scal, 1);
+    k_sum_parts<<<1, 256, 0, s>>>(part, kMassBlocks, scal, 1);
     return hipGetLastError();
 }
 
 hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
                            double* part) {
     k_apply_delta<<<kMassBlocks, 256, 0, s>>>(psi, d, cells, scal, part);
-    k_sum_mass<<<1, 64, 0, s>>>(part, scal, 2);
+    k_sum_parts<<<1, 256, 0, s>>>(part, kMassBlocks, scal, 2);
     k_rescale<<<unsigned((2 * cells + 255) / 256), 256, 0, s>>>(psi, cells, scal);
     return hipGetLastError();
 }
@@ -716,7 +718,7 @@ hipError_t net_moments(hipStream_t s, const float* x, const float* y, int64_t ce
 }
 
 hipError_t net_fit_scales(hipStream_t s, const double* rows, double count, double* scal) {
-    k_fit_scales<<<1, 64, 0, s>>>(rows, count, scal);
+    k_fit_scales<<<1, 256, 0, s>>>(rows, count, scal);
     return hipGetLastError();
 }
 

@@ -8,6 +8,10 @@
 #include "wdm_internal.hpp"
 #include "fft_device.hpp"
 
+// wavefront maximum (device library)
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(
+    unsigned long long);
+
 namespace wdm {
 
 constexpr int kRedThreads = 256;
@@ -164,33 +168,53 @@ hipError_t launch_dt_auto(const Launch& L, double zeta, double c_kin) {
 // |psi|^2) the call's P1 launches saw give dt_max = 0.5 min{c_kin dx_min^2 /
 // eta, 2 pi eta / max|Phi|, 2 pi eta / (|kappa| max|psi|^2)}; stab[0] keeps
 // the largest |dt| / dt_max since wdm_set_state, stab[1] is set once a
-// non-finite value was seen.  One work-group per member; the watch slots are
-// cleared for the next call.
-__global__ __launch_bounds__(256) void k_stability(const MemberDev* __restrict__ mems, int first,
-                                                   double c_kin) {
-    __shared__ unsigned long long red[2][256];
-    const MemberDev& m = mems[first + blockIdx.x];
-    const int t = int(threadIdx.x);
+// non-finite value was seen.
+//
+// k_watch_fold: many work-groups per member (blockIdx.y) take the maximum of
+// their share of the slots, clear it, and fold it into the member's two
+// totals after the slots (watch[2 watch_n], watch[2 watch_n + 1]) with an
+// integer atomicMax -- max is order-free, so the result is deterministic.
+// k_stability then turns the totals into the ratio and clears them.
+constexpr int kWatchPerThread = 8;
+__global__ __launch_bounds__(256) void k_watch_fold(const MemberDev* __restrict__ mems, int first) {
+    __shared__ unsigned long long red[2][4];
+    const MemberDev& m = mems[first + blockIdx.y];
+    unsigned long long* w = m.watch;
+    const int64_t n = m.watch_n;
     unsigned long long a = 0ull, b = 0ull;
-    for (int64_t i = t; i < m.watch_n; i += 256) {
-        a = max(a, m.watch[i]);
-        b = max(b, m.watch[m.watch_n + i]);
-        m.watch[i] = 0ull;
-        m.watch[m.watch_n + i] = 0ull;
-    }
-    red[0][t] = a;
-    red[1][t] = b;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) {
-            red[0][t] = max(red[0][t], red[0][t + w]);
-            red[1][t] = max(red[1][t], red[1][t + w]);
+    const int64_t base = int64_t(blockIdx.x) * (256 * kWatchPerThread) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kWatchPerThread; ++k) {
+        const int64_t i = base + int64_t(k) * 256;
+        if (i < n) {
+            a = max(a, w[i]);
+            b = max(b, w[n + i]);
+            w[i] = 0ull;
+            w[n + i] = 0ull;
         }
-        __syncthreads();
     }
-    if (t != 0) return;
-    const double mp = __longlong_as_double((long long)red[0][0]);
-    const double mr = __longlong_as_double((long long)red[1][0]);
+    a = __ockl_wfred_max_u64(a);
+    b = __ockl_wfred_max_u64(b);
+    const int wave = int(threadIdx.x) >> 6;
+    if (__lane_id() == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    a = max(max(red[0][0], red[0][1]), max(red[0][2], red[0][3]));
+    b = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
+    if (a) atomicMax(w + 2 * n, a);
+    if (b) atomicMax(w + 2 * n + 1, b);
+}
+
+__global__ void k_stability(const MemberDev* __restrict__ mems, int first, double c_kin) {
+    const MemberDev& m = mems[first + blockIdx.x];
+    unsigned long long* tot = m.watch + 2 * m.watch_n;
+    const double mp = __longlong_as_double((long long)tot[0]);
+    const double mr = __longlong_as_double((long long)tot[1]);
+    tot[0] = 0ull;
+    tot[1] = 0ull;
     if (!(mp <= DBL_MAX) || !(mr <= DBL_MAX)) {
         m.stab[1] = 1.0;
         return;
@@ -202,8 +226,11 @@ __global__ __launch_bounds__(256) void k_stability(const MemberDev* __restrict__
     m.stab[0] = fmax(m.stab[0], fabs(m.dt[0]) / (0.5 * tm));
 }
 
-hipError_t launch_stability(const Launch& L, double c_kin) {
-    k_stability<<<unsigned(L.count), 256, 0, L.stream>>>(L.members, L.first, c_kin);
+hipError_t launch_stability(const Launch& L, int64_t slots, double c_kin) {
+    const int64_t per = 256 * kWatchPerThread;
+    k_watch_fold<<<dim3(unsigned((slots + per - 1) / per), unsigned(L.count)), 256, 0, L.stream>>>(
+        L.members, L.first);
+    k_stability<<<unsigned(L.count), 1, 0, L.stream>>>(L.members, L.first, c_kin);
     return hipGetLastError();
 }
 

@@ -165,15 +165,30 @@ __global__ __launch_bounds__(256) void k_distance(const MemberDev* __restrict__ 
     }
 }
 
-__global__ void k_distance_finish(const double* __restrict__ part, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The two sums of the kDistBlocks partial pairs in a fixed order (thread t
+// adds blocks t, t + 256, ..., then the work-group tree).
+__global__ __launch_bounds__(256) void k_distance_finish(const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+    __shared__ double red[2][256];
+    const int t = int(threadIdx.x);
     double d = 0.0, o = 0.0;
-    for (int b = 0; b < kDistBlocks; ++b) {
+    for (int b = t; b < kDistBlocks; b += 256) {
         d += gldr(part, 2 * b);
         o += gldr(part, 2 * b + 1);
     }
-    gstr(out, 0, d);
-    gstr(out, 1, o);
+    red[0][t] = d;
+    red[1][t] = o;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    gstr(out, 0, red[0][0]);
+    gstr(out, 1, red[1][0]);
 }
 
 hipError_t launch_distance(const Launch& L, int prec, const void* other, int64_t n, double* part,
@@ -184,7 +199,7 @@ hipError_t launch_distance(const Launch& L, int prec, const void* other, int64_t
     else
         k_distance<float><<<kDistBlocks, 256, 0, L.stream>>>(
             L.members, L.first, static_cast<const cplx<float>*>(other), n, part);
-    k_distance_finish<<<1, 64, 0, L.stream>>>(part, out);
+    k_distance_finish<<<1, 256, 0, L.stream>>>(part, out);
     return hipGetLastError();
 }
 

@@ -86,7 +86,8 @@ struct MemberDev {
     // |Phi|, [watch_n, 2 watch_n) the largest |psi|^2 (kicks with a
     // self-interaction only), as FP64 bit patterns compared as unsigned
     // integers (NaN above +inf), one slot per wavefront of the launch (no two
-    // wavefronts share a slot); cleared by each check
+    // wavefronts share a slot); [2 watch_n, 2 watch_n + 2) the two maxima
+    // folded by the check; all cleared by each check
     unsigned long long* watch;
     int64_t watch_n;
     // [0] largest |dt| / dt_max (Sec. 3.5) over the steps checked since
@@ -204,10 +205,13 @@ hipError_t launch_advance_time(const Launch& L, int64_t nsteps);
 // Slots of the stability watch per member: at least the wavefronts of any P1
 // launch (one pencil or more per wavefront).
 inline int64_t watch_slots(int nx, int ny) { return int64_t(nx) * ny + 1024; }
-// Stability check after a wdm_step call: folds the watch slots into stab
-// (|dt| / dt_max with dt_max = 0.5 min{c_kin dx^2 / eta, 2 pi eta / max|Phi|,
-// 2 pi eta / (|kappa| max|psi|^2)}, Sec. 3.5) and clears them.
-hipError_t launch_stability(const Launch& L, double c_kin);
+// 64-bit words of a member's watch: the two slot halves and their two totals.
+inline int64_t watch_words(int nx, int ny) { return 2 * watch_slots(nx, ny) + 2; }
+// Stability check after a wdm_step call: folds the watch slots (`slots` =
+// watch_n of the class) into stab (|dt| / dt_max with dt_max = 0.5 min{c_kin
+// dx^2 / eta, 2 pi eta / max|Phi|, 2 pi eta / (|kappa| max|psi|^2)}, Sec. 3.5)
+// and clears them.
+hipError_t launch_stability(const Launch& L, int64_t slots, double c_kin);
 hipError_t launch_zero(hipStream_t s, void* p, size_t bytes);
 hipError_t launch_copy_complex(hipStream_t s, void* dst, const void* src, int64_t n,
                                int dst_prec, int src_prec);
