@@ -215,6 +215,9 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
     // per SIMD against seven) than the second memory wait costs
     T* rb = static_cast<T*>(m.rho_b) + q * NZ + ln.t;
     T rbv[FP::E];
+    // a member without particles has no baryon density: rho_b stays zero and
+    // is neither read nor cleared
+    const bool touched = ok && m.np > 0;
     if constexpr (FROM_PHI) {
 #pragma unroll
         for (int s = 0; s < FP::E; ++s)
@@ -232,9 +235,9 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
         }
 #pragma unroll
         for (int s = 0; s < FP::E; ++s)
-            rbv[s] = ok ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
+            rbv[s] = touched ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
         // the accumulator is cleared for the next deposit; a static deposit stays
-        const bool clear = ok && !m.static_baryons;
+        const bool clear = touched && !m.static_baryons;
 #pragma unroll
         for (int s = 0; s < FP::E; ++s) {
             v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
