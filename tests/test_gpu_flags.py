@@ -100,7 +100,12 @@ def test_deterministic_deposit_ignores_particle_order(wdm):
     perm = np.random.default_rng(0).permutation(wl.pos.shape[0])
     a = det_run(wdm, wl)
     b = det_run(wdm, wl, pos=wl.pos[perm], vel=wl.vel[perm])
-    # the potential of the initial state: equal bit for bit
+    # the uploaded particles, the density of the initial state (fixed-point
+    # deposit) and its potential: equal bit for bit
+    s0a, s0b = state(a), state(b)
+    assert np.array_equal(s0a[1][perm], s0b[1]) and np.array_equal(s0a[2][perm], s0b[2])
+    da, db = a.get_density(True), b.get_density(True)
+    assert np.array_equal(da, db), f"density differs in {int(np.count_nonzero(da != db))} cells"
     assert np.array_equal(a.get_phi(), b.get_phi())
     a.step(10, wl.dt)
     b.step(10, wl.dt)
