@@ -255,7 +255,11 @@ def mass_fraction_radii(cfg: Config, psi, centre=None, fractions=MASS_FRACTIONS)
 
 
 def dt_auto(cfg: Config, phi, psi=None, zeta=0.9, c_kin=4.0 / (3.0 * np.pi)) -> float:
-    """CFL step of Sec. 3.5.  Parity unpinned beyond its printed formula."""
+    """CFL step of Sec. 3.5: zeta * 0.5 * min{c_kin dx^2 / eta, 2 pi eta / max|Phi|,
+    2 pi eta / (|kappa| max|psi|^2)}.  Each term is the step over which the grid's
+    fastest drift mode, the kick at the deepest node, or the self-interaction kick
+    turns the phase by pi (pinned through one oracle step each); the printed
+    kinetic constant 4 / (3 pi) is itself a reading of the paper."""
     ps = _c128(psi).view(np.float64) if psi is not None else None
     return float(lib().orc_dt_auto(C.byref(cfg), _p(_f64(phi)), _p(ps), zeta, c_kin))
 

@@ -343,7 +343,8 @@ def test_paper_energy_terms_plane_wave(orc):
 
 
 def test_dt_auto_formula(orc):
-    # parity unpinned beyond the printed CFL formula (Sec. 3.5)
+    # the formula as printed in Sec. 3.5; what each term means is pinned by the
+    # half-turn tests below
     shape = (16, 16, 16)
     phi = np.zeros(shape)
     phi[3, 4, 5] = -2.0
@@ -477,3 +478,52 @@ def test_plummer_mass_profile_and_virial():
     W = 3 * math.pi * G * M * M / (32 * a)
     assert 2 * K / W == pytest.approx(1.0, abs=0.03)
     assert pos.min() >= 0 and pos.max() < 1
+
+
+def test_dt_auto_kinetic_bound_is_a_half_turn_of_the_corner_mode(orc):
+    # The kinetic term of Sec. 3.5's dt_max, 0.5 (4 / (3 pi)) dx^2 / eta, is the
+    # step over which the fastest mode of the grid, the corner Nyquist mode
+    # |k|^2 = 3 (pi / dx)^2, turns by pi under the drift exp(-i eta |k|^2 dt / 2).
+    # With zeta = 0.9 one oracle step at dt_auto turns that mode by 0.9 pi.
+    n = 16
+    cfg = orc.make_config((n,) * 3, hbar_over_m=0.7)
+    i, j, k = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    psi = np.where((i + j + k) % 2 == 0, 1.0, -1.0).astype(np.complex128)
+    # uniform density: Phi = 0 (the mean is removed), so only the drift acts
+    dt = orc.dt_auto(cfg, np.zeros((n,) * 3))
+    out, _, _ = orc.kdk(cfg, psi, nsteps=1, dt=dt)
+    ratio = out / psi
+    assert np.allclose(np.abs(ratio), 1.0, atol=1e-12)
+    assert np.allclose(np.angle(ratio), -0.9 * math.pi, atol=1e-12)
+
+
+def test_dt_auto_potential_bound_is_a_half_turn_of_the_kick(orc):
+    # The potential term, 0.5 * 2 pi eta / max|Phi|, is the step over which the
+    # kick exp(-i Phi dt / eta) turns the phase at the deepest node by pi; at
+    # zeta = 0.9 one oracle step (two half kicks in a static external potential,
+    # self-gravity off, eta small enough that the drift between them moves the
+    # phase by < 1e-5) turns it by 0.9 pi where |Phi| is largest.
+    n = 32
+    cfg = orc.make_config((n,) * 3, hbar_over_m=1e-4, four_pi_G=0.0)
+    x = np.arange(n) / n
+    phi = np.broadcast_to(np.cos(2 * math.pi * x)[:, None, None], (n,) * 3).copy()
+    phi_c = orc.tidal_correct(cfg, phi)
+    assert np.allclose(phi_c, phi, atol=1e-12)    # symmetric: no ramp removed
+    dt = orc.dt_auto(cfg, phi_c)
+    out, _, _ = orc.kdk(cfg, np.ones((n,) * 3, np.complex128), nsteps=1, dt=dt, phi_ext=phi_c)
+    assert np.angle(out[0, 0, 0]) == pytest.approx(-0.9 * math.pi, abs=1e-4)
+    assert np.angle(out[n // 2, 0, 0]) == pytest.approx(0.9 * math.pi, abs=1e-4)
+
+
+def test_dt_auto_self_interaction_bound_is_a_half_turn(orc):
+    # The kappa term, 0.5 * 2 pi eta / (|kappa| max|psi|^2), is the step over
+    # which the self-interaction kick turns a uniform field by pi (both half
+    # kicks; a uniform field has no drift and no potential): 0.9 pi at zeta.
+    n = 8
+    for kappa, amp in ((300.0, 2.0), (-500.0, 0.5)):
+        cfg = orc.make_config((n,) * 3, hbar_over_m=0.3, four_pi_G=0.0, kappa=kappa)
+        psi = np.full((n,) * 3, amp, np.complex128)
+        dt = orc.dt_auto(cfg, np.zeros((n,) * 3), psi)
+        assert dt < 0.9 * 0.5 * (4 / (3 * math.pi)) * (1 / n) ** 2 / 0.3   # this term binds
+        out, _, _ = orc.kdk(cfg, psi, nsteps=1, dt=dt)
+        assert np.allclose(np.angle(out / psi), -0.9 * math.pi * np.sign(kappa), atol=1e-12)
