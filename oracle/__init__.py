@@ -19,19 +19,27 @@ from pathlib import Path
 import numpy as np
 
 HERE = Path(__file__).resolve().parent
-LIB = HERE / "liboracle.so"
+# ORACLE_LIB selects another build of the same sources (the sanitized one)
+LIB = Path(os.environ.get("ORACLE_LIB", HERE / "liboracle.so"))
+SAN_LIB = HERE / "liboracle_san.so"
 SOURCES = ["fft.cpp", "spe.cpp", "analysis.cpp"]
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile the oracle with g++ -O2 (no fast-math) into oracle/liboracle.so."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
-           "-o", str(LIB) + ".tmp"] + [str(HERE / s) for s in SOURCES]
+def build(verbose: bool = False, sanitize: bool = False) -> Path:
+    """Compile the oracle with g++ -O2 (no fast-math) into oracle/liboracle.so;
+    with ``sanitize``, an AddressSanitizer + UndefinedBehaviorSanitizer build
+    (-O1, halting on the first report) into oracle/liboracle_san.so, which a
+    process loads with libasan preloaded and ORACLE_LIB pointing at it."""
+    out = SAN_LIB if sanitize else HERE / "liboracle.so"
+    opt = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"])
+    cmd = ["g++", *opt, "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
+           "-o", str(out) + ".tmp"] + [str(HERE / s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(str(LIB) + ".tmp", LIB)
-    return LIB
+    os.replace(str(out) + ".tmp", out)
+    return out
 
 
 class Config(C.Structure):
@@ -51,7 +59,7 @@ def lib():
     global _lib
     if _lib is None:
         if not LIB.exists():
-            build()
+            build(sanitize=LIB == SAN_LIB)
         L = C.CDLL(str(LIB))
         dp, ip = C.POINTER(C.c_double), C.c_int
         L.orc_set_threads.argtypes = [ip]
