@@ -154,6 +154,14 @@ def learned_cost(h, wl, args, dev, ms_per_step, every=8, blocks=16):
     torch.cuda.synchronize()
     t_c = time.perf_counter() - t0
     wdm.wdm_plan_attach_corrector(coarse.handle, None, 0, 0)
+    # the same blocks without the corrector: the difference is what a
+    # correction costs inside the captured block
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(blocks):
+        wdm.wdm_step(coarse.handle, every, dt_c)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
     # the corrector alone: one correction (inputs, three convolutions, update,
     # potential rebuilt) and the network's forward pass, HIP events on the
     # stream they run on
@@ -186,6 +194,7 @@ def learned_cost(h, wl, args, dev, ms_per_step, every=8, blocks=16):
     return {"s_per_unit_fine": s_fine, "s_per_unit_learned": s_learned,
             "ratio": s_fine / s_learned,
             "apply_us": apply_us,
+            "apply_in_block_us": (t_c - t_plain) / blocks * 1e6,
             "corrector_roofline": {
                 "kernel": "k_conv x3 + input pack (network forward pass)", "bound": "hbm",
                 "achieved": fwd_bytes / (fwd_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,

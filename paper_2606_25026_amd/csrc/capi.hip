@@ -33,8 +33,10 @@ hipError_t net_pack_weights(hipStream_t s, const float* w, uint16_t* fwd, uint16
                             int cout, int cpin, int cpout);
 hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uint16_t* x0,
                           int64_t cells, double* scal, double* part);
+// psi += s_out d and its new FP64 mass; with `rescale` also psi *= sqrt(mass
+// before / mass after) (else the Poisson rebuild's density pass applies it)
 hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
-                           double* part);
+                           double* part, bool rescale);
 hipError_t net_pair(hipStream_t s, const float* psi, const float* phi, const float* target,
                     float* x, float* y, int64_t cells);
 hipError_t net_moments(hipStream_t s, const float* x, const float* y, int64_t cells, double* rows,
@@ -420,14 +422,17 @@ bool member_extended(const wdm_config& c) {
 
 // Poisson solve of the density already deposited in rho_b plus |psi|^2
 // (psi in real space), ending with Phi written and psi untouched.
-hipError_t potential_from_state(wdm_plan* p, const Launch& L, const wdm_config& c) {
+hipError_t potential_from_state(wdm_plan* p, const Launch& L, const wdm_config& c,
+                                const double* rescale = nullptr) {
     hipError_t e;
     if (c.boundary == WDM_BOUNDARY_VACUUM) {
+        if (rescale != nullptr) return hipErrorInvalidValue;
         e = enqueue_vacuum_poisson(p, L.stream, L.first, L.count, c.nx, c.ny, c.nz,
                                    kDensDirectToPhi);
         if (e != hipSuccess) return e;
     } else {
-        if ((e = launch_z_density(L, p->prec, c.nx, c.ny, c.nz, kDensDirect)) != hipSuccess)
+        if ((e = launch_z_density(L, p->prec, c.nx, c.ny, c.nz, kDensDirect, 0, -1, rescale)) !=
+            hipSuccess)
             return e;
         if ((e = launch_y_fft_spec(L, p->prec, c.nx, c.ny, c.nz, false)) != hipSuccess) return e;
         if ((e = launch_x_green(L, p->prec, c.nx, c.ny, c.nz)) != hipSuccess) return e;
@@ -462,15 +467,18 @@ wdm_status check_stability(wdm_plan* p, int32_t member) {
 
 // Potential of a member's synchronised state (psi, particle positions): the
 // moving particles are deposited (static ones keep their deposit in rho_b)
-// and Poisson is solved, as wdm_set_state does.
-hipError_t rebuild_potential(wdm_plan* p, int32_t member, hipStream_t s) {
+// and Poisson is solved, as wdm_set_state does.  `rho_b_ready`: rho_b already
+// holds the deposit of the current positions (kept by the last step's P5), so
+// it is not deposited again.  `rescale`: see launch_z_density (periodic only).
+hipError_t rebuild_potential(wdm_plan* p, int32_t member, hipStream_t s, bool rho_b_ready = false,
+                             const double* rescale = nullptr) {
     const wdm_config& c = p->cfg[member];
     const Launch L{s, p->table, p->dev_index[member], 1};
-    if (c.n_particles > 0 && c.baryon_mode == WDM_BARYON_DYNAMIC) {
+    if (!rho_b_ready && c.n_particles > 0 && c.baryon_mode == WDM_BARYON_DYNAMIC) {
         const hipError_t e = launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det);
         if (e != hipSuccess) return e;
     }
-    return potential_from_state(p, L, c);
+    return potential_from_state(p, L, c, rescale);
 }
 
 }  // namespace
@@ -760,7 +768,8 @@ namespace {
 // One merged KDK step for every size class (P1, particles, P2 ... P8).  With
 // `aux` set the particle kernel is forked onto it after P1 and joined before
 // P5, so it overlaps the y/x/y passes.
-hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km) {
+hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km,
+                        int keep_member = -1) {
     const int prec = p->prec;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) {
@@ -824,7 +833,8 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             continue;
         }
         if (!chk(timed(p, kKZDens, [&] {
-                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft, c.var[kTzDens]);
+                return launch_z_density(L, prec, c.nx, c.ny, c.nz, kDensInvFft, c.var[kTzDens],
+                                        keep_member);
             })))
             return e;
         if (!chk(timed(p, kKYSpecF, [&] {
@@ -908,7 +918,8 @@ hipError_t capture_step(wdm_plan* p, int which) {
     return e;
 }
 
-hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t s);
+hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t s,
+                         bool rho_b_ready);
 wdm_status check_net_for(wdm_net* net, wdm_plan* p, int32_t member);
 
 // Capture `every` steps, the closing half kick and the corrector as one graph.
@@ -920,10 +931,17 @@ hipError_t capture_block(wdm_plan* p) {
     hipError_t e = hipStreamBeginCapture(p->s_main, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
+    // the last step's P5 keeps the corrected member's baryon deposit (the
+    // closing kick moves no particle), so the correction's Poisson rebuild
+    // reads it instead of depositing again (periodic members; the vacuum
+    // solve clears it)
+    const bool keep = p->cfg[p->net_member].boundary != WDM_BOUNDARY_VACUUM;
+    const int keep_dev = keep ? p->dev_index[p->net_member] : -1;
     for (int32_t i = 0; i < p->every && le == hipSuccess; ++i)
-        le = enqueue_step(p, p->s_main, p->s_aux, i == 0 ? kHalfKick : kFullKick);
+        le = enqueue_step(p, p->s_main, p->s_aux, i == 0 ? kHalfKick : kFullKick,
+                          i + 1 == p->every ? keep_dev : -1);
     if (le == hipSuccess) le = enqueue_close(p, p->s_main, p->every);
-    if (le == hipSuccess) le = enqueue_apply(p->net, p, p->net_member, p->s_main);
+    if (le == hipSuccess) le = enqueue_apply(p->net, p, p->net_member, p->s_main, keep);
     e = hipStreamEndCapture(p->s_main, &g);
     if (le != hipSuccess) e = le;
     if (e == hipSuccess) e = hipGraphInstantiate(&p->g_block, g, nullptr, nullptr, 0);
@@ -1009,7 +1027,7 @@ wdm_status run_steps(wdm_plan* p, int64_t n, double dt, After after) {
             i += k;
         }
         HIPCHK(enqueue_close(p, s, n));
-        if (after == kApplyAfter) HIPCHK(enqueue_apply(p->net, p, p->net_member, s));
+        if (after == kApplyAfter) HIPCHK(enqueue_apply(p->net, p, p->net_member, s, false));
     }
     if (graphs) {
         HIPCHK(hipEventRecord(p->ev_out, s));
@@ -1790,7 +1808,8 @@ namespace {
 // from (psi, Phi) with the network's scales, the three layers, psi += s_out y,
 // psi rescaled to its FP64 mass before the correction, and the potential
 // rebuilt from the corrected state (moving particles redeposited).
-hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t s) {
+hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t s,
+                         bool rho_b_ready) {
     const MemberDev& m = p->host[p->dev_index[member]];
     float* psi = static_cast<float*>(m.psi);
     double* scal = net->at<double>(net->L.scal);
@@ -1800,10 +1819,12 @@ hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t 
                             net->at<uint16_t>(net->L.x0), net->cells, scal, part)) != hipSuccess)
         return e;
     if ((e = net_run_layers(net, s)) != hipSuccess) return e;
-    if ((e = net_apply_delta(s, psi, net->at<float>(net->L.y), net->cells, scal, part)) !=
-        hipSuccess)
+    // the mass restoration rides on the rebuild's density pass (periodic)
+    const bool periodic = p->cfg[member].boundary != WDM_BOUNDARY_VACUUM;
+    if ((e = net_apply_delta(s, psi, net->at<float>(net->L.y), net->cells, scal, part,
+                             !periodic)) != hipSuccess)
         return e;
-    return rebuild_potential(p, member, s);
+    return rebuild_potential(p, member, s, rho_b_ready, periodic ? scal : nullptr);
 }
 
 // Checks shared by wdm_net_apply and wdm_plan_attach_corrector.
@@ -1825,7 +1846,7 @@ wdm_status wdm_net_apply(wdm_net* net, wdm_plan* p, int32_t member) {
     if (wdm_status st = check_member(p, member)) return st;
     if (wdm_status st = check_net_for(net, p, member)) return st;
     if (!p->has_state[member]) return fail(WDM_ESTATE, "no state set");
-    HIPCHK(enqueue_apply(net, p, member, p->stream));
+    HIPCHK(enqueue_apply(net, p, member, p->stream, false));
     return WDM_OK;
 }
 

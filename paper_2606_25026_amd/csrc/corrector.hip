@@ -698,10 +698,10 @@ hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uin
 }
 
 hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
-                           double* part) {
+                           double* part, bool rescale) {
     k_apply_delta<<<kMassBlocks, 256, 0, s>>>(psi, d, cells, scal, part);
     k_sum_parts<<<1, 256, 0, s>>>(part, kMassBlocks, scal, 2);
-    k_rescale<<<unsigned((2 * cells + 255) / 256), 256, 0, s>>>(psi, cells, scal);
+    if (rescale) k_rescale<<<unsigned((2 * cells + 255) / 256), 256, 0, s>>>(psi, cells, scal);
     return hipGetLastError();
 }
 

@@ -187,9 +187,15 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
 // ===========================================================================
 // P5: inverse z-FFT of psi, density, R2C forward z-FFT into the half spectrum.
 // ===========================================================================
+// `keep`: the device index of a member whose rho_b is left in place (the
+// Poisson rebuild after a correction of that member reads it instead of
+// depositing the unchanged positions again), -1 for none.  `scal` (direct density
+// only, else null): psi is first scaled by sqrt(scal[1] / scal[2]) and written
+// back -- the corrector's mass restoration, fused into the rebuild that reads
+// psi anyway.
 template <int NZ, typename T, int OP, int V>
 __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void k_z_density(
-    const MemberDev* __restrict__ mems, int first) {
+    const MemberDev* __restrict__ mems, int first, int keep, const double* __restrict__ scal) {
     using FP = typename PlanFor<NZ, V>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, false>;
@@ -231,13 +237,22 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
             store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
         } else {
             load_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+            if constexpr (OP == kDensDirect) {
+                if (scal != nullptr) {
+                    const double a = gldr(scal, 2);
+                    const T f = a > 0.0 ? T(sqrt(gldr(scal, 1) / a)) : T(1);
+#pragma unroll
+                    for (int s = 0; s < FP::E; ++s) v[s] = cplx<T>{v[s].re * f, v[s].im * f};
+                    store_slots<FP, FP::first()>(v, psi, q * NZ, 1, ok, ln);
+                }
+            }
             __syncthreads();
         }
 #pragma unroll
         for (int s = 0; s < FP::E; ++s)
             rbv[s] = touched ? gldr(rb, slot_const<FP, FP::first()>(s)) : T(0);
         // the accumulator is cleared for the next deposit; a static deposit stays
-        const bool clear = touched && !m.static_baryons;
+        const bool clear = touched && !m.static_baryons && first + int(blockIdx.y) != keep;
 #pragma unroll
         for (int s = 0; s < FP::E; ++s) {
             v[s] = cplx<T>{v[s].re * v[s].re + v[s].im * v[s].im + rbv[s], T(0)};
@@ -316,40 +331,47 @@ struct ZPotKick {
 template <int NZ>
 struct ZDens {
     template <typename T, int V>
-    static hipError_t go(const Launch& L, int nx, int ny, DensOp op) {
+    static hipError_t go(const Launch& L, int nx, int ny, DensOp op, int keep,
+                         const double* scal) {
         dim3 grid(unsigned(tiles<NZ, T, V>(int64_t(nx) * ny)), unsigned(L.count));
         const dim3 b = block<NZ, T, V>();
         if constexpr (V == 0) {
             switch (op) {
                 case kDensDirect:
-                    k_z_density<NZ, T, kDensDirect, 0><<<grid, b, 0, L.stream>>>(L.members, L.first);
+                    k_z_density<NZ, T, kDensDirect, 0>
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first, keep, scal);
                     return hipGetLastError();
                 case kDensInvToPhi:
                     k_z_density<NZ, T, kDensInvToPhi, 0>
-                        <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first, keep, scal);
                     return hipGetLastError();
                 case kDensDirectToPhi:
                     k_z_density<NZ, T, kDensDirectToPhi, 0>
-                        <<<grid, b, 0, L.stream>>>(L.members, L.first);
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first, keep, scal);
                     return hipGetLastError();
                 case kPhiR2C:
-                    k_z_density<NZ, T, kPhiR2C, 0><<<grid, b, 0, L.stream>>>(L.members, L.first);
+                    k_z_density<NZ, T, kPhiR2C, 0>
+                        <<<grid, b, 0, L.stream>>>(L.members, L.first, keep, scal);
                     return hipGetLastError();
                 default:
                     break;
             }
         }
-        k_z_density<NZ, T, kDensInvFft, V><<<grid, b, 0, L.stream>>>(L.members, L.first);
+        k_z_density<NZ, T, kDensInvFft, V>
+            <<<grid, b, 0, L.stream>>>(L.members, L.first, keep, scal);
         return hipGetLastError();
     }
     template <typename T>
-    static hipError_t pick(const Launch& L, int nx, int ny, DensOp op, int var) {
+    static hipError_t pick(const Launch& L, int nx, int ny, DensOp op, int var, int keep,
+                           const double* scal) {
         if constexpr (has_variant(NZ))
-            if (var == 1 && op == kDensInvFft) return go<T, 1>(L, nx, ny, op);
-        return go<T, 0>(L, nx, ny, op);
+            if (var == 1 && op == kDensInvFft) return go<T, 1>(L, nx, ny, op, keep, scal);
+        return go<T, 0>(L, nx, ny, op, keep, scal);
     }
-    static hipError_t run(const Launch& L, int prec, int nx, int ny, DensOp op, int var) {
-        return prec ? pick<double>(L, nx, ny, op, var) : pick<float>(L, nx, ny, op, var);
+    static hipError_t run(const Launch& L, int prec, int nx, int ny, DensOp op, int var,
+                          int keep, const double* scal) {
+        return prec ? pick<double>(L, nx, ny, op, var, keep, scal)
+                    : pick<float>(L, nx, ny, op, var, keep, scal);
     }
 };
 
@@ -358,8 +380,9 @@ hipError_t launch_z_potential_kick(const Launch& L, int prec, int nx, int ny, in
     return dispatch_n<ZPotKick>(nz, L, prec, nx, ny, op, kick, variant, extended);
 }
 hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op,
-                            int variant) {
-    return dispatch_n<ZDens>(nz, L, prec, nx, ny, op, variant);
+                            int variant, int keep_member, const double* rescale) {
+    if (rescale != nullptr && op != kDensDirect) return hipErrorInvalidValue;
+    return dispatch_n<ZDens>(nz, L, prec, nx, ny, op, variant, keep_member, rescale);
 }
 
 }  // namespace wdm

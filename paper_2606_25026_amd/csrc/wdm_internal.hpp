@@ -140,9 +140,13 @@ hipError_t launch_y_fft_spec(const Launch& L, int prec, int nx, int ny, int nz, 
 hipError_t launch_kinetic_tables(const Launch& L, int prec, int64_t max_entries);
 // P3: x forward, kinetic phase exp(-i eta |k|^2 dt/2)/N, x inverse.
 hipError_t launch_x_kinetic(const Launch& L, int prec, int nx, int ny, int nz, int variant = 0);
-// P5: z inverse of psi (optional), rho = |psi|^2 + rho_b (rho_b cleared), R2C along z.
+// P5: z inverse of psi (optional), rho = |psi|^2 + rho_b (rho_b cleared except
+// for the member of device index keep_member), R2C along z.  `rescale`
+// (kDensDirect only): psi is first scaled by sqrt(rescale[1] / rescale[2]) and
+// written back.
 hipError_t launch_z_density(const Launch& L, int prec, int nx, int ny, int nz, DensOp op,
-                            int variant = 0);
+                            int variant = 0, int keep_member = -1,
+                            const double* rescale = nullptr);
 // P7: x forward, Green's function -4 pi G / |k|^2 / N, x inverse (+ Nyquist plane).
 hipError_t launch_x_green(const Launch& L, int prec, int nx, int ny, int nz, int variant = 0);
 // Plain 3D transforms between psi-shaped buffers: axis 0 = x, 1 = y, 2 = z.
