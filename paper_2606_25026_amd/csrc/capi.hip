@@ -33,10 +33,12 @@ hipError_t net_pack_weights(hipStream_t s, const float* w, uint16_t* fwd, uint16
                             int cout, int cpin, int cpout);
 hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uint16_t* x0,
                           int64_t cells, double* scal, double* part);
-// psi += s_out d and its new FP64 mass; with `rescale` also psi *= sqrt(mass
-// before / mass after) (else the Poisson rebuild's density pass applies it)
-hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
-                           double* part, bool rescale);
+// the network's last layer with psi += s_out d fused into its epilogue and the
+// FP64 mass of the corrected psi; with `rescale`, psi *= sqrt(mass before /
+// mass after) (else the Poisson rebuild's density pass applies it)
+hipError_t net_last_layer_apply(hipStream_t s, const uint16_t* in, const uint16_t* w,
+                                const float* b, float* psi, int n, double* scal, double* part,
+                                bool rescale);
 hipError_t net_pair(hipStream_t s, const float* psi, const float* phi, const float* target,
                     float* x, float* y, int64_t cells);
 hipError_t net_moments(hipStream_t s, const float* x, const float* y, int64_t cells, double* rows,
@@ -1818,11 +1820,23 @@ hipError_t enqueue_apply(wdm_net* net, wdm_plan* p, int32_t member, hipStream_t 
     if ((e = net_state_pack(s, psi, static_cast<const float*>(m.phi),
                             net->at<uint16_t>(net->L.x0), net->cells, scal, part)) != hipSuccess)
         return e;
-    if ((e = net_run_layers(net, s)) != hipSuccess) return e;
-    // the mass restoration rides on the rebuild's density pass (periodic)
+    // the first two layers, then the last one with psi += s_out d in its
+    // epilogue; the mass restoration rides on the rebuild's density pass
+    // (periodic members)
+    const uint16_t* in[2] = {net->at<uint16_t>(net->L.x0), net->at<uint16_t>(net->L.a1)};
+    uint16_t* out[2] = {net->at<uint16_t>(net->L.a1), net->at<uint16_t>(net->L.a2)};
+    auto bias = [&](int l) {
+        return net->at<float>(net->L.params) + net->param_off(l) +
+               size_t(kNetCout[l]) * kNetCin[l] * 27;
+    };
+    for (int l = 0; l < 2; ++l)
+        if ((e = conv_forward_layer(s, l, in[l], net->at<uint16_t>(net->L.wf[l]), bias(l), out[l],
+                                    net->n)) != hipSuccess)
+            return e;
     const bool periodic = p->cfg[member].boundary != WDM_BOUNDARY_VACUUM;
-    if ((e = net_apply_delta(s, psi, net->at<float>(net->L.y), net->cells, scal, part,
-                             !periodic)) != hipSuccess)
+    if ((e = net_last_layer_apply(s, net->at<uint16_t>(net->L.a2),
+                                  net->at<uint16_t>(net->L.wf[2]), bias(2), psi, net->n, scal,
+                                  part, !periodic)) != hipSuccess)
         return e;
     return rebuild_potential(p, member, s, rho_b_ready, periodic ? scal : nullptr);
 }

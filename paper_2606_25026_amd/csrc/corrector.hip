@@ -58,6 +58,10 @@ enum ConvEpi : int {
     kEpiBiasReluBf16 = 0,   // out = bf16(relu(acc + bias)), CPOUT channels
     kEpiBiasF32 = 1,        // out = f32(acc + bias), COUT channels (network output)
     kEpiMaskBf16 = 2,       // out = bf16(acc * (mask > 0)), CPOUT channels (backward data)
+    // the correction (COUT = 2): out is psi (f32 re, im per cell),
+    // psi += s_out (acc + bias) with s_out = scal[5], and part[work-group] gets
+    // the FP64 sum of the corrected |psi|^2 over the work-group's cells
+    kEpiApply = 3,
 };
 
 // Convolution tile: 4 x 4 x 16 output cells (x, y, z) per work-group pass.
@@ -136,7 +140,8 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
                                                  const uint16_t* __restrict__ wmat,
                                                  const float* __restrict__ bias,
                                                  const uint16_t* __restrict__ mask, void* out,
-                                                 int n) {
+                                                 int n, const double* __restrict__ scal,
+                                                 double* __restrict__ part) {
     constexpr int KC = (27 * CPIN + 15) / 16;
     constexpr int KW = KC * 16 + 4;              // LDS row of the weights (bf16 entries)
     constexpr int W8 = CPIN / 4;                 // 8-byte words per brick cell
@@ -162,6 +167,8 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
     const int64_t ntiles = int64_t(tx) * ty * tz;
     BrickRegs<W8> R;
     if (int64_t(blockIdx.x) < ntiles) brick_load<CPIN, W8>(R, in, blockIdx.x, n, tz, ty);
+    double mass = 0.0;   // kEpiApply: this lane's cells, in tile order
+    const float s_out = EPI == kEpiApply ? float(gldr(scal, 5)) : 0.0f;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int iz = int(t % tz);
         const int64_t r = t / tz;
@@ -228,6 +235,15 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     if (m0 + q < COUT) gstr(o, cell * COUT + m0 + q, acc[s2][q] + gldr(bias, m0 + q));
+            } else if constexpr (EPI == kEpiApply) {
+                static_assert(COUT == 2, "the correction has two output channels");
+                if (m0 != 0) continue;
+                float* psi = static_cast<float*>(out);
+                const float re = gldr(psi, 2 * cell) + s_out * (acc[s2][0] + gldr(bias, 0));
+                const float im = gldr(psi, 2 * cell + 1) + s_out * (acc[s2][1] + gldr(bias, 1));
+                gstr(psi, 2 * cell, re);
+                gstr(psi, 2 * cell + 1, im);
+                mass += double(re) * double(re) + double(im) * double(im);
             } else {
                 if (m0 >= CPOUT) continue;
                 uint16_t rq[4];
@@ -249,6 +265,18 @@ __global__ __launch_bounds__(256, 3) void k_conv(const uint16_t* __restrict__ in
             }
         }
         __syncthreads();   // the next tile's brick overwrites this one
+    }
+    if constexpr (EPI == kEpiApply) {
+        // the work-group's sum in a fixed order (lanes, then the four
+        // wavefronts), reusing the brick's LDS
+        double* red = reinterpret_cast<double*>(brick);
+        red[tid] = mass;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) gstr(part, int64_t(blockIdx.x), red[0]);
     }
 }
 
@@ -462,27 +490,6 @@ __global__ __launch_bounds__(256) void k_state_pack(const float* __restrict__ ps
     if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), t);
 }
 
-// psi += s_out * d (d f32 [cells][2], the network output) and the FP64
-// partials of the corrected |psi|^2.
-__global__ __launch_bounds__(256) void k_apply_delta(float* __restrict__ psi,
-                                                     const float* __restrict__ d, int64_t cells,
-                                                     const double* __restrict__ scal,
-                                                     double* __restrict__ part) {
-    __shared__ double red[256];
-    const float so = float(gldr(scal, 5));
-    double m = 0.0;
-    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < cells;
-         p += int64_t(gridDim.x) * 256) {
-        const float re = gldr(psi, 2 * p) + so * gldr(d, 2 * p);
-        const float im = gldr(psi, 2 * p + 1) + so * gldr(d, 2 * p + 1);
-        gstr(psi, 2 * p, re);
-        gstr(psi, 2 * p + 1, im);
-        m += double(re) * double(re) + double(im) * double(im);
-    }
-    const double t = block_sum(m, red);
-    if (threadIdx.x == 0) gstr(part, int64_t(blockIdx.x), t);
-}
-
 // out[slot] = sum of n partials in a fixed order (thread t adds t, t + 256,
 // ..., then the work-group tree), one 256-thread work-group.
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int n,
@@ -624,12 +631,13 @@ hipError_t conv_forward_layer(hipStream_t s, int layer, const uint16_t* in, cons
                               const float* b, void* out, int n) {
     if (layer == 0)
         k_conv<4, 16, 16, kEpiBiasReluBf16><<<conv_blocks(n, 8), 256, 0, s>>>(in, w, b, nullptr,
-                                                                             out, n);
+                                                                             out, n, nullptr, nullptr);
     else if (layer == 1)
         k_conv<16, 16, 16, kEpiBiasReluBf16><<<conv_blocks(n, 3), 256, 0, s>>>(in, w, b, nullptr,
-                                                                              out, n);
+                                                                              out, n, nullptr, nullptr);
     else
-        k_conv<16, 2, 4, kEpiBiasF32><<<conv_blocks(n, 3), 256, 0, s>>>(in, w, b, nullptr, out, n);
+        k_conv<16, 2, 4, kEpiBiasF32><<<conv_blocks(n, 3), 256, 0, s>>>(in, w, b, nullptr, out, n,
+                                                                        nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -638,10 +646,12 @@ hipError_t conv_backward_data(hipStream_t s, int layer, const uint16_t* dz, cons
                               const uint16_t* act_in, uint16_t* dact, int n) {
     if (layer == 2)
         k_conv<4, 16, 16, kEpiMaskBf16><<<conv_blocks(n, 8), 256, 0, s>>>(dz, wbwd, nullptr,
-                                                                         act_in, dact, n);
+                                                                         act_in, dact, n,
+                                                                         nullptr, nullptr);
     else
         k_conv<16, 16, 16, kEpiMaskBf16><<<conv_blocks(n, 3), 256, 0, s>>>(dz, wbwd, nullptr,
-                                                                          act_in, dact, n);
+                                                                          act_in, dact, n,
+                                                                          nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -697,13 +707,21 @@ hipError_t net_state_pack(hipStream_t s, const float* psi, const float* phi, uin
     return hipGetLastError();
 }
 
-hipError_t net_apply_delta(hipStream_t s, float* psi, const float* d, int64_t cells, double* scal,
-                           double* part, bool rescale) {
-    k_apply_delta<<<kMassBlocks, 256, 0, s>>>(psi, d, cells, scal, part);
-    k_sum_parts<<<1, 256, 0, s>>>(part, kMassBlocks, scal, 2);
+// The network's last layer with the correction in its epilogue: psi +=
+// s_out (layer output), the corrected mass summed per work-group and then in
+// a fixed order into scal[2]; with `rescale`, psi *= sqrt(scal[1] / scal[2]).
+hipError_t net_last_layer_apply(hipStream_t s, const uint16_t* in, const uint16_t* w,
+                                const float* b, float* psi, int n, double* scal, double* part,
+                                bool rescale) {
+    const unsigned g = conv_blocks(n, 3);
+    if (g > unsigned(kMassBlocks)) return hipErrorInvalidValue;   // the partials' capacity
+    k_conv<16, 2, 4, kEpiApply><<<g, 256, 0, s>>>(in, w, b, nullptr, psi, n, scal, part);
+    k_sum_parts<<<1, 256, 0, s>>>(part, int(g), scal, 2);
+    const int64_t cells = int64_t(n) * n * n;
     if (rescale) k_rescale<<<unsigned((2 * cells + 255) / 256), 256, 0, s>>>(psi, cells, scal);
     return hipGetLastError();
 }
+
 
 hipError_t net_pair(hipStream_t s, const float* psi, const float* phi, const float* target,
                     float* x, float* y, int64_t cells) {
