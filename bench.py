@@ -507,6 +507,21 @@ def main():
                     "traffic": traffic_from_profiles(dom["name"], pass_variant(dom["name"], tuning)),
                     "fft_plan_variant": pass_variant(dom["name"], tuning),
                     "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6}
+    # what a wdm_step call of K steps carries besides its K steps: the closing
+    # half kick (P1's kick-only pass and the particles' closing kick) once per
+    # call, and a particle re-sort every sort_interval steps
+    amortised = None
+    if per_kernel:
+        close_us = sum(per_kernel[k]["avg_us"] for k in ("z_potential_close_kick",
+                                                          "particles_close_kick")
+                       if k in per_kernel)
+        sort = per_kernel.get("particle_sort")
+        amortised = {"closing_kick_us_per_call": close_us,
+                     "closing_kick_us_per_step": close_us / args.steps,
+                     "sorts_in_profiled_region": sort["launches"] if sort else 0,
+                     "sort_us": sort["avg_us"] if sort else None,
+                     "sort_us_per_step": (sort["launches"] * sort["avg_us"] / args.steps
+                                          if sort else 0.0)}
     step_bytes = STEP_BYTES_PER_CELL * n3 + STEP_BYTES_PER_PARTICLE * wl.n_particles
     step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
 
@@ -544,6 +559,7 @@ def main():
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
                           "copy_kernel_gbs": copy_gbs},
         "per_kernel": per_kernel,
+        "per_call_amortised": amortised,
         "timing": "value: captured-graph replay, no per-kernel events; per_kernel and "
                   "roofline: HIP events around every launch over an equal profiled region",
         "profiled_region_ms_per_step": (elapsed_prof * 1e3 / args.steps) if elapsed_prof else None,
