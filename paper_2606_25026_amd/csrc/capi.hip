@@ -1100,10 +1100,14 @@ wdm_status wdm_use_graphs(wdm_plan* p, int32_t enable) {
 
 namespace {
 
-// The second plan replaces the default only when its median launch time is
-// this fraction faster: the plans of one pass are usually within a few per
-// cent, and a choice made on noise would change from run to run.
+// Another plan replaces the default only when its median launch time is this
+// fraction faster: the plans of one pass are usually within a few per cent,
+// and a choice made on noise would change from run to run.
 constexpr float kTuneMargin = 0.02f;
+// Plans a pass can take: 0 the default, 1 the second radix plan (twice the
+// lanes per pencil), 2 (strided passes: y and x) the default radices with
+// twice the pencils per work-group, i.e. 256-byte row segments.
+constexpr int kTunePlans = 3;
 
 // Axis length that decides each tunable pass's plan.
 int tune_axis(const SizeClass& c, int slot) {
@@ -1112,6 +1116,16 @@ int tune_axis(const SizeClass& c, int slot) {
         case kTyPsi: case kTySpec: return c.ny;
         default: return c.nx;
     }
+}
+
+bool strided_slot(int slot) { return slot != kTzPot && slot != kTzDens; }
+
+// Whether plan v exists for a pass of the class.
+bool plan_available(const SizeClass& c, int slot, int v) {
+    const int n = tune_axis(c, slot);
+    if (v == 0) return true;
+    if (v == 1) return axis_has_variant(n);
+    return v == 2 && strided_slot(slot) && axis_has_wide(n);
 }
 
 // One launch of a tunable pass with plan variant v (both directions of the
@@ -1157,9 +1171,10 @@ wdm_status wdm_set_tuning(wdm_plan* p, const int32_t* in, int32_t n) {
     for (size_t k = 0; k < p->classes.size(); ++k)
         for (int j = 0; j < kTuneSlots; ++j) {
             const int v = in[k * kTuneSlots + j];
-            if (v != 0 && v != 1) return fail(WDM_EINVAL, "plan variants are 0 or 1");
-            if (v == 1 && !axis_has_variant(tune_axis(p->classes[k], j)))
-                return fail(WDM_EINVAL, "no second plan for this axis length");
+            if (v < 0 || v >= kTunePlans) return fail(WDM_EINVAL, "plan variants are 0, 1 or 2");
+            if (!plan_available(p->classes[k], j, v))
+                return fail(WDM_EINVAL, v == 1 ? "no second plan for this axis length"
+                                               : "no wide-row plan for this pass and length");
         }
     for (size_t k = 0; k < p->classes.size(); ++k)
         for (int j = 0; j < kTuneSlots; ++j) p->classes[k].var[j] = in[k * kTuneSlots + j];
@@ -1171,8 +1186,9 @@ wdm_status wdm_autotune(wdm_plan* p, int32_t reps) {
     if (!p) return fail(WDM_EINVAL, "null plan");
     if (reps < 1 || reps > 1000) return fail(WDM_EINVAL, "reps must be in [1, 1000]");
     if (p->profiling) return fail(WDM_ESTATE, "switch profiling off before tuning");
-    // one event pair per timed launch: reps launches of each of two plans
-    std::vector<hipEvent_t> ev(4 * size_t(reps), nullptr);
+    // one event pair per timed launch: reps launches of each plan
+    std::vector<hipEvent_t> ev(2 * size_t(kTunePlans) * size_t(reps), nullptr);
+    auto evp = [&](int r, int v, int w) { return ev[(size_t(r) * kTunePlans + v) * 2 + w]; };
     hipError_t e = hipSuccess;
     for (auto& x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
@@ -1203,36 +1219,41 @@ wdm_status wdm_autotune(wdm_plan* p, int32_t reps) {
         }
         for (int j = 0; j < kTuneSlots && e == hipSuccess; ++j) {
             c.var[j] = 0;
-            if (!axis_has_variant(tune_axis(c, j))) continue;
+            int plans[kTunePlans], np = 0;
+            for (int v = 0; v < kTunePlans; ++v)
+                if (plan_available(c, j, v)) plans[np++] = v;
+            if (np < 2) continue;
             // a warm-up launch of each plan, then reps rounds timing each plan
-            // once per round, in alternating order, every launch on its own
-            for (int v = 0; v < 2 && e == hipSuccess; ++v) e = tune_launch(p, L, c, j, v);
+            // once per round, in rotating order, every launch on its own
+            for (int i = 0; i < np && e == hipSuccess; ++i) e = tune_launch(p, L, c, j, plans[i]);
             for (int r = 0; r < reps && e == hipSuccess; ++r)
-                for (int q = 0; q < 2 && e == hipSuccess; ++q) {
-                    const int v = (r + q) & 1;
-                    hipEvent_t a = ev[4 * size_t(r) + 2 * v], b = ev[4 * size_t(r) + 2 * v + 1];
-                    if ((e = hipEventRecord(a, p->stream)) != hipSuccess) break;
-                    if ((e = tune_launch(p, L, c, j, v)) != hipSuccess) break;
-                    e = hipEventRecord(b, p->stream);
+                for (int q = 0; q < np && e == hipSuccess; ++q) {
+                    const int i = (r + q) % np;
+                    if ((e = hipEventRecord(evp(r, i, 0), p->stream)) != hipSuccess) break;
+                    if ((e = tune_launch(p, L, c, j, plans[i])) != hipSuccess) break;
+                    e = hipEventRecord(evp(r, i, 1), p->stream);
                 }
             if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-            std::vector<float> t[2];
+            std::vector<float> t[kTunePlans];
             for (int r = 0; r < reps && e == hipSuccess; ++r)
-                for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+                for (int i = 0; i < np && e == hipSuccess; ++i) {
                     float ms = 0.0f;
-                    e = hipEventElapsedTime(&ms, ev[4 * size_t(r) + 2 * v],
-                                            ev[4 * size_t(r) + 2 * v + 1]);
-                    t[v].push_back(ms);
+                    e = hipEventElapsedTime(&ms, evp(r, i, 0), evp(r, i, 1));
+                    t[i].push_back(ms);
                 }
             if (e != hipSuccess) break;
-            // medians; the second plan must win by kTuneMargin to replace the default
-            float med[2];
-            for (int v = 0; v < 2; ++v) {
-                std::sort(t[v].begin(), t[v].end());
-                const size_t h = t[v].size() / 2;
-                med[v] = t[v].size() % 2 ? t[v][h] : 0.5f * (t[v][h - 1] + t[v][h]);
+            // medians; another plan must win by kTuneMargin to replace the
+            // default, and the fastest such plan is taken
+            float med[kTunePlans];
+            for (int i = 0; i < np; ++i) {
+                std::sort(t[i].begin(), t[i].end());
+                const size_t h = t[i].size() / 2;
+                med[i] = t[i].size() % 2 ? t[i][h] : 0.5f * (t[i][h - 1] + t[i][h]);
             }
-            c.var[j] = med[1] < (1.0f - kTuneMargin) * med[0] ? 1 : 0;
+            int best = 0;
+            for (int i = 1; i < np; ++i)
+                if (med[i] < (1.0f - kTuneMargin) * med[0] && med[i] < med[best]) best = i;
+            c.var[j] = plans[best];
         }
     }
     release();

@@ -274,6 +274,16 @@ template <class P, std::size_t... I>
 struct ReverseHelper<P, std::index_sequence<I...>> {
     using type = FftPlan<P::N, P::T, P::radix[P::L - 1 - I]...>;
 };
+// The same plan with twice the pencils per work-group of the strided passes
+// (256-byte row segments for complex64): an autotuner choice.
+template <class P>
+struct WideRows : P {
+    static constexpr int kRowMul = 2;
+};
+template <class Q, std::size_t... I>
+struct ReverseHelper<WideRows<Q>, std::index_sequence<I...>> {
+    using type = WideRows<typename ReverseHelper<Q, std::index_sequence<I...>>::type>;
+};
 template <class P>
 using Reversed = typename ReverseHelper<P, std::make_index_sequence<P::L>>::type;
 

@@ -49,9 +49,20 @@ template <> struct PlanFor<256, 1> { using type = FftPlan<256, 32, 8, 8, 4>; };
 template <> struct PlanFor<384, 1> { using type = FftPlan<384, 32, 6, 4, 4, 4>; };
 template <> struct PlanFor<512, 1> { using type = FftPlan<512, 64, 8, 8, 8>; };
 
+// V = 2 (strided passes only): the default radices with twice the pencils per
+// work-group (row segments of 256 bytes for complex64), for lengths up to 256.
+template <int N>
+struct PlanFor<N, 2> {
+    using type = WideRows<typename PlanFor<N, 0>::type>;
+};
+
 // Lengths with a second plan.
 constexpr bool has_variant(int n) {
     return n == 32 || n == 64 || n == 128 || n == 256 || n == 384 || n == 512;
+}
+// Lengths with the wide-row plan of the strided passes.
+constexpr bool has_wide(int n) {
+    return n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
 }
 static_assert(PlanFor<16>::type::valid() && PlanFor<32>::type::valid() &&
                   PlanFor<64>::type::valid() && PlanFor<96>::type::valid() &&
@@ -64,10 +75,21 @@ static_assert(PlanFor<32, 1>::type::valid() && PlanFor<64, 1>::type::valid() &&
                   PlanFor<384, 1>::type::valid() && PlanFor<512, 1>::type::valid(),
               "second plans");
 
-// Pencils per work-group: at least 128 bytes per row segment, at least 256 lanes.
+// Row-segment multiplier of a plan (2 for WideRows).
+template <class P, class = void>
+struct RowMul {
+    static constexpr int v = 1;
+};
+template <class P>
+struct RowMul<P, std::void_t<decltype(P::kRowMul)>> {
+    static constexpr int v = P::kRowMul;
+};
+
+// Pencils per work-group: at least 128 bytes per row segment (256 for a
+// wide-row plan), at least 256 lanes.
 template <class P, typename T>
 constexpr int pencils_per_wg() {
-    constexpr int pmin = 128 / int(sizeof(cplx<T>));
+    constexpr int pmin = 128 * RowMul<P>::v / int(sizeof(cplx<T>));
     constexpr int pfill = 256 / P::T;
     return pmin > pfill ? pmin : pfill;
 }

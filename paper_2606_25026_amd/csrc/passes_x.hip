@@ -230,6 +230,8 @@ struct XKin {
     static hipError_t pick(const Launch& L, int ny, int nz, int var) {
         if constexpr (has_variant(NX))
             if (var == 1) return go<T, 1>(L, ny, nz);
+        if constexpr (has_wide(NX))
+            if (var == 2) return go<T, 2>(L, ny, nz);
         return go<T, 0>(L, ny, nz);
     }
     static hipError_t run(const Launch& L, int prec, int ny, int nz, int var) {
@@ -250,6 +252,8 @@ struct XGreen {
     static hipError_t pick(const Launch& L, int ny, int nz, int var) {
         if constexpr (has_variant(NX))
             if (var == 1) return go<T, 1>(L, ny, nz);
+        if constexpr (has_wide(NX))
+            if (var == 2) return go<T, 2>(L, ny, nz);
         return go<T, 0>(L, ny, nz);
     }
     static hipError_t run(const Launch& L, int prec, int ny, int nz, int var) {

@@ -13,6 +13,7 @@ bool axis_supported(int n) {
 }
 
 bool axis_has_variant(int n) { return axis_supported(n) && has_variant(n); }
+bool axis_has_wide(int n) { return axis_supported(n) && has_wide(n); }
 
 // P2 / P4 (psi) and P6 / P8 (half spectrum + Nyquist plane).
 template <int NY, typename T, bool INV, bool SPEC, int V>
@@ -201,6 +202,8 @@ struct YFft {
     static hipError_t pick(const Launch& L, int nx, int nz, bool inv, bool spec, int var) {
         if constexpr (has_variant(NY))
             if (var == 1) return go<T, 1>(L, nx, nz, inv, spec);
+        if constexpr (has_wide(NY))
+            if (var == 2) return go<T, 2>(L, nx, nz, inv, spec);
         return go<T, 0>(L, nx, nz, inv, spec);
     }
     static hipError_t run(const Launch& L, int prec, int nx, int nz, bool inv, bool spec,

@@ -124,6 +124,8 @@ enum DensOp : int {
 bool axis_supported(int n);
 // True where the axis length has a second FFT plan (the autotuner's choice).
 bool axis_has_variant(int n);
+// Whether a length has the wide-row plan (V = 2) of the strided passes.
+bool axis_has_wide(int n);
 // P1: half spectrum -> Phi (C2R along z), then kick and optionally z-FFT.
 // `extended` selects the kick with the local self-interaction, the absorbing
 // boundary and the external potential (needed when a member of the class has

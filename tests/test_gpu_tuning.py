@@ -1,7 +1,9 @@
-"""The step passes' second FFT plans (twice the lanes per pencil, half the
-values per lane) and the autotuner that chooses between plans: forced second
-plans against the FP64 oracle, tuned plans against the oracle, and the
-choice table's validation and cache.
+"""The step passes' other FFT plans -- the second radix plan (twice the lanes
+per pencil, half the values per lane) and, for the strided passes, the
+wide-row plan (twice the pencils per work-group, 256-byte row segments) --
+and the autotuner that chooses among them: forced plans against the FP64
+oracle, tuned plans against the oracle, and the choice table's validation and
+cache.
 """
 import json
 
@@ -32,6 +34,10 @@ def all_second(wdm, plan):
     except wdm.WdmError:
         table = None
     return table
+
+
+# tuning slots: P1, P2/P4, P3, P5, P6/P8, P7; the strided ones take the wide-row plan
+WIDE = [0, 2, 2, 0, 2, 2]
 
 
 def run_psi(wdm, plan, psi, steps, dt, prec, pos=None, vel=None):
@@ -87,7 +93,8 @@ def test_autotuned_plan_matches_oracle(wdm, orc):
     plan = wdm.Plan(cfg)
     wdm.wdm_autotune(plan.handle, 3)
     table = wdm.wdm_get_tuning(plan.handle)
-    assert len(table) == 6 and set(table) <= {0, 1}
+    assert len(table) == 6 and set(table) <= {0, 1, 2}
+    assert table[0] in (0, 1) and table[3] in (0, 1)        # z passes: no wide-row plan
     print(f"32^3 tuned plan variants: {table}")
     got = run_psi(wdm, plan, wl.psi, 100, wl.dt, 0)
     ref, _, _ = orc.kdk(orc.make_config((32,) * 3), wl.psi, nsteps=100, dt=wl.dt)
@@ -97,7 +104,7 @@ def test_autotuned_plan_matches_oracle(wdm, orc):
 
 def test_autotune_overwrites_state_and_validates_tables(wdm):
     wl = inputs.plane_wave_box(32, seed=0)
-    # two size classes: 96^3 has no second plan, 32^3 has
+    # two size classes: 96^3 has no second radix plan, 32^3 has
     cfgs = [wdm.make_config(96), wdm.make_config(32)]
     plan = wdm.Plan(cfgs)
     assert wdm.wdm_tuning_entries(plan.handle) == 12
@@ -115,7 +122,10 @@ def test_autotune_overwrites_state_and_validates_tables(wdm):
     wdm.wdm_set_tuning(plan.handle, ok)
     assert wdm.wdm_get_tuning(plan.handle) == ok
     wdm.wdm_autotune(plan.handle, 2)
-    assert wdm.wdm_get_tuning(plan.handle)[6:] == [0] * 6
+    t96 = wdm.wdm_get_tuning(plan.handle)[6:]
+    # 96 has no second radix plan: its z passes stay on the default, its
+    # strided passes may take the wide-row plan
+    assert t96[0] == 0 and t96[3] == 0 and set(t96) <= {0, 2}
     with pytest.raises(wdm.WdmError):
         wdm.wdm_step(plan.handle, 1, 1e-4)                  # states were overwritten
     plan.close()
@@ -131,9 +141,61 @@ def test_tuning_cache_round_trip(wdm, tmp_path):
     plan.close()
     plan2 = wdm.Plan(cfg)
     # a different stored table is taken from the cache without re-timing
-    forced = [1 - v for v in t1]
+    forced = [1 if v == 0 else 0 for v in t1]
     store[wdm.tuning_key(cfg)] = forced
     cache.write_text(json.dumps(store))
     assert wdm.autotune(plan2.handle, cfg, cache=str(cache)) == forced
     assert wdm.wdm_get_tuning(plan2.handle) == forced
     plan2.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wide_row_plans_plane_wave_box_vs_oracle(wdm, orc, prec):
+    wl = inputs.plane_wave_box(32, seed=0)
+    plan = wdm.Plan(wdm.make_config(32, precision=prec))
+    wdm.wdm_set_tuning(plan.handle, WIDE)
+    assert wdm.wdm_get_tuning(plan.handle) == WIDE
+    got = run_psi(wdm, plan, wl.psi, 100, wl.dt, prec)
+    ref, _, _ = orc.kdk(orc.make_config((32,) * 3), wl.psi, nsteps=100, dt=wl.dt)
+    err = rel_l2(got, ref)
+    print(f"wide-row plans, 32^3 plane waves, 100 steps, prec={prec}: rel L2 {err:.3e}")
+    assert err < (1e-5 if prec == 0 else 1e-11)
+    plan.close()
+
+
+def test_wide_row_plans_halo_64_with_particles_vs_oracle(wdm, orc):
+    n, npart, steps = 64, 10_000, 20
+    wl = inputs.coupled_halo(n=n, n_particles=npart, seed=1, steps=steps)
+    plan = wdm.Plan(wdm.make_config(n, n_particles=npart, particle_mass=wl.particle_mass))
+    wdm.wdm_set_tuning(plan.handle, WIDE)
+    wdm.wdm_set_sort_interval(plan.handle, 8)
+    got = run_psi(wdm, plan, wl.psi, steps, wl.dt, 0, wl.pos, wl.vel)
+    cfg = orc.make_config((n,) * 3, n_particles=npart, particle_mass=wl.particle_mass)
+    ref, p_ref, _ = orc.kdk(cfg, wl.psi, wl.pos.astype(np.float64), wl.vel.astype(np.float64),
+                            nsteps=steps, dt=wl.dt)
+    err = rel_l2(got, ref)
+    p = torch.empty((npart, 3), dtype=torch.float32, device="cuda")
+    v = torch.empty_like(p)
+    wdm.wdm_particles(plan.handle, 0, p, v)
+    torch.cuda.synchronize()
+    print(f"wide-row plans, halo 64^3 + 1e4, {steps} steps: rel L2 {err:.3e}")
+    assert err < 1e-5
+    assert np.max(np.abs(periodic_diff(p.cpu().numpy(), p_ref))) < 1e-6
+    plan.close()
+
+
+def test_wide_row_plan_validation(wdm):
+    plan = wdm.Plan(wdm.make_config(32))
+    for bad in ([2, 0, 0, 0, 0, 0], [0, 0, 0, 2, 0, 0], [0, 3, 0, 0, 0, 0], [0, -1, 0, 0, 0, 0]):
+        with pytest.raises(wdm.WdmError):
+            wdm.wdm_set_tuning(plan.handle, bad)          # z passes have no wide-row plan
+    assert wdm.wdm_get_tuning(plan.handle) == [0] * 6
+    plan.close()
+    plan = wdm.Plan(wdm.make_config((32, 32, 384)))      # x and y 32, z 384
+    wdm.wdm_set_tuning(plan.handle, WIDE)
+    plan.close()
+    plan = wdm.Plan(wdm.make_config((384, 32, 32)))      # x 384: P3 and P7 have none
+    with pytest.raises(wdm.WdmError):
+        wdm.wdm_set_tuning(plan.handle, WIDE)
+    wdm.wdm_set_tuning(plan.handle, [0, 2, 0, 0, 2, 0])
+    plan.close()
