@@ -76,6 +76,10 @@ constexpr size_t kAlign = 256;
 constexpr double kCKin = 4.0 / (3.0 * kPi);
 // merged steps per replayed step graph (runs of steps between re-sorts)
 constexpr int kStepChunk = 8;
+// resident particle work-groups per CU where the particle kernel is the longer
+// branch of a step or runs alone (deposits of a state); the default (four)
+// leaves room for the psi passes it overlaps
+constexpr int kPartsAlone = 8;
 
 struct Carver {
     size_t off = 0;
@@ -477,7 +481,8 @@ hipError_t rebuild_potential(wdm_plan* p, int32_t member, hipStream_t s, bool rh
     const wdm_config& c = p->cfg[member];
     const Launch L{s, p->table, p->dev_index[member], 1};
     if (!rho_b_ready && c.n_particles > 0 && c.baryon_mode == WDM_BARYON_DYNAMIC) {
-        const hipError_t e = launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det);
+        const hipError_t e =
+            launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det, kPartsAlone);
         if (e != hipSuccess) return e;
     }
     return potential_from_state(p, L, c, rescale);
@@ -744,7 +749,7 @@ wdm_status wdm_set_state(wdm_plan* p, int32_t member, const void* psi, const flo
     if (c.n_particles > 0) {
         HIPCHK(launch_particle_upload(p->stream, m, pos, vel));
         HIPCHK(launch_particle_sort(L, c.n_particles, c.nx, c.ny, c.nz));
-        HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det));
+        HIPCHK(launch_particles(L, p->prec, c.n_particles, 2, kHalfKick, p->det, kPartsAlone));
     }
     HIPCHK(potential_from_state(p, L, c));
     HIPCHK(launch_reduce_grid(L, p->prec, n, 0));
@@ -807,7 +812,8 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
             if (!parts_first && !psi_f()) return e;
             if (!chk(hipStreamWaitEvent(aux, p->ev_fork, 0))) return e;
             if (!chk(timed_on(p, aux, kKParticles, [&] {
-                    return launch_particles(LA, prec, c.moving_np, 0, km, p->det);
+                    return launch_particles(LA, prec, c.moving_np, 0, km, p->det,
+                                            parts_first ? kPartsAlone : 0);
                 })))
                 return e;
             if (!chk(hipEventRecord(p->ev_join, aux))) return e;
@@ -815,7 +821,10 @@ hipError_t enqueue_step(wdm_plan* p, hipStream_t s, hipStream_t aux, KickMode km
         } else {
             if (parts &&
                 !chk(timed(p, kKParticles,
-                           [&] { return launch_particles(L, prec, c.moving_np, 0, km, p->det); })))
+                           [&] {
+                               return launch_particles(L, prec, c.moving_np, 0, km, p->det,
+                                                       kPartsAlone);
+                           })))
                 return e;
             if (!psi_f()) return e;
         }

@@ -320,12 +320,13 @@ __device__ __forceinline__ void deposit_group(A* __restrict__ grid, const Member
 // mode 0: kick + drift + deposit into rho_b; 1: kick only; 2: deposit into
 // rho_b; 3: deposit into scratch (as a real grid).
 //
-// Persistent work-groups: at most kGroupsPerCU per compute unit are launched
-// and each walks the member's 256-particle chunks with a grid stride.  The
-// particle kernel runs beside the y/x/y passes on its own stream; capped this
-// way it leaves them most of the machine instead of flooding every CU at once
-// (measured: 424 us per 256^3 + 1e6 step against 429 us with one work-group per
-// chunk).
+// Persistent work-groups: at most `per_cu` per compute unit are launched and
+// each walks the member's 256-particle chunks with a grid stride.  Beside
+// longer y/x/y passes (the 256^3 step) four per CU leave them most of the
+// machine (0.4065 against 0.4103 ms per step with eight); where the particles
+// are the step's longer branch (10^6 particles on 128^3) eight per CU shorten
+// it (0.1146 against 0.1176 ms), and alone the kernel runs 44.5 against
+// 47 us at 256^3 + 10^6.
 constexpr int kGroupsPerCU = 4;
 
 // With S = m.substeps leapfrog sub-steps of h = dt / S (Sec. 3.2.2), mode 0
@@ -425,10 +426,11 @@ __global__ __launch_bounds__(256) void k_fixed_to_real(const MemberDev* __restri
 }
 
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
-                            KickMode kick, bool det) {
+                            KickMode kick, bool det, int per_cu) {
     if (max_np <= 0) return hipSuccess;
+    if (per_cu <= 0) per_cu = kGroupsPerCU;
     const int64_t chunks = (max_np + kParticleWG - 1) / kParticleWG;
-    const int64_t cap = int64_t(kGroupsPerCU) * device_cus();
+    const int64_t cap = int64_t(per_cu) * device_cus();
     dim3 grid(unsigned(chunks < cap ? chunks : cap), unsigned(L.count));
     const bool fx = det && mode != 1;   // mode 1 deposits nothing
     if (prec) {

@@ -166,9 +166,10 @@ hipError_t launch_x_kinetic_energy(const Launch& L, int prec, int nx, int ny, in
 
 // ---- particles (particles.hip) ----
 // mode 0: kick (tau) + drift (dt) + deposit; 1: kick only; 2: deposit only
-// into rho_b; 3: deposit only into scratch (as real grid).
+// into rho_b; 3: deposit only into scratch (as real grid).  per_cu: resident
+// work-groups per compute unit (0: the default, four).
 hipError_t launch_particles(const Launch& L, int prec, int64_t max_np, int mode,
-                            KickMode kick, bool det = false);
+                            KickMode kick, bool det = false, int per_cu = 0);
 // Stable radix sort by Morton cell key of every member of a size class.
 hipError_t launch_particle_sort(const Launch& L, int64_t max_np, int nx, int ny, int nz);
 hipError_t launch_particle_unsort(hipStream_t s, const MemberDev& m, float* pos_out,
