@@ -290,12 +290,14 @@ wdm_status wdm_use_graphs(wdm_plan* plan, int32_t enable);
 wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);
 
 /* Autotuning of the step's FFT passes.  Each tunable pass (P1, P2/P4, P3, P5,
- * P6/P8, P7) of each size class chooses among up to three FFT plans: 0, the
+ * P6/P8, P7) of each size class chooses among up to four FFT plans: 0, the
  * default; 1, where the axis length allows (32, 64, 128, 256, 384, 512), twice
  * the lanes per pencil and half the values per lane; 2, for the strided
  * passes (P2/P4, P3, P6/P8, P7) at axis lengths up to 256, the default radices
  * with twice the pencils per work-group (256-byte row segments for complex64,
- * the "z-chunk width").  wdm_autotune times the available plans on the plan's
+ * the "z-chunk width"); 3, for the same passes and lengths, the default
+ * radices exchanging whole complex values through LDS (one barrier pair per
+ * radix level instead of two, twice the LDS).  wdm_autotune times the available plans on the plan's
  * stream (a warm-up launch each, then `reps` rounds, reps in [1, 1000], timing
  * each plan once per round in rotating order, each launch between its own
  * events, on zeroed fields) and leaves the default unless another plan's
@@ -307,7 +309,7 @@ wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);
  * wdm_tuning_entries: number of int32 entries of the choice table (size
  * classes in ascending (nx, ny, nz) order, six passes each in the order above;
  * 0 for a null plan).  wdm_get_tuning / wdm_set_tuning copy the table to / from
- * a host array of exactly that length (values 0, 1 or 2, each only where that
+ * a host array of exactly that length (values 0 to 3, each only where that
  * plan exists for the pass and its axis length, else WDM_EINVAL and nothing
  * changes), e.g. to reuse a cached choice without re-timing. */
 wdm_status wdm_autotune(wdm_plan* plan, int32_t reps);

@@ -1115,8 +1115,9 @@ namespace {
 constexpr float kTuneMargin = 0.02f;
 // Plans a pass can take: 0 the default, 1 the second radix plan (twice the
 // lanes per pencil), 2 (strided passes: y and x) the default radices with
-// twice the pencils per work-group, i.e. 256-byte row segments.
-constexpr int kTunePlans = 3;
+// twice the pencils per work-group, i.e. 256-byte row segments, 3 (strided
+// passes) the default radices exchanging whole complex values through LDS.
+constexpr int kTunePlans = 4;
 
 // Axis length that decides each tunable pass's plan.
 int tune_axis(const SizeClass& c, int slot) {
@@ -1134,7 +1135,7 @@ bool plan_available(const SizeClass& c, int slot, int v) {
     const int n = tune_axis(c, slot);
     if (v == 0) return true;
     if (v == 1) return axis_has_variant(n);
-    return v == 2 && strided_slot(slot) && axis_has_wide(n);
+    return (v == 2 || v == 3) && strided_slot(slot) && axis_has_wide(n);
 }
 
 // One launch of a tunable pass with plan variant v (both directions of the
@@ -1180,10 +1181,12 @@ wdm_status wdm_set_tuning(wdm_plan* p, const int32_t* in, int32_t n) {
     for (size_t k = 0; k < p->classes.size(); ++k)
         for (int j = 0; j < kTuneSlots; ++j) {
             const int v = in[k * kTuneSlots + j];
-            if (v < 0 || v >= kTunePlans) return fail(WDM_EINVAL, "plan variants are 0, 1 or 2");
+            if (v < 0 || v >= kTunePlans)
+                return fail(WDM_EINVAL, "plan variants are 0, 1, 2 or 3");
             if (!plan_available(p->classes[k], j, v))
-                return fail(WDM_EINVAL, v == 1 ? "no second plan for this axis length"
-                                               : "no wide-row plan for this pass and length");
+                return fail(WDM_EINVAL, v == 1   ? "no second plan for this axis length"
+                                        : v == 2 ? "no wide-row plan for this pass and length"
+                                                 : "no complex-exchange plan for this pass and length");
         }
     for (size_t k = 0; k < p->classes.size(); ++k)
         for (int j = 0; j < kTuneSlots; ++j) p->classes[k].var[j] = in[k * kTuneSlots + j];

@@ -284,6 +284,17 @@ template <class Q, std::size_t... I>
 struct ReverseHelper<WideRows<Q>, std::index_sequence<I...>> {
     using type = WideRows<typename ReverseHelper<Q, std::index_sequence<I...>>::type>;
 };
+// The same plan exchanging whole complex values through LDS in the strided
+// passes (one barrier pair per level instead of two, twice the LDS): an
+// autotuner choice.
+template <class P>
+struct ComplexExchange : P {
+    static constexpr bool kComplexX = true;
+};
+template <class Q, std::size_t... I>
+struct ReverseHelper<ComplexExchange<Q>, std::index_sequence<I...>> {
+    using type = ComplexExchange<typename ReverseHelper<Q, std::index_sequence<I...>>::type>;
+};
 template <class P>
 using Reversed = typename ReverseHelper<P, std::make_index_sequence<P::L>>::type;
 

@@ -56,11 +56,18 @@ struct PlanFor<N, 2> {
     using type = WideRows<typename PlanFor<N, 0>::type>;
 };
 
+// V = 3 (strided passes only): the default radices with the complex LDS
+// exchange, for lengths up to 256.
+template <int N>
+struct PlanFor<N, 3> {
+    using type = ComplexExchange<typename PlanFor<N, 0>::type>;
+};
+
 // Lengths with a second plan.
 constexpr bool has_variant(int n) {
     return n == 32 || n == 64 || n == 128 || n == 256 || n == 384 || n == 512;
 }
-// Lengths with the wide-row plan of the strided passes.
+// Lengths with the wide-row and complex-exchange plans of the strided passes.
 constexpr bool has_wide(int n) {
     return n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
 }
@@ -110,12 +117,25 @@ constexpr int lds_entries() {
 // count; along the contiguous axis the three-level plans (96, 192, 384, 512)
 // need more registers with it (P1 at 512: 114 -> 131, 3 waves per SIMD, 628
 // -> 1125 us a pass), so they keep the complex exchange.
+// A ComplexExchange plan always exchanges whole complex values.
+template <class P, class = void>
+struct IsComplexX {
+    static constexpr bool v = false;
+};
+template <class P>
+struct IsComplexX<P, std::void_t<decltype(P::kComplexX)>> {
+    static constexpr bool v = P::kComplexX;
+};
 template <class P, bool STRIDED>
 constexpr bool split_exchange() {
-    return STRIDED || P::L <= 2;
+    return !IsComplexX<P>::v && (STRIDED || P::L <= 2);
 }
 template <class P, typename T, bool STRIDED>
 using lds_t = std::conditional_t<split_exchange<P, STRIDED>(), T, cplx<T>>;
+// LDS element type of the strided-axis passes (whose Nyquist-plane tiles use
+// the contiguous mapping with the same exchange).
+template <class P, typename T>
+using strided_lds_t = std::conditional_t<IsComplexX<P>::v, cplx<T>, T>;
 
 // Lane coordinates and LDS addressing for the two pencil mappings.
 //   strided:    neighbouring lanes take neighbouring pencils (rows in memory
@@ -304,9 +324,9 @@ struct Strides {
 };
 
 // Plain transform of one batch of pencils.
-template <class P, typename T, bool INV, bool STRIDED>
+template <class P, typename T, bool INV, bool STRIDED, typename LT>
 __device__ __forceinline__ void transform_tile(cplx<T>* data, const Strides& sd, int64_t tile,
-                                               T* lds, const cplx<T>* tw) {
+                                               LT* lds, const cplx<T>* tw) {
     using LN = Lanes<P, T, STRIDED>;
     const LN ln;
     const int64_t q = tile * LN::PP + ln.p;

@@ -18,7 +18,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
     using LN = Lanes<FP, T, true>;
     constexpr int WG = wg_size<FP, T>();
     constexpr bool kSplit = std::is_same<T, float>::value;
-    __shared__ T lds[lds_entries<FP, T, true>()];
+    __shared__ strided_lds_t<FP, T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ cplx<double> ex[NX];   // e_x in FP64
     const MemberDev& m = mems[first + blockIdx.y];
@@ -84,7 +84,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
     using FP = typename PlanFor<NX, V>::type;
     using IP = Reversed<FP>;
     using LN = Lanes<FP, T, true>;
-    __shared__ T lds[lds_entries<FP, T, true>()];
+    __shared__ strided_lds_t<FP, T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ double kx2[NX];
     const MemberDev& m = mems[first + blockIdx.y];
@@ -230,8 +230,10 @@ struct XKin {
     static hipError_t pick(const Launch& L, int ny, int nz, int var) {
         if constexpr (has_variant(NX))
             if (var == 1) return go<T, 1>(L, ny, nz);
-        if constexpr (has_wide(NX))
+        if constexpr (has_wide(NX)) {
             if (var == 2) return go<T, 2>(L, ny, nz);
+            if (var == 3) return go<T, 3>(L, ny, nz);
+        }
         return go<T, 0>(L, ny, nz);
     }
     static hipError_t run(const Launch& L, int prec, int ny, int nz, int var) {
@@ -252,8 +254,10 @@ struct XGreen {
     static hipError_t pick(const Launch& L, int ny, int nz, int var) {
         if constexpr (has_variant(NX))
             if (var == 1) return go<T, 1>(L, ny, nz);
-        if constexpr (has_wide(NX))
+        if constexpr (has_wide(NX)) {
             if (var == 2) return go<T, 2>(L, ny, nz);
+            if (var == 3) return go<T, 3>(L, ny, nz);
+        }
         return go<T, 0>(L, ny, nz);
     }
     static hipError_t run(const Launch& L, int prec, int ny, int nz, int var) {

@@ -21,7 +21,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY, V>::type, T>())) void
     const MemberDev* __restrict__ mems, int first) {
     using FP = typename PlanFor<NY, V>::type;
     constexpr int PP = pencils_per_wg<FP, T>();
-    __shared__ T lds[lds_entries<FP, T, !SPEC>()];
+    __shared__ strided_lds_t<FP, T> lds[lds_entries<FP, T, !SPEC>()];
     __shared__ cplx<T> tw[tw_entries<T>(NY)];
     const MemberDev& m = mems[first + blockIdx.y];
     load_twiddles<NY, wg_size<FP, T>()>(tw, m.tw_y);
@@ -202,8 +202,10 @@ struct YFft {
     static hipError_t pick(const Launch& L, int nx, int nz, bool inv, bool spec, int var) {
         if constexpr (has_variant(NY))
             if (var == 1) return go<T, 1>(L, nx, nz, inv, spec);
-        if constexpr (has_wide(NY))
+        if constexpr (has_wide(NY)) {
             if (var == 2) return go<T, 2>(L, nx, nz, inv, spec);
+            if (var == 3) return go<T, 3>(L, nx, nz, inv, spec);
+        }
         return go<T, 0>(L, nx, nz, inv, spec);
     }
     static hipError_t run(const Launch& L, int prec, int nx, int nz, bool inv, bool spec,

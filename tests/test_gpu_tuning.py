@@ -1,7 +1,8 @@
 """The step passes' other FFT plans -- the second radix plan (twice the lanes
 per pencil, half the values per lane) and, for the strided passes, the
-wide-row plan (twice the pencils per work-group, 256-byte row segments) --
-and the autotuner that chooses among them: forced plans against the FP64
+wide-row plan (twice the pencils per work-group, 256-byte row segments) and
+the complex-exchange plan (whole complex values through LDS) -- and the
+autotuner that chooses among them: forced plans against the FP64
 oracle, tuned plans against the oracle, and the choice table's validation and
 cache.
 """
@@ -36,8 +37,11 @@ def all_second(wdm, plan):
     return table
 
 
-# tuning slots: P1, P2/P4, P3, P5, P6/P8, P7; the strided ones take the wide-row plan
+# tuning slots: P1, P2/P4, P3, P5, P6/P8, P7; the strided ones take the wide-row
+# plan (2) or the complex-exchange plan (3)
 WIDE = [0, 2, 2, 0, 2, 2]
+CX = [0, 3, 3, 0, 3, 3]
+STRIDED_PLANS = {"wide-row": WIDE, "complex-exchange": CX}
 
 
 def run_psi(wdm, plan, psi, steps, dt, prec, pos=None, vel=None):
@@ -93,8 +97,8 @@ def test_autotuned_plan_matches_oracle(wdm, orc):
     plan = wdm.Plan(cfg)
     wdm.wdm_autotune(plan.handle, 3)
     table = wdm.wdm_get_tuning(plan.handle)
-    assert len(table) == 6 and set(table) <= {0, 1, 2}
-    assert table[0] in (0, 1) and table[3] in (0, 1)        # z passes: no wide-row plan
+    assert len(table) == 6 and set(table) <= {0, 1, 2, 3}
+    assert table[0] in (0, 1) and table[3] in (0, 1)        # z passes: no strided-only plan
     print(f"32^3 tuned plan variants: {table}")
     got = run_psi(wdm, plan, wl.psi, 100, wl.dt, 0)
     ref, _, _ = orc.kdk(orc.make_config((32,) * 3), wl.psi, nsteps=100, dt=wl.dt)
@@ -124,8 +128,8 @@ def test_autotune_overwrites_state_and_validates_tables(wdm):
     wdm.wdm_autotune(plan.handle, 2)
     t96 = wdm.wdm_get_tuning(plan.handle)[6:]
     # 96 has no second radix plan: its z passes stay on the default, its
-    # strided passes may take the wide-row plan
-    assert t96[0] == 0 and t96[3] == 0 and set(t96) <= {0, 2}
+    # strided passes may take the wide-row or the complex-exchange plan
+    assert t96[0] == 0 and t96[3] == 0 and set(t96) <= {0, 2, 3}
     with pytest.raises(wdm.WdmError):
         wdm.wdm_step(plan.handle, 1, 1e-4)                  # states were overwritten
     plan.close()
@@ -149,25 +153,28 @@ def test_tuning_cache_round_trip(wdm, tmp_path):
     plan2.close()
 
 
+@pytest.mark.parametrize("kind", sorted(STRIDED_PLANS))
 @pytest.mark.parametrize("prec", [0, 1])
-def test_wide_row_plans_plane_wave_box_vs_oracle(wdm, orc, prec):
+def test_strided_plans_plane_wave_box_vs_oracle(wdm, orc, prec, kind):
     wl = inputs.plane_wave_box(32, seed=0)
     plan = wdm.Plan(wdm.make_config(32, precision=prec))
-    wdm.wdm_set_tuning(plan.handle, WIDE)
-    assert wdm.wdm_get_tuning(plan.handle) == WIDE
+    table = STRIDED_PLANS[kind]
+    wdm.wdm_set_tuning(plan.handle, table)
+    assert wdm.wdm_get_tuning(plan.handle) == table
     got = run_psi(wdm, plan, wl.psi, 100, wl.dt, prec)
     ref, _, _ = orc.kdk(orc.make_config((32,) * 3), wl.psi, nsteps=100, dt=wl.dt)
     err = rel_l2(got, ref)
-    print(f"wide-row plans, 32^3 plane waves, 100 steps, prec={prec}: rel L2 {err:.3e}")
+    print(f"{kind} plans, 32^3 plane waves, 100 steps, prec={prec}: rel L2 {err:.3e}")
     assert err < (1e-5 if prec == 0 else 1e-11)
     plan.close()
 
 
-def test_wide_row_plans_halo_64_with_particles_vs_oracle(wdm, orc):
+@pytest.mark.parametrize("kind", sorted(STRIDED_PLANS))
+def test_strided_plans_halo_64_with_particles_vs_oracle(wdm, orc, kind):
     n, npart, steps = 64, 10_000, 20
     wl = inputs.coupled_halo(n=n, n_particles=npart, seed=1, steps=steps)
     plan = wdm.Plan(wdm.make_config(n, n_particles=npart, particle_mass=wl.particle_mass))
-    wdm.wdm_set_tuning(plan.handle, WIDE)
+    wdm.wdm_set_tuning(plan.handle, STRIDED_PLANS[kind])
     wdm.wdm_set_sort_interval(plan.handle, 8)
     got = run_psi(wdm, plan, wl.psi, steps, wl.dt, 0, wl.pos, wl.vel)
     cfg = orc.make_config((n,) * 3, n_particles=npart, particle_mass=wl.particle_mass)
@@ -178,24 +185,27 @@ def test_wide_row_plans_halo_64_with_particles_vs_oracle(wdm, orc):
     v = torch.empty_like(p)
     wdm.wdm_particles(plan.handle, 0, p, v)
     torch.cuda.synchronize()
-    print(f"wide-row plans, halo 64^3 + 1e4, {steps} steps: rel L2 {err:.3e}")
+    print(f"{kind} plans, halo 64^3 + 1e4, {steps} steps: rel L2 {err:.3e}")
     assert err < 1e-5
     assert np.max(np.abs(periodic_diff(p.cpu().numpy(), p_ref))) < 1e-6
     plan.close()
 
 
-def test_wide_row_plan_validation(wdm):
+def test_strided_plan_validation(wdm):
     plan = wdm.Plan(wdm.make_config(32))
-    for bad in ([2, 0, 0, 0, 0, 0], [0, 0, 0, 2, 0, 0], [0, 3, 0, 0, 0, 0], [0, -1, 0, 0, 0, 0]):
+    # z passes have no strided-only plan; 4 and -1 are no plan
+    for bad in ([2, 0, 0, 0, 0, 0], [0, 0, 0, 2, 0, 0], [3, 0, 0, 0, 0, 0], [0, 0, 0, 3, 0, 0],
+                [0, 4, 0, 0, 0, 0], [0, -1, 0, 0, 0, 0]):
         with pytest.raises(wdm.WdmError):
-            wdm.wdm_set_tuning(plan.handle, bad)          # z passes have no wide-row plan
+            wdm.wdm_set_tuning(plan.handle, bad)
     assert wdm.wdm_get_tuning(plan.handle) == [0] * 6
     plan.close()
-    plan = wdm.Plan(wdm.make_config((32, 32, 384)))      # x and y 32, z 384
-    wdm.wdm_set_tuning(plan.handle, WIDE)
-    plan.close()
-    plan = wdm.Plan(wdm.make_config((384, 32, 32)))      # x 384: P3 and P7 have none
-    with pytest.raises(wdm.WdmError):
-        wdm.wdm_set_tuning(plan.handle, WIDE)
-    wdm.wdm_set_tuning(plan.handle, [0, 2, 0, 0, 2, 0])
-    plan.close()
+    for table in (WIDE, CX):
+        plan = wdm.Plan(wdm.make_config((32, 32, 384)))  # x and y 32, z 384
+        wdm.wdm_set_tuning(plan.handle, table)
+        plan.close()
+        plan = wdm.Plan(wdm.make_config((384, 32, 32)))  # x 384: P3 and P7 have none
+        with pytest.raises(wdm.WdmError):
+            wdm.wdm_set_tuning(plan.handle, table)
+        wdm.wdm_set_tuning(plan.handle, [0, table[1], 0, 0, table[4], 0])
+        plan.close()
