@@ -372,8 +372,9 @@ def main():
                     help="time without per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default FFT plan of every pass (no autotuning)")
-    ap.add_argument("--plans", choices=["tune", "default", "second"], default="tune",
-                    help="step FFT plans: chosen by timing, or all default / all second plans")
+    ap.add_argument("--plans", choices=["tune", "default", "second", "exchange"], default="tune",
+                    help="step FFT plans: chosen by timing, or all default / all second plans / "
+                         "the complex-exchange plan wherever it exists")
     ap.add_argument("--workload", choices=["halo", "ensemble", "precision", "learned"],
                     default="halo")
     ap.add_argument("--learned-small", action="store_true")
@@ -427,6 +428,13 @@ def main():
         tuning = wdm.wdm_get_tuning(h)
     elif args.plans == "second":
         wdm.wdm_set_tuning(h, [1] * wdm.wdm_tuning_entries(h))
+        tuning = wdm.wdm_get_tuning(h)
+    elif args.plans == "exchange":
+        # slots P1, P2/P4, P3, P5, P6/P8, P7: strided passes up to 256, z passes
+        # whose default splits the exchange
+        zcx = 3 if args.n in (16, 32, 64, 128, 256) else 0
+        strided = 3 if args.n <= 256 else 0
+        wdm.wdm_set_tuning(h, [zcx, strided, strided, zcx, strided, strided])
         tuning = wdm.wdm_get_tuning(h)
     else:
         tuning = wdm.autotune(h, cfg, reps=20)

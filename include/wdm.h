@@ -295,9 +295,11 @@ wdm_status wdm_set_sort_interval(wdm_plan* plan, int32_t interval);
  * the lanes per pencil and half the values per lane; 2, for the strided
  * passes (P2/P4, P3, P6/P8, P7) at axis lengths up to 256, the default radices
  * with twice the pencils per work-group (256-byte row segments for complex64,
- * the "z-chunk width"); 3, for the same passes and lengths, the default
- * radices exchanging whole complex values through LDS (one barrier pair per
- * radix level instead of two, twice the LDS).  wdm_autotune times the available plans on the plan's
+ * the "z-chunk width"); 3, the default radices exchanging whole complex
+ * values through LDS (one barrier pair per radix level instead of two, twice
+ * the LDS), for the strided passes at axis lengths up to 256 and for the z
+ * passes at 16, 32, 64, 128 and 256 (whose default splits the exchange).
+ * wdm_autotune times the available plans on the plan's
  * stream (a warm-up launch each, then `reps` rounds, reps in [1, 1000], timing
  * each plan once per round in rotating order, each launch between its own
  * events, on zeroed fields) and leaves the default unless another plan's

@@ -1115,8 +1115,9 @@ namespace {
 constexpr float kTuneMargin = 0.02f;
 // Plans a pass can take: 0 the default, 1 the second radix plan (twice the
 // lanes per pencil), 2 (strided passes: y and x) the default radices with
-// twice the pencils per work-group, i.e. 256-byte row segments, 3 (strided
-// passes) the default radices exchanging whole complex values through LDS.
+// twice the pencils per work-group, i.e. 256-byte row segments, 3 the default
+// radices exchanging whole complex values through LDS (strided passes up to
+// 256; z passes where the default splits the exchange).
 constexpr int kTunePlans = 4;
 
 // Axis length that decides each tunable pass's plan.
@@ -1135,7 +1136,8 @@ bool plan_available(const SizeClass& c, int slot, int v) {
     const int n = tune_axis(c, slot);
     if (v == 0) return true;
     if (v == 1) return axis_has_variant(n);
-    return (v == 2 || v == 3) && strided_slot(slot) && axis_has_wide(n);
+    if (v == 2) return strided_slot(slot) && axis_has_wide(n);
+    return v == 3 && (strided_slot(slot) ? axis_has_wide(n) : axis_has_zcx(n));
 }
 
 // One launch of a tunable pass with plan variant v (both directions of the

@@ -132,6 +132,19 @@ constexpr bool split_exchange() {
 }
 template <class P, typename T, bool STRIDED>
 using lds_t = std::conditional_t<split_exchange<P, STRIDED>(), T, cplx<T>>;
+// Lengths whose contiguous-axis (z) passes split the exchange by default (the
+// two-level plans), so that the complex-exchange plan differs for them too.
+constexpr bool has_zcx(int n) {
+    return n == 16 || n == 32 || n == 64 || n == 128 || n == 256;
+}
+static_assert(split_exchange<PlanFor<16>::type, false>() &&
+                  split_exchange<PlanFor<32>::type, false>() &&
+                  split_exchange<PlanFor<64>::type, false>() &&
+                  split_exchange<PlanFor<128>::type, false>() &&
+                  split_exchange<PlanFor<256>::type, false>() &&
+                  !split_exchange<PlanFor<96>::type, false>() &&
+                  !split_exchange<PlanFor<512>::type, false>(),
+              "z-pass lengths with a complex-exchange plan");
 // LDS element type of the strided-axis passes (whose Nyquist-plane tiles use
 // the contiguous mapping with the same exchange).
 template <class P, typename T>

@@ -281,6 +281,8 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NZ, V>::type, T>())) void
 }
 
 
+bool axis_has_zcx(int n) { return axis_supported(n) && has_zcx(n); }
+
 template <int NZ>
 struct ZPotKick {
     template <typename T, int V, bool GEN>
@@ -316,9 +318,11 @@ struct ZPotKick {
                            bool gen) {
         // the extended kick runs on the default plan only
         if (gen) return go<T, 0, true>(L, nx, ny, op, k);
-        // only the merged kick + z-FFT variant has a second plan
+        // only the merged kick + z-FFT variant has other plans
         if constexpr (has_variant(NZ))
             if (var == 1 && op == kZKickFft) return go<T, 1, false>(L, nx, ny, op, k);
+        if constexpr (has_zcx(NZ))
+            if (var == 3 && op == kZKickFft) return go<T, 3, false>(L, nx, ny, op, k);
         return go<T, 0, false>(L, nx, ny, op, k);
     }
     static hipError_t run(const Launch& L, int prec, int nx, int ny, ZOp op, KickMode k, int var,
@@ -366,6 +370,8 @@ struct ZDens {
                            const double* scal) {
         if constexpr (has_variant(NZ))
             if (var == 1 && op == kDensInvFft) return go<T, 1>(L, nx, ny, op, keep, scal);
+        if constexpr (has_zcx(NZ))
+            if (var == 3 && op == kDensInvFft) return go<T, 3>(L, nx, ny, op, keep, scal);
         return go<T, 0>(L, nx, ny, op, keep, scal);
     }
     static hipError_t run(const Launch& L, int prec, int nx, int ny, DensOp op, int var,

@@ -126,6 +126,7 @@ bool axis_supported(int n);
 bool axis_has_variant(int n);
 // Whether a length has the wide-row plan (V = 2) of the strided passes.
 bool axis_has_wide(int n);
+bool axis_has_zcx(int n);   // z passes with a complex-exchange plan
 // P1: half spectrum -> Phi (C2R along z), then kick and optionally z-FFT.
 // `extended` selects the kick with the local self-interaction, the absorbing
 // boundary and the external potential (needed when a member of the class has

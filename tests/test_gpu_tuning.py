@@ -1,8 +1,8 @@
 """The step passes' other FFT plans -- the second radix plan (twice the lanes
 per pencil, half the values per lane) and, for the strided passes, the
-wide-row plan (twice the pencils per work-group, 256-byte row segments) and
-the complex-exchange plan (whole complex values through LDS) -- and the
-autotuner that chooses among them: forced plans against the FP64
+wide-row plan (twice the pencils per work-group, 256-byte row segments),
+and the complex-exchange plan (whole complex values through LDS; strided
+passes, and z passes whose default splits the exchange) -- and the autotuner that chooses among them: forced plans against the FP64
 oracle, tuned plans against the oracle, and the choice table's validation and
 cache.
 """
@@ -38,9 +38,9 @@ def all_second(wdm, plan):
 
 
 # tuning slots: P1, P2/P4, P3, P5, P6/P8, P7; the strided ones take the wide-row
-# plan (2) or the complex-exchange plan (3)
+# plan (2), every pass the complex-exchange plan (3) at these lengths
 WIDE = [0, 2, 2, 0, 2, 2]
-CX = [0, 3, 3, 0, 3, 3]
+CX = [3, 3, 3, 3, 3, 3]
 STRIDED_PLANS = {"wide-row": WIDE, "complex-exchange": CX}
 
 
@@ -98,7 +98,7 @@ def test_autotuned_plan_matches_oracle(wdm, orc):
     wdm.wdm_autotune(plan.handle, 3)
     table = wdm.wdm_get_tuning(plan.handle)
     assert len(table) == 6 and set(table) <= {0, 1, 2, 3}
-    assert table[0] in (0, 1) and table[3] in (0, 1)        # z passes: no strided-only plan
+    assert table[0] in (0, 1, 3) and table[3] in (0, 1, 3)  # z passes: no wide-row plan
     print(f"32^3 tuned plan variants: {table}")
     got = run_psi(wdm, plan, wl.psi, 100, wl.dt, 0)
     ref, _, _ = orc.kdk(orc.make_config((32,) * 3), wl.psi, nsteps=100, dt=wl.dt)
@@ -127,8 +127,9 @@ def test_autotune_overwrites_state_and_validates_tables(wdm):
     assert wdm.wdm_get_tuning(plan.handle) == ok
     wdm.wdm_autotune(plan.handle, 2)
     t96 = wdm.wdm_get_tuning(plan.handle)[6:]
-    # 96 has no second radix plan: its z passes stay on the default, its
-    # strided passes may take the wide-row or the complex-exchange plan
+    # 96 has no second radix plan and its z passes exchange whole complex
+    # values already: they stay on the default, its strided passes may take
+    # the wide-row or the complex-exchange plan
     assert t96[0] == 0 and t96[3] == 0 and set(t96) <= {0, 2, 3}
     with pytest.raises(wdm.WdmError):
         wdm.wdm_step(plan.handle, 1, 1e-4)                  # states were overwritten
@@ -193,14 +194,19 @@ def test_strided_plans_halo_64_with_particles_vs_oracle(wdm, orc, kind):
 
 def test_strided_plan_validation(wdm):
     plan = wdm.Plan(wdm.make_config(32))
-    # z passes have no strided-only plan; 4 and -1 are no plan
-    for bad in ([2, 0, 0, 0, 0, 0], [0, 0, 0, 2, 0, 0], [3, 0, 0, 0, 0, 0], [0, 0, 0, 3, 0, 0],
-                [0, 4, 0, 0, 0, 0], [0, -1, 0, 0, 0, 0]):
+    # z passes have no wide-row plan; 4 and -1 are no plan
+    for bad in ([2, 0, 0, 0, 0, 0], [0, 0, 0, 2, 0, 0], [0, 4, 0, 0, 0, 0], [0, -1, 0, 0, 0, 0]):
         with pytest.raises(wdm.WdmError):
             wdm.wdm_set_tuning(plan.handle, bad)
     assert wdm.wdm_get_tuning(plan.handle) == [0] * 6
+    wdm.wdm_set_tuning(plan.handle, [3, 0, 0, 3, 0, 0])     # z passes at 32: complex exchange
     plan.close()
-    for table in (WIDE, CX):
+    plan = wdm.Plan(wdm.make_config((32, 32, 96)))       # z 96 exchanges whole values already
+    for bad in ([3, 0, 0, 0, 0, 0], [0, 0, 0, 3, 0, 0]):
+        with pytest.raises(wdm.WdmError):
+            wdm.wdm_set_tuning(plan.handle, bad)
+    plan.close()
+    for table in (WIDE, [0, 3, 3, 0, 3, 3]):
         plan = wdm.Plan(wdm.make_config((32, 32, 384)))  # x and y 32, z 384
         wdm.wdm_set_tuning(plan.handle, table)
         plan.close()
