@@ -18,6 +18,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NX, V>::type, T>())) void
     using LN = Lanes<FP, T, true>;
     constexpr int WG = wg_size<FP, T>();
     constexpr bool kSplit = std::is_same<T, float>::value;
+    __builtin_amdgcn_s_setprio(2);   // beside the particle kernel, as P2 / P4
     __shared__ strided_lds_t<FP, T> lds[lds_entries<FP, T, true>()];
     __shared__ cplx<T> tw[tw_entries<T>(NX)];
     __shared__ cplx<double> ex[NX];   // e_x in FP64
