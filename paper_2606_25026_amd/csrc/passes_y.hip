@@ -24,7 +24,7 @@ __global__ __launch_bounds__((wg_size<typename PlanFor<NY, V>::type, T>())) void
     // P2 / P4 share the machine with the particle kernel: their waves issue
     // first on a SIMD (wave priority 2 of 0-3; the particle waves stay at 0),
     // which keeps these bandwidth-bound passes streaming (256^3 + 1e6 step
-    // 0.4080 -> 0.4062 ms on average over four paired runs on two machines)
+    // 0.4079 -> 0.4060 ms on average over four paired runs on two machines)
     if constexpr (!SPEC) __builtin_amdgcn_s_setprio(2);
     __shared__ strided_lds_t<FP, T> lds[lds_entries<FP, T, !SPEC>()];
     __shared__ cplx<T> tw[tw_entries<T>(NY)];
