@@ -1,6 +1,7 @@
 """Full-size parity: the 256^3 + 1e6-particle coupled halo, in the launch
-configuration the benchmark times, against sampled FP64-oracle values written
-by tests/golden/make_coupled_halo_reference.py (65536 cells, 10000 particles);
+configuration the benchmark times (on each FFT plan the autotuner can choose),
+against sampled FP64-oracle values written by
+tests/golden/make_coupled_halo_reference.py (65536 cells, 10000 particles);
 and the optional parts of the step (self-interaction, absorbing layer, external
 tidal field, particle sub-steps; static baryons) on the same workload over 3
 steps against the oracle run in the test, on the whole grid and every particle.
@@ -38,6 +39,10 @@ def run_vs_golden(wdm, wl, steps, plans, sort_interval=128):
     plan = wdm.Plan(cfg)
     if plans == "second":     # every tunable pass on its second FFT plan
         wdm.wdm_set_tuning(plan.handle, [1] * wdm.wdm_tuning_entries(plan.handle))
+    elif plans == "wide":     # the strided passes on the wide-row plan
+        wdm.wdm_set_tuning(plan.handle, [0, 2, 2, 0, 2, 2])
+    elif plans == "exchange":  # every pass exchanging whole complex values
+        wdm.wdm_set_tuning(plan.handle, [3] * 6)
     psi = torch.from_numpy(wl.psi.astype(np.complex64)).cuda()
     pos = torch.from_numpy(wl.pos).cuda()
     vel = torch.from_numpy(wl.vel).cuda()
@@ -70,7 +75,7 @@ def run_vs_golden(wdm, wl, steps, plans, sort_interval=128):
     return res
 
 
-@pytest.mark.parametrize("plans", ["default", "second"])
+@pytest.mark.parametrize("plans", ["default", "second", "wide", "exchange"])
 def test_coupled_halo_256_100_steps_vs_oracle(wdm, halo, plans):
     r = run_vs_golden(wdm, halo, 100, plans)
     assert r["err"] < 1e-5
