@@ -46,6 +46,18 @@ def test_traffic_lookup_checks_source_hash_and_variant(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("z_density_r2c", 0) is None     # kernels changed
 
 
+def test_committed_traffic_covers_every_plan_the_tuner_can_pick_for_p1():
+    """The bench's roofline kernel (P1) at 256^3 may run its default, second
+    or complex-exchange plan; the committed counters hold each of them for the
+    current kernel sources, so the bench line's traffic field is never null
+    because of the tuner's choice."""
+    for v in (0, 1, 3):
+        hbm = bench.traffic_from_profiles("z_potential_kick", v)
+        assert hbm is not None, f"no counters for plan {v}"
+        alg = bench.BYTES_PER_CELL["z_potential_kick"] * 256 ** 3
+        assert 0.99 < hbm / alg < 1.05
+
+
 def test_pk_error_is_relative_l2_over_shells_from_one():
     pf = np.array([100.0, 4.0, 3.0, 0.0])
     pc = np.array([0.0, 4.0, 3.0, 0.0])     # shell 0 is excluded
