@@ -19,13 +19,24 @@ def periodic_diff(a, b):
     return d - np.round(d)
 
 
-def test_mixed_size_ensemble_matches_oracle(wdm, orc):
+# FFT plan tables of the three size classes (ascending shapes: 32^3, 64^3,
+# 96^3; slots P1, P2/P4, P3, P5, P6/P8, P7): the defaults, the wide-row plan on
+# the strided passes, and the complex exchange wherever it exists (z passes at
+# 96 exchange whole values by default)
+PLANS = {"default": [0] * 18,
+         "wide": [0, 2, 2, 0, 2, 2] * 3,
+         "exchange": [3] * 12 + [0, 3, 3, 0, 3, 3]}
+
+
+@pytest.mark.parametrize("plans", sorted(PLANS))
+def test_mixed_size_ensemble_matches_oracle(wdm, orc, plans):
     sizes = [64, 32, 64, 96, 32]
     npart = 2000
     steps = 10
     members = [inputs.ensemble_member(seed=s, n=n, n_particles=npart) for s, n in enumerate(sizes)]
     cfgs = [wdm.make_config(m.n, n_particles=npart, particle_mass=m.particle_mass) for m in members]
     plan = wdm.Plan(cfgs)
+    wdm.wdm_set_tuning(plan.handle, PLANS[plans])
     bufs = []
     for i, m in enumerate(members):
         psi = torch.from_numpy(m.psi.astype(np.complex64)).cuda()
@@ -47,7 +58,7 @@ def test_mixed_size_ensemble_matches_oracle(wdm, orc):
         ref, pr, vr = orc.kdk(cfg, m.psi, m.pos.astype(np.float64), m.vel.astype(np.float64),
                               nsteps=steps, dt=m.dt)
         err = rel_l2(out.cpu().numpy().astype(np.complex128), ref)
-        print(f"member {i} ({m.n}^3): psi rel L2 {err:.2e}, t = {e['t']:.3e}")
+        print(f"[{plans}] member {i} ({m.n}^3): psi rel L2 {err:.2e}, t = {e['t']:.3e}")
         assert err < 1e-5
         assert e["t"] == pytest.approx(steps * m.dt, rel=1e-12)
         assert np.max(np.abs(periodic_diff(p.cpu().numpy().astype(np.float64), pr))) < 1e-6
