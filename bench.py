@@ -430,11 +430,17 @@ def main():
         wdm.wdm_set_tuning(h, [1] * wdm.wdm_tuning_entries(h))
         tuning = wdm.wdm_get_tuning(h)
     elif args.plans == "exchange":
-        # slots P1, P2/P4, P3, P5, P6/P8, P7: strided passes up to 256, z passes
-        # whose default splits the exchange
-        zcx = 3 if args.n in (16, 32, 64, 128, 256) else 0
-        strided = 3 if args.n <= 256 else 0
-        wdm.wdm_set_tuning(h, [zcx, strided, strided, zcx, strided, strided])
+        # the complex-exchange plan on every pass that has one (the library
+        # rejects a table naming it where it does not exist)
+        ne = wdm.wdm_tuning_entries(h)
+        table = [0] * ne
+        for j in range(ne):
+            try:
+                wdm.wdm_set_tuning(h, [3 if k == j else 0 for k in range(ne)])
+                table[j] = 3
+            except wdm.WdmError:
+                pass
+        wdm.wdm_set_tuning(h, table)
         tuning = wdm.wdm_get_tuning(h)
     else:
         tuning = wdm.autotune(h, cfg, reps=20)
