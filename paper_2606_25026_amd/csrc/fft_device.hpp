@@ -284,9 +284,9 @@ template <class Q, std::size_t... I>
 struct ReverseHelper<WideRows<Q>, std::index_sequence<I...>> {
     using type = WideRows<typename ReverseHelper<Q, std::index_sequence<I...>>::type>;
 };
-// The same plan exchanging whole complex values through LDS in the strided
-// passes (one barrier pair per level instead of two, twice the LDS): an
-// autotuner choice.
+// The same plan exchanging whole complex values through LDS (one barrier pair
+// per level instead of two, twice the LDS) where the default splits real and
+// imaginary parts: an autotuner choice.
 template <class P>
 struct ComplexExchange : P {
     static constexpr bool kComplexX = true;

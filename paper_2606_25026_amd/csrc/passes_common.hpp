@@ -56,8 +56,9 @@ struct PlanFor<N, 2> {
     using type = WideRows<typename PlanFor<N, 0>::type>;
 };
 
-// V = 3 (strided passes only): the default radices with the complex LDS
-// exchange, for lengths up to 256.
+// V = 3: the default radices with the complex LDS exchange -- the strided
+// passes at lengths up to 256 (has_wide), the z passes at the lengths whose
+// default splits the exchange (has_zcx).
 template <int N>
 struct PlanFor<N, 3> {
     using type = ComplexExchange<typename PlanFor<N, 0>::type>;
